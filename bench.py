@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark: catalogs/s of the momentum power spectrum estimator on one MI355X.
+
+Workload: a 512^3-particle Zel'dovich catalog (lattice displaced by a Gaussian
+field with P(k) = A k^-1.5 exp(-k/0.5), rms displacement 8 Mpc/h, v = 50 Psi)
+in a 1000 Mpc/h box, estimated on a 512^3 grid: moments, tile sort, BL3
+assignment, three FFT passes, fused deconvolution/shot-noise/binning of
+P_pp, P_theta-theta, P_delta-theta and P_dd into 32 linear bins, finalize.
+One step = one full estimate with the catalog already resident in HBM.
+
+`value` is the FP32-grid path's catalogs/s; the plain FP64-grid path is timed
+beside it (`fp64`).  Per-stage device times come from HIP events recorded on
+the stream the stages run on.  The CPU oracle is timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_GRID = 512
+N_LAT = 512
+BOX = 1000.0
+HAF = 50.0
+RMS = 8.0
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n_grid, n_part, real):
+    """HBM bytes each stage must move at minimum."""
+    n3 = n_grid ** 3
+    grid = 4 * n3 * real                     # four real (or N/2-complex) grids
+    rec = 32                                 # sorted record (x, y, z, w, vx, vy, vz, pad)
+    inp = 24                                 # float32 pos + vel
+    half = n_grid // 2
+    # x pass reads only (ky, kz-block) items that intersect |n| < N/2
+    return {
+        "moments+count": n_part * inp,
+        "permute": n_part * (inp + rec),
+        "clear": grid,
+        "scatter": n_part * rec + grid,      # records in, grids out once
+        "fft_z": 2 * grid,
+        "fft_y": 2 * grid,
+        "fft_x+bin": grid * math.pi / 4,     # pencils inside the k_N disc
+    }
+
+
+def time_path(mps, torch, pos, vel, prec, steps, warmup):
+    plan = mps.Plan(N_GRID, prec)
+    plan.reserve(pos.shape[0])
+    kw = dict(box=BOX, haf=HAF, n_bins=32)
+    for _ in range(warmup):
+        plan.estimate(pos, vel, **kw)
+    plan.set_timing(True)
+    stages = []
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        out = plan.estimate(pos, vel, **kw)
+        lat.append(time.perf_counter() - t1)
+        stages.append(plan.stage_times())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.set_timing(False)
+    plan.close()
+    avg = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+    return wall, np.array(lat), avg, out
+
+
+def cpu_baseline():
+    """Oracle on 1/64 of the workload: a 128^3-particle Zel'dovich catalog of the
+    same construction on a 128^3 grid (64x fewer particles and cells)."""
+    import oracle
+    from synth import catalogs
+    pos, vel = catalogs.zeldovich(128, BOX, RMS, haf=HAF, seed=catalogs.seed_for(3, 1))
+    t0 = time.perf_counter()
+    oracle.estimate(pos, vel, box=BOX, n_grid=128, haf=HAF, n_bins=32)
+    t = time.perf_counter() - t0
+    return {"value": 1.0 / (64.0 * t), "unit": "catalogs/s", "cores": os.cpu_count(),
+            "kind": "oracle",
+            "sample": (f"oracle.estimate on a 128^3-particle Zel'dovich catalog, 128^3 grid "
+                       f"(1/64 of the particles and cells): {t:.1f} s, scaled x64; numpy "
+                       f"bincount assignment is single-threaded, scipy FFTs use all cores")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--shuffle", action="store_true",
+                    help="permute particle order randomly (no spatial coherence)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the estimator's catalogs are independent and "
+              "multi-GPU runs are not part of this build (see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2005_06170_amd as mps
+    from synth import catalogs
+
+    _log("generating the 512^3 Zel'dovich catalog")
+    t0 = time.perf_counter()
+    pos_np, vel_np = catalogs.zeldovich(N_LAT, BOX, RMS, haf=HAF, seed=catalogs.seed_for(3))
+    if args.shuffle:
+        perm = np.random.default_rng(1).permutation(pos_np.shape[0])
+        pos_np, vel_np = pos_np[perm], vel_np[perm]
+    _log(f"catalog ready in {time.perf_counter() - t0:.1f} s; uploading")
+    pos = torch.from_numpy(pos_np).cuda()
+    vel = torch.from_numpy(vel_np).cuda()
+    del pos_np, vel_np
+    n_part = pos.shape[0]
+
+    _log("timing the FP32 path")
+    wall, lat, stages, _ = time_path(mps, torch, pos, vel, "f32", args.steps, args.warmup)
+    ms_step = 1e3 * wall / args.steps
+    _log(f"f32: {ms_step:.2f} ms/step; stages {stages}")
+
+    fp64 = None
+    if not args.no_fp64:
+        _log("timing the FP64 path")
+        steps64 = max(3, args.steps // 4)
+        wall64, lat64, stages64, _ = time_path(mps, torch, pos, vel, "f64", steps64, 1)
+        fp64 = {"catalogs_per_s": steps64 / wall64, "ms_per_step": 1e3 * wall64 / steps64,
+                "stage_ms": stages64}
+        _log(f"f64: {1e3 * wall64 / steps64:.2f} ms/step")
+
+    abytes = algorithmic_bytes(N_GRID, n_part, 4)
+    per_stage = {}
+    for k, ms in stages.items():
+        entry = {"ms": ms}
+        if k in abytes and ms > 0:
+            gbs = abytes[k] / (ms * 1e-3) / 1e9
+            entry.update({"algorithmic_GB": abytes[k] / 1e9, "GB_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS})
+        per_stage[k] = entry
+    dom = max((k for k in stages if k in abytes), key=lambda k: stages[k])
+    dom_gbs = abytes[dom] / (stages[dom] * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS, "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        _log("timing the CPU oracle sample")
+        cpu = cpu_baseline()
+
+    line = {
+        "metric": "catalogs/sec (P_pp,P_thth,P_dth) at 512^3 grid, 134M particles; p50/p99 latency",
+        "value": args.steps / wall,
+        "unit": "catalogs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "zeldovich_512^3_particles_512^3_grid", "n_grid": N_GRID,
+                   "n_particles": n_part, "box_mpc_h": BOX, "rms_disp_mpc_h": RMS, "haf": HAF,
+                   "n_bins": 32, "particle_order": "shuffled" if args.shuffle else "lattice"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3)},
+        "fp64": fp64,
+        "stages": per_stage,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * mps.h -- momentum power spectra of a periodic particle catalog on one
+ * AMD Instinct MI355X (gfx950), C ABI.
+ *
+ * The library implements the FFT estimator of J. Pan, "Estimating power
+ * spectrum of discrete cosmic momentum field with fast Fourier transform":
+ *
+ *   - the momentum field p = (1 + delta) v (Eq. 1) and its Fourier estimator
+ *     p_hat(k) = (1/N) sum_j v_j e^{i k.r_j} (Eq. 4), generalised to weights
+ *     w_j (N -> W = sum w, shot terms use sum w^2);
+ *   - assignment of rho, rho v_x, rho v_y, rho v_z to a periodic N^3 grid
+ *     with the third-order (cubic) orthogonalised Battle-Lemarie scaling
+ *     function (Sec. 2.4.1), truncated to six taps per axis (d in (-3, 3]);
+ *   - 3D real-to-complex FFTs of the four fields;
+ *   - deconvolution by the window W_t(k)^2 of the truncated kernel and
+ *     subtraction of the shot noise scaled by its alias sum
+ *     sum_J W_t^2(k + 2 k_N J) (Eqs. rawPp, rawPtheta, rawPx);
+ *   - the divergence theta_p = i k.p / (Haf) (Sec. 2.2), with the
+ *     directional shot noise k^T S k / Haf^2 (Eq. thetanoise);
+ *   - optional bulk-flow removal v' = v - v_b, v_b = sum w v / W (Sec. 3.1);
+ *   - averages in |k| shells of P_pp = <|p|^2> (Eq. 3), P_theta-theta,
+ *     Re P_delta-theta (its shot noise is purely imaginary, Eq. rawPx) and the
+ *     density spectrum P_dd.
+ *
+ * Conventions (where the paper is silent):
+ *   - grid node g sits at g L / N; a particle's grid coordinate is
+ *     u = (double)x * ((double)N / L), its cell floor(u) mod N, and it
+ *     deposits phi(j - f) on nodes cell + j, j = -2..3, f = u - floor(u);
+ *   - spectra are multiplied by V = L^3 (units (Mpc/h)^3 (km/s)^2 for P_pp,
+ *     (Mpc/h)^3 otherwise when L is in Mpc/h and velocities in km/s);
+ *   - bins are half-open shells [k_b, k_{b+1}); the DC mode and every mode
+ *     with |k| >= k_N = pi N / L are excluded.  Without explicit edges the
+ *     bins are n_bins linear bins on [0, k_N) and a mode with integer vector
+ *     n joins bin b iff (b N/2)^2 <= n_bins^2 |n|^2 < ((b+1) N/2)^2, decided
+ *     in exact integer arithmetic.  With edges, bin b holds modes with
+ *     t_b <= |n|^2 < t_{b+1}, t_b = (k_b / k_f)^2, k_f = 2 pi / L, in FP64;
+ *   - empty bins report n_modes = 0 and NaN values.
+ *
+ * All functions return an int status: MPS_OK (0) or a negative MPS_E_* code.
+ * No exception crosses the ABI.  Device pointers are HIP device (or managed)
+ * pointers on the plan's device; host pointers are ordinary host memory.
+ */
+#ifndef MPS_H_
+#define MPS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPS_OK 0
+#define MPS_E_ARG (-1)        /* invalid argument (null pointer, size, bins) */
+#define MPS_E_NONFINITE (-2)  /* a position, velocity or weight is NaN/Inf */
+#define MPS_E_ZEROWEIGHT (-3) /* sum of weights is zero */
+#define MPS_E_NOMEM (-4)      /* device or pinned allocation failed */
+#define MPS_E_HIP (-5)        /* a HIP runtime call failed */
+#define MPS_E_TIMEOUT (-6)    /* mps_wait timed out */
+#define MPS_E_BUSY (-7)       /* the server queue is full */
+#define MPS_E_TOOBIG (-8)     /* request can never fit the server's budget */
+
+#define MPS_MAX_BINS 128
+
+typedef enum { MPS_F32 = 1, MPS_F64 = 2 } mps_precision;
+
+enum {
+  MPS_BULKFLOW_SUBTRACT = 1u << 0, /* use v - v_b (Sec. 3.1) */
+  MPS_NO_SHOTNOISE = 1u << 1,      /* report raw (deconvolved) spectra */
+  MPS_NO_DECONVOLVE = 1u << 2      /* do not divide by W_t(k)^2 */
+};
+
+/* One catalog.  The caller owns every buffer; they must stay valid until the
+ * call that uses them returns (or, for mps_submit, until mps_wait reports the
+ * ticket done).  The library never frees or retains them. */
+typedef struct {
+  int64_t n_particles;   /* 1 .. 2^31 - 1 */
+  const float* pos;      /* device, n x 3 interleaved (x, y, z); any finite
+                            value, wrapped periodically into [0, L) */
+  const float* vel;      /* device, n x 3 interleaved */
+  const float* weight;   /* device, n; NULL means unit weights */
+  double box;            /* L > 0 */
+  double haf;            /* H a f > 0, velocity units per length unit */
+  int n_bins;            /* 1 .. MPS_MAX_BINS */
+  const double* k_edges; /* host, n_bins + 1 strictly ascending values in
+                            [0, k_N], or NULL for linear bins on [0, k_N) */
+  uint32_t flags;        /* MPS_BULKFLOW_SUBTRACT | MPS_NO_SHOTNOISE | ... */
+} mps_catalog;
+
+/* Results.  Array members are caller-allocated host arrays of length n_bins;
+ * any of them may be NULL to skip that output.  The scalar members are
+ * written by the library. */
+typedef struct {
+  double* k_mean;   /* mode-averaged |k| per bin */
+  double* p_pp;     /* momentum auto spectrum, shot noise subtracted */
+  double* p_tt;     /* momentum-divergence auto spectrum */
+  double* p_dt;     /* Re of the density x divergence cross spectrum */
+  double* p_dd;     /* density spectrum */
+  double* sn_pp;    /* bin-averaged shot terms that were (or would be) */
+  double* sn_tt;    /*   subtracted, after deconvolution */
+  double* sn_dd;
+  int64_t* n_modes; /* modes in the bin (full sphere, both k and -k) */
+  double v_bulk[3]; /* v_b = sum w v / W */
+  double sigma_v2;  /* sum w^2 |v|^2 / sum w^2 of the velocities used */
+  double n_eff;     /* W^2 / sum w^2 (= N for unit weights) */
+} mps_result;
+
+typedef struct mps_plan mps_plan;
+typedef struct mps_server mps_server;
+
+/* Create a plan for N^3 grids (N a power of two in [8, 1024]) on the current
+ * HIP device.  The plan owns the four grids, FFT twiddles, the BL3 tables
+ * and the bin tables; particle workspace grows on demand (or see
+ * mps_plan_reserve).  A plan is not thread-safe. */
+int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec);
+int mps_plan_destroy(mps_plan* plan);
+
+/* Pre-allocate workspace for catalogs of up to max_particles particles so
+ * that later calls allocate nothing. */
+int mps_plan_reserve(mps_plan* plan, int64_t max_particles);
+
+/* Device bytes a plan of this shape holds when used for n_particles. */
+size_t mps_footprint(int n_grid, mps_precision prec, int64_t n_particles);
+
+/* Estimate the binned spectra of one catalog.  All work is enqueued on
+ * `stream`; the call returns after the few-KB result copy has completed. */
+int mps_estimate(mps_plan* plan, const mps_catalog* cat, mps_result* out,
+                 hipStream_t stream);
+
+/* Estimate n catalogs, each with its own plan (plans may differ in N and
+ * precision; a plan may not appear twice).  Stages of all catalogs are
+ * launched together so that small catalogs share the device. */
+int mps_estimate_batch(mps_plan* const* plans, const mps_catalog* cats,
+                       mps_result* outs, int n, hipStream_t stream);
+
+/* Diagnostics of the hot path's first stages, using the same kernels as
+ * mps_estimate.  mps_assign writes the four assigned real grids
+ * (rho, rho v_x, rho v_y, rho v_z; layout [field][x][y][z], z fastest, the
+ * plan's precision) to `grids`, a device buffer of 4 N^3 reals.  With
+ * MPS_BULKFLOW_SUBTRACT the momentum grids are those of v - v_b.
+ * mps_fft transforms such grids in place: on return `grids` holds, per field,
+ * the complex array F[x][y][kz] for kz in [0, N/2) (e^{-2 pi i n.g / N}; the
+ * kz = N/2 plane, never binned, is dropped), interleaved (re, im). */
+int mps_assign(mps_plan* plan, const mps_catalog* cat, void* grids,
+               hipStream_t stream);
+int mps_fft(mps_plan* plan, void* grids, hipStream_t stream);
+
+/* Per-stage device time of the last mps_estimate on this plan when stage
+ * timing is on (mps_plan_set_timing).  ms[0..n) receives, in order:
+ * moments+count, scan, permute, clear, scatter, fft_z, fft_y, fft_x+bin,
+ * finalize. */
+int mps_plan_set_timing(mps_plan* plan, int enable);
+int mps_plan_stage_times(const mps_plan* plan, double* ms, int n);
+
+/* Serving: continuous batching of catalogs of uneven sizes.
+ * hbm_budget_bytes bounds the device memory the server's plans and
+ * workspaces may hold; max_inflight bounds requests on the device at once;
+ * small_particles is the particle count below which requests of one grid
+ * size are batched together.  mps_submit copies the catalog descriptor (not
+ * the buffers) and returns a ticket; mps_wait blocks until the ticket is done
+ * (then its mps_result is filled and its status returned) or timeout_s
+ * elapses (MPS_E_TIMEOUT).  The server is thread-safe. */
+int mps_server_create(mps_server** out, size_t hbm_budget_bytes,
+                      int max_inflight, int64_t small_particles);
+int mps_submit(mps_server* srv, const mps_catalog* cat, int n_grid,
+               mps_precision prec, mps_result* out, uint64_t* ticket);
+int mps_wait(mps_server* srv, uint64_t ticket, double timeout_s);
+int mps_server_destroy(mps_server* srv);
+
+const char* mps_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPS_H_ */

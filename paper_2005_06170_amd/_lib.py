@@ -1,0 +1,108 @@
+"""ctypes view of libmps.so (include/mps.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmps.so")
+
+MPS_OK = 0
+ERRORS = {-1: "MPS_E_ARG", -2: "MPS_E_NONFINITE", -3: "MPS_E_ZEROWEIGHT",
+          -4: "MPS_E_NOMEM", -5: "MPS_E_HIP", -6: "MPS_E_TIMEOUT",
+          -7: "MPS_E_BUSY", -8: "MPS_E_TOOBIG"}
+MPS_F32, MPS_F64 = 1, 2
+BULKFLOW_SUBTRACT, NO_SHOTNOISE, NO_DECONVOLVE = 1, 2, 4
+MAX_BINS = 128
+NUM_STAGES = 9
+STAGES = ("moments+count", "scan", "permute", "clear", "scatter",
+          "fft_z", "fft_y", "fft_x+bin", "finalize")
+
+
+class Catalog(C.Structure):
+    _fields_ = [("n_particles", C.c_int64), ("pos", C.c_void_p), ("vel", C.c_void_p),
+                ("weight", C.c_void_p), ("box", C.c_double), ("haf", C.c_double),
+                ("n_bins", C.c_int), ("k_edges", C.POINTER(C.c_double)),
+                ("flags", C.c_uint32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("k_mean", C.POINTER(C.c_double)), ("p_pp", C.POINTER(C.c_double)),
+                ("p_tt", C.POINTER(C.c_double)), ("p_dt", C.POINTER(C.c_double)),
+                ("p_dd", C.POINTER(C.c_double)), ("sn_pp", C.POINTER(C.c_double)),
+                ("sn_tt", C.POINTER(C.c_double)), ("sn_dd", C.POINTER(C.c_double)),
+                ("n_modes", C.POINTER(C.c_int64)), ("v_bulk", C.c_double * 3),
+                ("sigma_v2", C.c_double), ("n_eff", C.c_double)]
+
+
+class MpsError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        name = ERRORS.get(status, str(status))
+        super().__init__(f"{what}: {name} ({_strerror(status)})" if what else name)
+
+
+_lib = None
+
+
+def lib():
+    """Load libmps.so; raise if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2005_06170_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    sig = {
+        "mps_plan_create": (i32, [C.POINTER(vp), i32, i32]),
+        "mps_plan_destroy": (i32, [vp]),
+        "mps_plan_reserve": (i32, [vp, i64]),
+        "mps_footprint": (C.c_size_t, [i32, i32, i64]),
+        "mps_estimate": (i32, [vp, C.POINTER(Catalog), C.POINTER(Result), vp]),
+        "mps_estimate_batch": (i32, [C.POINTER(vp), C.POINTER(Catalog), C.POINTER(Result), i32, vp]),
+        "mps_assign": (i32, [vp, C.POINTER(Catalog), vp, vp]),
+        "mps_fft": (i32, [vp, vp, vp]),
+        "mps_plan_set_timing": (i32, [vp, i32]),
+        "mps_plan_stage_times": (i32, [vp, C.POINTER(dbl), i32]),
+        "mps_strerror": (C.c_char_p, [i32]),
+    }
+    optional = {
+        "mps_server_create": (i32, [C.POINTER(vp), C.c_size_t, i32, i64]),
+        "mps_submit": (i32, [vp, C.POINTER(Catalog), i32, i32, C.POINTER(Result), C.POINTER(C.c_uint64)]),
+        "mps_wait": (i32, [vp, C.c_uint64, dbl]),
+        "mps_server_destroy": (i32, [vp]),
+    }
+    for name, (res, args) in {**sig, **optional}.items():
+        if not hasattr(L, name):
+            if name in sig:
+                raise ImportError(f"{LIB_PATH} does not export {name}")
+            continue
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _strerror(status: int) -> str:
+    try:
+        return lib().mps_strerror(status).decode()
+    except Exception:  # pragma: no cover - only while reporting another error
+        return "?"
+
+
+def check(status: int, what: str = "") -> None:
+    if status != MPS_OK:
+        raise MpsError(status, what)
+
+
+def exported_symbols():
+    """Names declared in include/mps.h that the loaded library exports."""
+    L = lib()
+    names = ["mps_plan_create", "mps_plan_destroy", "mps_plan_reserve", "mps_footprint",
+             "mps_estimate", "mps_estimate_batch", "mps_assign", "mps_fft",
+             "mps_plan_set_timing", "mps_plan_stage_times", "mps_server_create",
+             "mps_submit", "mps_wait", "mps_server_destroy", "mps_strerror"]
+    return {n: hasattr(L, n) for n in names}

@@ -1,0 +1,388 @@
+// C ABI of the estimator: plan management, argument validation, stage
+// scheduling on the caller's stream and result unpacking.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+namespace mps {
+
+hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int bulk);
+
+namespace {
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+template <typename T>
+hipError_t dalloc(T** ptr, size_t bytes) {
+  *ptr = nullptr;
+  return hipMalloc(reinterpret_cast<void**>(ptr), bytes < 1 ? 1 : bytes);
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+size_t real_bytes(mps_precision prec) { return prec == MPS_F64 ? 8 : 4; }
+
+int tile_for(int n, mps_precision prec) { return (prec == MPS_F32 && n >= 16) ? 16 : 8; }
+
+int num_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 256;
+  return cus;
+}
+
+int x_bin_items(int n, mps_precision prec) {
+  int b = (prec == MPS_F32 ? 8 : 4) * 512 / (n > 512 ? n : 512);
+  if (b > n / 2) b = n / 2;
+  return n * ((n / 2) / b);
+}
+
+void release(Plan* p) {
+  if (!p) return;
+  dfree(p->grid);
+  dfree(p->sorted);
+  dfree(p->tile_count);
+  dfree(p->tile_offset);
+  dfree(p->tile_cursor);
+  dfree(p->moment_partials);
+  dfree(p->d_header);
+  dfree(p->d_win2);
+  dfree(p->d_alias);
+  dfree(p->d_twiddle);
+  dfree(p->d_lut);
+  dfree(p->d_bin_partials);
+  dfree(p->d_bins);
+  if (p->h_stage) (void)hipHostFree(p->h_stage);
+  for (auto& e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete p;
+}
+
+}  // namespace
+
+int validate_catalog(const Plan* p, const mps_catalog* c) {
+  if (!c || !c->pos || !c->vel) return MPS_E_ARG;
+  if (c->n_particles < 1 || c->n_particles > 0x7fffffffll) return MPS_E_ARG;
+  if (!(c->box > 0.0) || !std::isfinite(c->box)) return MPS_E_ARG;
+  if (!(c->haf > 0.0) || !std::isfinite(c->haf)) return MPS_E_ARG;
+  if (c->n_bins < 1 || c->n_bins > kMaxBins) return MPS_E_ARG;
+  if (c->flags & ~7u) return MPS_E_ARG;
+  (void)p;
+  return MPS_OK;
+}
+
+int ensure_bins(Plan* p, const mps_catalog* c) {
+  std::vector<double> key;
+  if (c->k_edges) key.assign(c->k_edges, c->k_edges + c->n_bins + 1);
+  if (p->lut_box == c->box && p->lut_nbins == c->n_bins && p->lut_edges == key) return MPS_OK;
+  std::vector<int32_t> lut;
+  std::vector<double> edges;
+  if (!bin_lut(p->n, c->box, c->n_bins, c->k_edges, &lut, &edges)) return MPS_E_ARG;
+  if (hipMemcpy(p->d_lut, lut.data(), lut.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+    return MPS_E_HIP;
+  p->lut_box = c->box;
+  p->lut_nbins = c->n_bins;
+  p->lut_edges = key;
+  p->edges_used = edges;
+  return MPS_OK;
+}
+
+int ensure_particles(Plan* p, int64_t np) {
+  if (np <= p->sorted_cap) return MPS_OK;
+  dfree(p->sorted);
+  p->sorted = nullptr;
+  p->sorted_cap = 0;
+  if (dalloc(&p->sorted, static_cast<size_t>(np) * 2 * sizeof(float4)) != hipSuccess) return MPS_E_NOMEM;
+  p->sorted_cap = np;
+  return MPS_OK;
+}
+
+#define MPS_TRY(expr)                               \
+  do {                                              \
+    if ((expr) != hipSuccess) return MPS_E_HIP;     \
+  } while (0)
+
+void mark(Plan* p, int i, hipStream_t s) {
+  if (p->timing) (void)hipEventRecord(p->ev[i], s);
+}
+
+// Stages up to (and including) the scatter; `bulk_grid` deposits v - v_b.
+int enqueue_particles(Plan* p, const mps_catalog* c, hipStream_t s, int bulk_grid) {
+  mark(p, 0, s);
+  MPS_TRY(launch_count(p, c, s));
+  MPS_TRY(launch_derive(p, c, s));
+  mark(p, 1, s);
+  MPS_TRY(launch_scan(p, s));
+  mark(p, 2, s);
+  MPS_TRY(launch_permute(p, c, s));
+  mark(p, 3, s);
+  MPS_TRY(launch_clear_grid(p, s));
+  mark(p, 4, s);
+  MPS_TRY(launch_scatter_impl(p, c, s, bulk_grid));
+  mark(p, 5, s);
+  return MPS_OK;
+}
+
+int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s) {
+  int st = enqueue_particles(p, c, s, 0);
+  if (st != MPS_OK) return st;
+  MPS_TRY(launch_fft_z(p, p->grid, s));
+  mark(p, 6, s);
+  MPS_TRY(launch_fft_y(p, p->grid, s));
+  mark(p, 7, s);
+  MPS_TRY(launch_fft_x_bin(p, c, s));
+  mark(p, 8, s);
+  MPS_TRY(launch_finalize(p, c, s));
+  mark(p, 9, s);
+  const size_t bytes = sizeof(ResultHeader) + sizeof(double) * kNumQ * c->n_bins;
+  MPS_TRY(hipMemcpyAsync(p->h_stage, p->d_header, sizeof(ResultHeader), hipMemcpyDeviceToHost, s));
+  MPS_TRY(hipMemcpyAsync(static_cast<char*>(p->h_stage) + sizeof(ResultHeader), p->d_bins,
+                         bytes - sizeof(ResultHeader), hipMemcpyDeviceToHost, s));
+  return MPS_OK;
+}
+
+namespace {
+
+int check_header(const ResultHeader* h) {
+  if (h->flags & 1u) return MPS_E_NONFINITE;
+  for (int q = 0; q < kMomentSums; ++q)
+    if (!std::isfinite(h->sums[q])) return MPS_E_NONFINITE;
+  if (h->sums[0] == 0.0) return MPS_E_ZEROWEIGHT;
+  return MPS_OK;
+}
+
+}  // namespace
+
+int unpack(Plan* p, const mps_catalog* c, mps_result* out) {
+  const ResultHeader* h = static_cast<const ResultHeader*>(p->h_stage);
+  const int st = check_header(h);
+  if (st != MPS_OK) return st;
+  const double* bins = reinterpret_cast<const double*>(static_cast<const char*>(p->h_stage) + sizeof(ResultHeader));
+  for (int b = 0; b < c->n_bins; ++b) {
+    const double* s = bins + b * kNumQ;
+    if (out->n_modes) out->n_modes[b] = static_cast<int64_t>(std::llround(s[QCount]));
+    if (out->k_mean) out->k_mean[b] = s[QKsum];
+    if (out->p_dd) out->p_dd[b] = s[QPdd];
+    if (out->p_pp) out->p_pp[b] = s[QPpp];
+    if (out->p_tt) out->p_tt[b] = s[QPtt];
+    if (out->p_dt) out->p_dt[b] = s[QPdt];
+    if (out->sn_dd) out->sn_dd[b] = s[QSdd];
+    if (out->sn_pp) out->sn_pp[b] = s[QSpp];
+    if (out->sn_tt) out->sn_tt[b] = s[QStt];
+  }
+  for (int a = 0; a < 3; ++a) out->v_bulk[a] = h->d.vb[a];
+  out->sigma_v2 = h->d.sigma_v2;
+  out->n_eff = h->d.W * h->d.W / h->d.W2;
+  if (p->timing)
+    for (int i = 0; i < kNumStages; ++i) {
+      float ms = 0.f;
+      p->stage_ms[i] = hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]) == hipSuccess ? ms : -1.0;
+    }
+  return MPS_OK;
+}
+
+}  // namespace mps
+
+using namespace mps;
+
+extern "C" {
+
+int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec) {
+  if (!out) return MPS_E_ARG;
+  *out = nullptr;
+  if (!is_pow2(n_grid) || n_grid < 8 || n_grid > 1024) return MPS_E_ARG;
+  if (prec != MPS_F32 && prec != MPS_F64) return MPS_E_ARG;
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return MPS_E_NOMEM;
+  p->n = n_grid;
+  p->prec = prec;
+  p->real_size = real_bytes(prec);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return MPS_E_HIP;
+  }
+  p->tile = tile_for(n_grid, prec);
+  const int64_t nt = n_grid / p->tile;
+  p->n_tiles = nt * nt * nt;
+  const int64_t n3 = static_cast<int64_t>(n_grid) * n_grid * n_grid;
+  const int half = n_grid / 2;
+  const int items = x_bin_items(n_grid, prec);
+  const int cus = num_cus();
+  p->bin_blocks = items < cus ? items : cus;
+  bool ok = true;
+  ok = ok && dalloc(&p->grid, static_cast<size_t>(kNumFields) * n3 * p->real_size) == hipSuccess;
+  ok = ok && dalloc(&p->tile_count, sizeof(uint32_t) * p->n_tiles) == hipSuccess;
+  ok = ok && dalloc(&p->tile_offset, sizeof(uint32_t) * (p->n_tiles + 1)) == hipSuccess;
+  ok = ok && dalloc(&p->tile_cursor, sizeof(uint32_t) * p->n_tiles) == hipSuccess;
+  ok = ok && dalloc(&p->moment_partials, sizeof(double) * kMomentBlocks * kMomentSums) == hipSuccess;
+  ok = ok && dalloc(&p->d_header, sizeof(ResultHeader)) == hipSuccess;
+  ok = ok && dalloc(&p->d_win2, sizeof(double) * (half + 1)) == hipSuccess;
+  ok = ok && dalloc(&p->d_alias, sizeof(double) * (half + 1)) == hipSuccess;
+  ok = ok && dalloc(&p->d_twiddle, 2 * p->real_size * n_grid) == hipSuccess;
+  ok = ok && dalloc(&p->d_lut, sizeof(int32_t) * half * half) == hipSuccess;
+  ok = ok && dalloc(&p->d_bin_partials, sizeof(double) * p->bin_blocks * kMaxBins * kNumQ) == hipSuccess;
+  ok = ok && dalloc(&p->d_bins, sizeof(double) * kMaxBins * kNumQ) == hipSuccess;
+  p->stage_bytes = sizeof(ResultHeader) + sizeof(double) * kMaxBins * kNumQ;
+  ok = ok && hipHostMalloc(&p->h_stage, p->stage_bytes, hipHostMallocDefault) == hipSuccess;
+  for (auto& e : p->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+  if (!ok) {
+    release(p);
+    return MPS_E_NOMEM;
+  }
+  p->taps = bl3_tap_polynomials();
+  std::vector<double> win2, alias;
+  bl3_axis_tables(n_grid, &win2, &alias);
+  const std::vector<double> tw = twiddles(n_grid);
+  bool up = hipMemcpy(p->d_win2, win2.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) == hipSuccess;
+  up = up && hipMemcpy(p->d_alias, alias.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) == hipSuccess;
+  if (prec == MPS_F32) {
+    std::vector<float> twf(tw.begin(), tw.end());
+    up = up && hipMemcpy(p->d_twiddle, twf.data(), sizeof(float) * twf.size(), hipMemcpyHostToDevice) == hipSuccess;
+  } else {
+    up = up && hipMemcpy(p->d_twiddle, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (!up) {
+    release(p);
+    return MPS_E_HIP;
+  }
+  *out = reinterpret_cast<mps_plan*>(p);
+  return MPS_OK;
+}
+
+int mps_plan_destroy(mps_plan* plan) {
+  if (!plan) return MPS_E_ARG;
+  release(reinterpret_cast<Plan*>(plan));
+  return MPS_OK;
+}
+
+int mps_plan_reserve(mps_plan* plan, int64_t max_particles) {
+  if (!plan || max_particles < 1 || max_particles > 0x7fffffffll) return MPS_E_ARG;
+  return ensure_particles(reinterpret_cast<Plan*>(plan), max_particles);
+}
+
+size_t mps_footprint(int n_grid, mps_precision prec, int64_t n_particles) {
+  if (!is_pow2(n_grid) || n_grid < 8 || n_grid > 1024) return 0;
+  const size_t rs = real_bytes(prec);
+  const int64_t n3 = static_cast<int64_t>(n_grid) * n_grid * n_grid;
+  const int64_t nt = n_grid / tile_for(n_grid, prec);
+  const int64_t tiles = nt * nt * nt;
+  const int half = n_grid / 2;
+  size_t b = static_cast<size_t>(kNumFields) * n3 * rs;              // grids
+  b += static_cast<size_t>(n_particles) * 2 * sizeof(float4);        // sorted records
+  b += sizeof(uint32_t) * (3 * tiles + 1);                           // tile tables
+  b += sizeof(int32_t) * half * half;                                // bin LUT
+  b += sizeof(double) * (static_cast<size_t>(256) + 1) * kMaxBins * kNumQ;
+  b += sizeof(double) * (kMomentBlocks * kMomentSums + 2 * (half + 1)) + 2 * rs * n_grid + sizeof(ResultHeader);
+  return b;
+}
+
+int mps_estimate(mps_plan* plan, const mps_catalog* cat, mps_result* out, hipStream_t stream) {
+  if (!plan || !out) return MPS_E_ARG;
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  int st = validate_catalog(p, cat);
+  if (st != MPS_OK) return st;
+  if (hipSetDevice(p->device) != hipSuccess) return MPS_E_HIP;
+  if ((st = ensure_bins(p, cat)) != MPS_OK) return st;
+  if ((st = ensure_particles(p, cat->n_particles)) != MPS_OK) return st;
+  if ((st = enqueue_estimate(p, cat, stream)) != MPS_OK) return st;
+  if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
+  return unpack(p, cat, out);
+}
+
+int mps_estimate_batch(mps_plan* const* plans, const mps_catalog* cats, mps_result* outs, int n,
+                       hipStream_t stream) {
+  if (!plans || !cats || !outs || n < 0) return MPS_E_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return MPS_E_ARG;
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return MPS_E_ARG;
+    const int st = validate_catalog(reinterpret_cast<Plan*>(plans[i]), &cats[i]);
+    if (st != MPS_OK) return st;
+  }
+  for (int i = 0; i < n; ++i) {
+    Plan* p = reinterpret_cast<Plan*>(plans[i]);
+    int st;
+    if ((st = ensure_bins(p, &cats[i])) != MPS_OK) return st;
+    if ((st = ensure_particles(p, cats[i].n_particles)) != MPS_OK) return st;
+  }
+  for (int i = 0; i < n; ++i) {
+    const int st = enqueue_estimate(reinterpret_cast<Plan*>(plans[i]), &cats[i], stream);
+    if (st != MPS_OK) return st;
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
+  int first = MPS_OK;
+  for (int i = 0; i < n; ++i) {
+    const int st = unpack(reinterpret_cast<Plan*>(plans[i]), &cats[i], &outs[i]);
+    if (st != MPS_OK && first == MPS_OK) first = st;
+  }
+  return first;
+}
+
+int mps_assign(mps_plan* plan, const mps_catalog* cat, void* grids, hipStream_t stream) {
+  if (!plan || !grids) return MPS_E_ARG;
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  int st = validate_catalog(p, cat);
+  if (st != MPS_OK) return st;
+  if (hipSetDevice(p->device) != hipSuccess) return MPS_E_HIP;
+  if ((st = ensure_particles(p, cat->n_particles)) != MPS_OK) return st;
+  const bool was = p->timing;
+  p->timing = false;
+  st = enqueue_particles(p, cat, stream, (cat->flags & MPS_BULKFLOW_SUBTRACT) ? 1 : 0);
+  p->timing = was;
+  if (st != MPS_OK) return st;
+  const size_t bytes = static_cast<size_t>(kNumFields) * p->n * p->n * p->n * p->real_size;
+  if (hipMemcpyAsync(grids, p->grid, bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess) return MPS_E_HIP;
+  if (hipMemcpyAsync(p->h_stage, p->d_header, sizeof(ResultHeader), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return MPS_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
+  return check_header(static_cast<const ResultHeader*>(p->h_stage));
+}
+
+int mps_fft(mps_plan* plan, void* grids, hipStream_t stream) {
+  if (!plan || !grids) return MPS_E_ARG;
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (hipSetDevice(p->device) != hipSuccess) return MPS_E_HIP;
+  if (launch_fft_z(p, grids, stream) != hipSuccess) return MPS_E_HIP;
+  if (launch_fft_y(p, grids, stream) != hipSuccess) return MPS_E_HIP;
+  if (launch_fft_x_store(p, grids, stream) != hipSuccess) return MPS_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
+  return MPS_OK;
+}
+
+int mps_plan_set_timing(mps_plan* plan, int enable) {
+  if (!plan) return MPS_E_ARG;
+  reinterpret_cast<Plan*>(plan)->timing = enable != 0;
+  return MPS_OK;
+}
+
+int mps_plan_stage_times(const mps_plan* plan, double* ms, int n) {
+  if (!plan || !ms || n < 0) return MPS_E_ARG;
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  for (int i = 0; i < n && i < kNumStages; ++i) ms[i] = p->stage_ms[i];
+  return MPS_OK;
+}
+
+const char* mps_strerror(int status) {
+  switch (status) {
+    case MPS_OK: return "ok";
+    case MPS_E_ARG: return "invalid argument";
+    case MPS_E_NONFINITE: return "non-finite position, velocity or weight";
+    case MPS_E_ZEROWEIGHT: return "sum of weights is zero";
+    case MPS_E_NOMEM: return "out of device or pinned memory";
+    case MPS_E_HIP: return "HIP runtime error";
+    case MPS_E_TIMEOUT: return "timed out";
+    case MPS_E_BUSY: return "server queue full";
+    case MPS_E_TOOBIG: return "request exceeds the server's memory budget";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Internal declarations of the MI355X momentum-power-spectrum library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "mps.h"
+
+namespace mps {
+
+constexpr int kNumFields = 4;     // rho, rho v_x, rho v_y, rho v_z
+constexpr int kTaps = 6;          // BL3 taps j = -2..3
+constexpr int kTapLo = -2;
+constexpr int kNumQ = 9;          // per-bin accumulators (see BinQ)
+constexpr int kMaxBins = MPS_MAX_BINS;
+constexpr int kMomentSums = 14;   // W, W2, sum w v (3), sum w^2 v (3), sum w^2 v v^T (6)
+constexpr int kNumStages = 9;
+
+// Per-bin accumulators, in order.
+enum BinQ { QCount = 0, QKsum, QPdd, QPpp, QPtt, QPdt, QSdd, QSpp, QStt };
+
+// Polynomial weights of the six taps: w_j(f) = sum_p coef[j][p] f^p with
+// f = u - floor(u) in [0, 1).  FP64.
+struct TapPoly {
+  double c[kTaps][4];
+};
+
+// Scalars derived on the device from the moment sums (FP64).
+struct Derived {
+  double W, W2;
+  double vb[3];          // bulk flow
+  double s_dd;           // W2 / W^2
+  double S[6];           // shot tensor of the velocities used: xx yy zz xy xz yz
+  double s_pp;           // trace S
+  double inv_W;          // 1 / W
+  double sigma_v2;       // trace(sum w^2 v v^T) / W2 of the velocities used
+  int bulk;              // 1 if p is replaced by p - v_b delta
+};
+
+// Layout of the device result block copied back to the host.
+struct ResultHeader {
+  double sums[kMomentSums];
+  Derived d;
+  uint32_t flags;        // bit 0: non-finite position seen
+  uint32_t pad;
+};
+
+struct Plan;
+
+// ----------------------------------------------------------------- tables
+// Host-side FP64 construction of the truncated cubic Battle-Lemarie kernel.
+TapPoly bl3_tap_polynomials();
+// W_t(2 pi n / N)^2 and C_t(2 pi n / N) for n = 0..N/2.
+void bl3_axis_tables(int n_grid, std::vector<double>* win2, std::vector<double>* alias);
+// e^{-2 pi i m / N}, m = 0..N-1, interleaved (re, im).
+std::vector<double> twiddles(int n_grid);
+// n^2 -> bin (or -1) for n^2 in [0, (N/2)^2).  Returns false for bad edges.
+bool bin_lut(int n_grid, double box, int n_bins, const double* k_edges,
+             std::vector<int32_t>* lut, std::vector<double>* edges_out);
+
+// ----------------------------------------------------------------- plan
+struct Plan {
+  int n = 0;
+  mps_precision prec = MPS_F32;
+  int device = 0;
+  int tile = 16;
+  int64_t n_tiles = 0;
+  size_t real_size = 4;
+
+  void* grid = nullptr;              // 4 N^3 reals
+  float4* sorted = nullptr;          // 2 float4 per particle
+  int64_t sorted_cap = 0;
+  uint32_t* tile_count = nullptr;    // n_tiles
+  uint32_t* tile_offset = nullptr;   // n_tiles + 1
+  uint32_t* tile_cursor = nullptr;   // n_tiles
+  double* moment_partials = nullptr; // kMomentBlocks x kMomentSums
+  ResultHeader* d_header = nullptr;
+  double* d_win2 = nullptr;          // N/2 + 1
+  double* d_alias = nullptr;         // N/2 + 1
+  void* d_twiddle = nullptr;         // N complex of the plan's precision
+  int32_t* d_lut = nullptr;          // (N/2)^2
+  double* d_bin_partials = nullptr;  // bin_blocks x kMaxBins x kNumQ
+  double* d_bins = nullptr;          // kMaxBins x kNumQ (final sums)
+  int bin_blocks = 0;
+
+  // host staging (pinned): header + bins
+  void* h_stage = nullptr;
+  size_t stage_bytes = 0;
+
+  // bin-table cache key
+  double lut_box = -1.0;
+  int lut_nbins = -1;
+  std::vector<double> lut_edges;     // edges the LUT was built for (empty: default)
+  std::vector<double> edges_used;    // n_bins + 1 edges actually used
+
+  TapPoly taps;
+
+  // stage timing
+  bool timing = false;
+  hipEvent_t ev[kNumStages + 1] = {};
+  double stage_ms[kNumStages] = {};
+};
+
+constexpr int kMomentBlocks = 1024;
+
+// Estimate steps shared by the C ABI and the server (api.cpp).
+int validate_catalog(const Plan* p, const mps_catalog* c);
+int ensure_bins(Plan* p, const mps_catalog* c);
+int ensure_particles(Plan* p, int64_t np);
+int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s);  // async, incl. D2H
+int unpack(Plan* p, const mps_catalog* c, mps_result* out);          // after the stream synced
+
+// Launchers (particles.hip).  All enqueue on `stream`.
+hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s);
+hipError_t launch_derive(Plan* p, const mps_catalog* c, hipStream_t s);
+hipError_t launch_scan(Plan* p, hipStream_t s);
+hipError_t launch_permute(Plan* p, const mps_catalog* c, hipStream_t s);
+hipError_t launch_clear_grid(Plan* p, hipStream_t s);
+hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s);
+
+// Launchers (fft.hip).
+hipError_t launch_fft_z(Plan* p, void* grid, hipStream_t s);
+hipError_t launch_fft_y(Plan* p, void* grid, hipStream_t s);
+hipError_t launch_fft_x_store(Plan* p, void* grid, hipStream_t s);
+hipError_t launch_fft_x_bin(Plan* p, const mps_catalog* c, hipStream_t s);
+hipError_t launch_finalize(Plan* p, const mps_catalog* c, hipStream_t s);
+
+}  // namespace mps

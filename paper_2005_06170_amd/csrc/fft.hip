@@ -1,0 +1,490 @@
+// Fourier-side stages on gfx950: three pencil passes of a 3D real-to-complex
+// FFT kept in LDS (Stockham autosort, radix 8/4/2), the last of which is fused
+// with the per-mode estimator and |k|-shell binning, then a fixed-order
+// finalize.
+//
+// Layout.  Field f's real grid is [x][y][z], z fastest (4 fields stacked).
+// The z pass turns each row of N reals into N/2 complex values in place
+// (bins 0..N/2-1; the kz = N/2 plane is dropped: every mode on it has
+// |k| >= k_N and is never binned).  The y and x passes work on columns of the
+// resulting [x][y][kz] complex array.  The FFT sign is e^{-2 pi i n.g / N}.
+//
+// Per mode (the estimator of Eqs. rawPp, rawPtheta, rawPx with the BL3 window,
+// bulk-flow removal of Sec. 3.1 in Fourier space, p' = p - v_b delta):
+//   delta = F_0 / W, p = F_{1..3} / W,
+//   P_dd = (|delta|^2 - S_dd C) / W_t^2,  P_pp = (|p|^2 - tr S C) / W_t^2,
+//   P_tt = (|k.p|^2 - k^T S k C) / (Haf^2 W_t^2),
+//   P_dt = Re(delta conj(-i k.p / Haf)) / W_t^2,
+// with W_t^2 and C products of per-axis tables of the truncated kernel.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "common.h"
+
+namespace mps {
+namespace {
+
+template <typename T>
+struct cpx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_mi(cpx<T> a) { return {a.im, -a.re}; }  // * (-i)
+
+template <typename T>
+__device__ __forceinline__ void dft2(cpx<T>* v) {
+  const cpx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cpx<T>& a, cpx<T>& b, cpx<T>& c, cpx<T>& d) {
+  const cpx<T> s02 = a + c, d02 = a - c, s13 = b + d, d13 = mul_mi(b - d);
+  a = s02 + s13;
+  b = d02 + d13;
+  c = s02 - s13;
+  d = d02 - d13;
+}
+
+template <typename T>
+__device__ __forceinline__ void dft8(cpx<T>* v) {
+  cpx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cpx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  const T h = static_cast<T>(0.70710678118654752440);
+  // o_k *= e^{-2 pi i k / 8}
+  o1 = {h * (o1.re + o1.im), h * (o1.im - o1.re)};
+  o2 = mul_mi(o2);
+  o3 = {h * (o3.im - o3.re), -h * (o3.re + o3.im)};
+  v[0] = e0 + o0;
+  v[4] = e0 - o0;
+  v[1] = e1 + o1;
+  v[5] = e1 - o1;
+  v[2] = e2 + o2;
+  v[6] = e2 - o2;
+  v[3] = e3 + o3;
+  v[7] = e3 - o3;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft(cpx<T>* v) {
+  if constexpr (R == 8) dft8(v);
+  else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
+  else dft2(v);
+}
+
+// One radix-R Stockham pass over COUNT transforms of length L held in LDS
+// (element j of transform t at buf[t * tstride + j]).  tw[m * TWS] is
+// e^{-2 pi i m / L}.  Butterflies are dealt transform-fastest over NT threads.
+template <typename T, int L, int R, int NS, int COUNT, int NT, int TWS>
+__device__ __forceinline__ void stockham_pass(cpx<T>* buf, int tstride, const cpx<T>* tw) {
+  constexpr int NB = COUNT * (L / R);
+  constexpr int PER = (NB + NT - 1) / NT;
+  cpx<T> v[PER][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int b = tid + k * NT;
+    if (NB % NT == 0 || b < NB) {
+      const int t = b % COUNT, j = b / COUNT;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k][r] = buf[t * tstride + j + r * (L / R)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int b = tid + k * NT;
+    if (NB % NT == 0 || b < NB) {
+      const int t = b % COUNT, j = b / COUNT;
+      const int kk = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[k][r] = cmul(v[k][r], tw[(kk * r * (L / (NS * R))) * TWS]);
+      }
+      dft<T, R>(v[k]);
+      const int idx = (j / NS) * NS * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[t * tstride + idx + r * NS] = v[k][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int L, int NS, int COUNT, int NT, int TWS>
+__device__ __forceinline__ void fft_passes(cpx<T>* buf, int tstride, const cpx<T>* tw) {
+  if constexpr (NS < L) {
+    constexpr int REM = L / NS;
+    constexpr int R = REM >= 8 ? 8 : REM;
+    stockham_pass<T, L, R, NS, COUNT, NT, TWS>(buf, tstride, tw);
+    fft_passes<T, L, NS * R, COUNT, NT, TWS>(buf, tstride, tw);
+  }
+}
+
+template <typename T, int N, int NT>
+__device__ __forceinline__ void load_twiddles(cpx<T>* tw, const cpx<T>* __restrict__ gtw) {
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = gtw[i];
+}
+
+// ---------------------------------------------------------------- z pass
+// P rows of N reals per workgroup: complex FFT of length N/2 on the packed
+// even/odd samples, then the real-to-complex split.
+template <typename T, int N, int P, int NT>
+__global__ __launch_bounds__(NT) void fft_z_kernel(T* __restrict__ grid, const cpx<T>* __restrict__ gtw) {
+  constexpr int M = N / 2;
+  constexpr int TS = M + 1;
+  __shared__ cpx<T> buf[P * TS];
+  __shared__ cpx<T> tw[N];
+  load_twiddles<T, N, NT>(tw, gtw);
+  cpx<T>* rows = reinterpret_cast<cpx<T>*>(grid) + static_cast<int64_t>(blockIdx.x) * P * M;
+  for (int i = threadIdx.x; i < P * M; i += NT) {
+    const int q = i / M, j = i % M;
+    buf[q * TS + j] = rows[i];
+  }
+  __syncthreads();
+  fft_passes<T, M, 1, P, NT, 2>(buf, TS, tw);
+  const T half = static_cast<T>(0.5);
+  for (int i = threadIdx.x; i < P * M; i += NT) {
+    const int q = i / M, k = i % M;
+    const cpx<T> a = buf[q * TS + k];
+    const cpx<T> z2 = buf[q * TS + (M - k) % M];
+    const cpx<T> b = {z2.re, -z2.im};
+    const cpx<T> s = a + b, d = a - b;
+    const cpx<T> t = cmul(tw[k], mul_mi(d));
+    rows[i] = {half * (s.re + t.re), half * (s.im + t.im)};
+  }
+}
+
+// ------------------------------------------------------------- y, x passes
+// B columns (consecutive kz) of N complex values spaced by `stride` complex.
+// Workgroup index -> (field f, outer index o, column block kb); the column
+// block is fastest.  For the y pass outer = x and stride = N/2; for the x
+// pass outer = y and stride = N * N/2.
+template <typename T, int N, int B, int NT>
+__global__ __launch_bounds__(NT) void fft_cols_kernel(T* __restrict__ grid, const cpx<T>* __restrict__ gtw,
+                                                      int64_t stride, int64_t outer_stride) {
+  constexpr int M = N / 2;
+  constexpr int TS = N + 1;
+  constexpr int KB = M / B;
+  __shared__ cpx<T> buf[B * TS];
+  __shared__ cpx<T> tw[N];
+  load_twiddles<T, N, NT>(tw, gtw);
+  const int64_t blk = blockIdx.x;
+  const int kb = static_cast<int>(blk % KB);
+  const int64_t fo = blk / KB;                 // f * N + o
+  const int64_t f = fo / N, o = fo % N;
+  cpx<T>* base = reinterpret_cast<cpx<T>*>(grid) + f * static_cast<int64_t>(N) * N * M + o * outer_stride +
+                 kb * B;
+  for (int i = threadIdx.x; i < N * B; i += NT) {
+    const int r = i / B, c = i % B;
+    buf[c * TS + r] = base[r * stride + c];
+  }
+  __syncthreads();
+  fft_passes<T, N, 1, B, NT, 1>(buf, TS, tw);
+  for (int i = threadIdx.x; i < N * B; i += NT) {
+    const int r = i / B, c = i % B;
+    base[r * stride + c] = buf[c * TS + r];
+  }
+}
+
+// ------------------------------------------------- x pass fused with bins
+struct BinParams {
+  double kf;        // 2 pi / L
+  double haf;
+  int n_bins;
+  int no_shot;
+  int no_deconv;
+  int bulk;
+};
+
+__device__ __forceinline__ void flush_bin(double* lbins, int bin, const double* acc) {
+#pragma unroll
+  for (int q = 0; q < kNumQ; ++q) atomicAdd(lbins + bin * kNumQ + q, acc[q]);
+}
+
+// Persistent: workgroup g handles items g, g + G, ... where an item is one
+// y row and a block of B consecutive kz columns, for all four fields.  Items
+// whose every mode lies outside |n| < N/2 are skipped.  LDS bin sums of the
+// workgroup are written to partials[g] at the end (no global atomics, fixed
+// summation order in the finalize).
+template <typename T, int N, int B, int NT>
+__global__ __launch_bounds__(NT) void fft_x_bin_kernel(const T* __restrict__ grid, const cpx<T>* __restrict__ gtw,
+                                                       const ResultHeader* __restrict__ hdr,
+                                                       const double* __restrict__ win2_tab,
+                                                       const double* __restrict__ alias_tab,
+                                                       const int32_t* __restrict__ lut, BinParams bp,
+                                                       double* __restrict__ partials) {
+  constexpr int M = N / 2;
+  constexpr int TS = N + 1;
+  constexpr int KB = M / B;
+  constexpr int COUNT = kNumFields * B;
+  constexpr int MODES = B * N;
+  constexpr int RUN = MODES >= NT ? MODES / NT : 1;
+  constexpr int64_t H2 = static_cast<int64_t>(M) * M;
+  __shared__ cpx<T> buf[COUNT * TS];
+  __shared__ cpx<T> tw[N];
+  __shared__ double lbins[kMaxBins * kNumQ];
+  load_twiddles<T, N, NT>(tw, gtw);
+  for (int i = threadIdx.x; i < kMaxBins * kNumQ; i += NT) lbins[i] = 0.0;
+
+  const Derived d = hdr->d;
+  const double haf2 = bp.haf * bp.haf;
+  const int64_t field_stride = static_cast<int64_t>(N) * N * M;
+  const int64_t xstride = static_cast<int64_t>(N) * M;
+  const cpx<T>* g = reinterpret_cast<const cpx<T>*>(grid);
+  const int n_items = N * KB;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int y = item / KB, kb = item % KB;
+    const int ny = y < M ? y : y - N;
+    const int kz0 = kb * B;
+    if (static_cast<int64_t>(ny) * ny + static_cast<int64_t>(kz0) * kz0 >= H2) continue;
+    __syncthreads();  // previous item's LDS reads are done
+    for (int i = threadIdx.x; i < kNumFields * N * B; i += NT) {
+      const int c = i % B;
+      const int r = (i / B) % N;
+      const int f = i / (B * N);
+      buf[(f * B + c) * TS + r] = g[f * field_stride + r * xstride + static_cast<int64_t>(y) * M + kz0 + c];
+    }
+    __syncthreads();
+    fft_passes<T, N, 1, COUNT, NT, 1>(buf, TS, tw);
+
+    // per-mode estimator; each thread walks RUN consecutive kx of one column
+    int cur = -1;
+    double acc[kNumQ];
+#pragma unroll
+    for (int q = 0; q < kNumQ; ++q) acc[q] = 0.0;
+    const int m0 = threadIdx.x * RUN;
+    if (m0 < MODES) {
+      const int c = m0 / N;
+      const int nz = kz0 + c;
+      const double wgt = nz == 0 ? 1.0 : 2.0;
+      for (int r = 0; r < RUN; ++r) {
+        const int kx = (m0 % N) + r;
+        const int nx = kx < M ? kx : kx - N;
+        const int64_t n2 = static_cast<int64_t>(nx) * nx + static_cast<int64_t>(ny) * ny +
+                           static_cast<int64_t>(nz) * nz;
+        if (n2 == 0 || n2 >= H2) continue;
+        const int bin = lut[n2];
+        if (bin < 0) continue;
+        const int ax = nx < 0 ? -nx : nx, ay = ny < 0 ? -ny : ny;
+        const double w2 = bp.no_deconv ? 1.0 : win2_tab[ax] * win2_tab[ay] * win2_tab[nz];
+        const double cal = alias_tab[ax] * alias_tab[ay] * alias_tab[nz];
+        const cpx<T> F0 = buf[(0 * B + c) * TS + kx];
+        const cpx<T> F1 = buf[(1 * B + c) * TS + kx];
+        const cpx<T> F2 = buf[(2 * B + c) * TS + kx];
+        const cpx<T> F3 = buf[(3 * B + c) * TS + kx];
+        const double dr = static_cast<double>(F0.re) * d.inv_W, di = static_cast<double>(F0.im) * d.inv_W;
+        double pxr = static_cast<double>(F1.re) * d.inv_W, pxi = static_cast<double>(F1.im) * d.inv_W;
+        double pyr = static_cast<double>(F2.re) * d.inv_W, pyi = static_cast<double>(F2.im) * d.inv_W;
+        double pzr = static_cast<double>(F3.re) * d.inv_W, pzi = static_cast<double>(F3.im) * d.inv_W;
+        if (bp.bulk) {
+          pxr -= d.vb[0] * dr;
+          pxi -= d.vb[0] * di;
+          pyr -= d.vb[1] * dr;
+          pyi -= d.vb[1] * di;
+          pzr -= d.vb[2] * dr;
+          pzi -= d.vb[2] * di;
+        }
+        const double kx_ = bp.kf * nx, ky_ = bp.kf * ny, kz_ = bp.kf * nz;
+        const double kpr = kx_ * pxr + ky_ * pyr + kz_ * pzr;
+        const double kpi = kx_ * pxi + ky_ * pyi + kz_ * pzi;
+        const double iw2 = 1.0 / w2;
+        const double raw_dd = (dr * dr + di * di) * iw2;
+        const double raw_pp = (pxr * pxr + pxi * pxi + pyr * pyr + pyi * pyi + pzr * pzr + pzi * pzi) * iw2;
+        const double raw_tt = (kpr * kpr + kpi * kpi) * iw2 / haf2;
+        const double raw_dt = (dr * kpi - di * kpr) * iw2 / bp.haf;
+        const double ksk = d.S[0] * kx_ * kx_ + d.S[1] * ky_ * ky_ + d.S[2] * kz_ * kz_ +
+                           2.0 * (d.S[3] * kx_ * ky_ + d.S[4] * kx_ * kz_ + d.S[5] * ky_ * kz_);
+        const double sdd = d.s_dd * cal * iw2;
+        const double spp = d.s_pp * cal * iw2;
+        const double stt = ksk * cal * iw2 / haf2;
+        const double pdd = bp.no_shot ? raw_dd : raw_dd - sdd;
+        const double ppp = bp.no_shot ? raw_pp : raw_pp - spp;
+        const double ptt = bp.no_shot ? raw_tt : raw_tt - stt;
+        if (bin != cur) {
+          if (cur >= 0) flush_bin(lbins, cur, acc);
+#pragma unroll
+          for (int q = 0; q < kNumQ; ++q) acc[q] = 0.0;
+          cur = bin;
+        }
+        acc[QCount] += wgt;
+        acc[QKsum] += wgt * bp.kf * sqrt(static_cast<double>(n2));
+        acc[QPdd] += wgt * pdd;
+        acc[QPpp] += wgt * ppp;
+        acc[QPtt] += wgt * ptt;
+        acc[QPdt] += wgt * raw_dt;
+        acc[QSdd] += wgt * sdd;
+        acc[QSpp] += wgt * spp;
+        acc[QStt] += wgt * stt;
+      }
+    }
+    if (cur >= 0) flush_bin(lbins, cur, acc);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < bp.n_bins * kNumQ; i += NT)
+    partials[static_cast<int64_t>(blockIdx.x) * kMaxBins * kNumQ + i] = lbins[i];
+}
+
+// Fixed-order reduction of the workgroup partials and the final per-bin
+// means (times V = L^3); empty bins are NaN.
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ partials, int nblocks,
+                                                       int n_bins, double volume, double* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_bins * kNumQ) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partials[static_cast<int64_t>(b) * kMaxBins * kNumQ + i];
+  out[i] = s;
+}
+
+__global__ void finalize_means_kernel(double* __restrict__ sums, int n_bins, double volume) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bins) return;
+  double* s = sums + b * kNumQ;
+  const double cnt = s[QCount];
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  const double inv = cnt > 0 ? 1.0 / cnt : 0.0;
+  s[QKsum] = cnt > 0 ? s[QKsum] * inv : nan;
+  for (int q = QPdd; q < kNumQ; ++q) s[q] = cnt > 0 ? volume * s[q] * inv : nan;
+}
+
+template <typename T>
+struct FftDims {
+  static constexpr int ColsY(int n) {
+    const int b = (std::is_same<T, float>::value ? 16 : 8) * 512 / (n > 512 ? n : 512);
+    return b < n / 2 ? b : n / 2;
+  }
+  static constexpr int ColsX(int n) {
+    const int b = (std::is_same<T, float>::value ? 8 : 4) * 512 / (n > 512 ? n : 512);
+    return b < n / 2 ? b : n / 2;
+  }
+  static constexpr int RowsZ(int n) {
+    const int m = n / 2;
+    const int p = (std::is_same<T, float>::value ? 4096 : 2048) / m;
+    const int rows = 4 * n * n;
+    return p < rows ? (p < 1 ? 1 : p) : rows;
+  }
+};
+
+template <typename T, int N>
+hipError_t run_z(Plan* p, void* grid, hipStream_t s) {
+  constexpr int P = FftDims<T>::RowsZ(N);
+  const int64_t rows = static_cast<int64_t>(kNumFields) * N * N;
+  fft_z_kernel<T, N, P, 256><<<static_cast<unsigned>(rows / P), 256, 0, s>>>(
+      static_cast<T*>(grid), static_cast<const cpx<T>*>(p->d_twiddle));
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t run_cols(Plan* p, void* grid, hipStream_t s, bool x_axis) {
+  constexpr int B = FftDims<T>::ColsY(N);
+  constexpr int M = N / 2;
+  const int64_t blocks = static_cast<int64_t>(kNumFields) * N * (M / B);
+  const int64_t stride = x_axis ? static_cast<int64_t>(N) * M : M;
+  const int64_t outer = x_axis ? M : static_cast<int64_t>(N) * M;
+  fft_cols_kernel<T, N, B, 256><<<static_cast<unsigned>(blocks), 256, 0, s>>>(
+      static_cast<T*>(grid), static_cast<const cpx<T>*>(p->d_twiddle), stride, outer);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t run_x_bin(Plan* p, const mps_catalog* c, hipStream_t s) {
+  constexpr int B = FftDims<T>::ColsX(N);
+  BinParams bp;
+  bp.kf = 2.0 * M_PI / c->box;
+  bp.haf = c->haf;
+  bp.n_bins = c->n_bins;
+  bp.no_shot = (c->flags & MPS_NO_SHOTNOISE) ? 1 : 0;
+  bp.no_deconv = (c->flags & MPS_NO_DECONVOLVE) ? 1 : 0;
+  bp.bulk = (c->flags & MPS_BULKFLOW_SUBTRACT) ? 1 : 0;
+  fft_x_bin_kernel<T, N, B, 512><<<static_cast<unsigned>(p->bin_blocks), 512, 0, s>>>(
+      static_cast<const T*>(p->grid), static_cast<const cpx<T>*>(p->d_twiddle), p->d_header, p->d_win2,
+      p->d_alias, p->d_lut, bp, p->d_bin_partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_z(Plan* p, void* g, hipStream_t s) {
+  switch (p->n) {
+    case 8: return run_z<T, 8>(p, g, s);
+    case 16: return run_z<T, 16>(p, g, s);
+    case 32: return run_z<T, 32>(p, g, s);
+    case 64: return run_z<T, 64>(p, g, s);
+    case 128: return run_z<T, 128>(p, g, s);
+    case 256: return run_z<T, 256>(p, g, s);
+    case 512: return run_z<T, 512>(p, g, s);
+    case 1024: return run_z<T, 1024>(p, g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t dispatch_cols(Plan* p, void* g, hipStream_t s, bool x_axis) {
+  switch (p->n) {
+    case 8: return run_cols<T, 8>(p, g, s, x_axis);
+    case 16: return run_cols<T, 16>(p, g, s, x_axis);
+    case 32: return run_cols<T, 32>(p, g, s, x_axis);
+    case 64: return run_cols<T, 64>(p, g, s, x_axis);
+    case 128: return run_cols<T, 128>(p, g, s, x_axis);
+    case 256: return run_cols<T, 256>(p, g, s, x_axis);
+    case 512: return run_cols<T, 512>(p, g, s, x_axis);
+    case 1024: return run_cols<T, 1024>(p, g, s, x_axis);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t dispatch_x_bin(Plan* p, const mps_catalog* c, hipStream_t s) {
+  switch (p->n) {
+    case 8: return run_x_bin<T, 8>(p, c, s);
+    case 16: return run_x_bin<T, 16>(p, c, s);
+    case 32: return run_x_bin<T, 32>(p, c, s);
+    case 64: return run_x_bin<T, 64>(p, c, s);
+    case 128: return run_x_bin<T, 128>(p, c, s);
+    case 256: return run_x_bin<T, 256>(p, c, s);
+    case 512: return run_x_bin<T, 512>(p, c, s);
+    case 1024: return run_x_bin<T, 1024>(p, c, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_fft_z(Plan* p, void* grid, hipStream_t s) {
+  return p->prec == MPS_F32 ? dispatch_z<float>(p, grid, s) : dispatch_z<double>(p, grid, s);
+}
+
+hipError_t launch_fft_y(Plan* p, void* grid, hipStream_t s) {
+  return p->prec == MPS_F32 ? dispatch_cols<float>(p, grid, s, false) : dispatch_cols<double>(p, grid, s, false);
+}
+
+hipError_t launch_fft_x_store(Plan* p, void* grid, hipStream_t s) {
+  return p->prec == MPS_F32 ? dispatch_cols<float>(p, grid, s, true) : dispatch_cols<double>(p, grid, s, true);
+}
+
+hipError_t launch_fft_x_bin(Plan* p, const mps_catalog* c, hipStream_t s) {
+  return p->prec == MPS_F32 ? dispatch_x_bin<float>(p, c, s) : dispatch_x_bin<double>(p, c, s);
+}
+
+hipError_t launch_finalize(Plan* p, const mps_catalog* c, hipStream_t s) {
+  const int nq = c->n_bins * kNumQ;
+  const double vol = c->box * c->box * c->box;
+  finalize_kernel<<<(nq + 255) / 256, 256, 0, s>>>(p->d_bin_partials, p->bin_blocks, c->n_bins, vol, p->d_bins);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  finalize_means_kernel<<<1, kMaxBins, 0, s>>>(p->d_bins, c->n_bins, vol);
+  return hipGetLastError();
+}
+
+}  // namespace mps

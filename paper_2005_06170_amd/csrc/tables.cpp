@@ -1,0 +1,199 @@
+// Host-side FP64 tables of the estimator: the truncated cubic
+// Battle-Lemarie (BL3) tap polynomials, its window and alias sum per axis,
+// FFT twiddles and the |n|^2 -> bin lookup table.
+//
+// BL3 (third-order orthogonalised Battle-Lemarie scaling function, used for
+// assignment in Sec. 2.4.1) is read as the cubic-spline member of the family:
+// phi(x) = sum_n c_n beta3(x - n), where beta3 is the centred cubic B-spline
+// and c_n are the Fourier coefficients of A(w)^(-1/2),
+// A(w) = (2416 + 2382 cos w + 240 cos 2w + 2 cos 3w) / 5040, the alias sum of
+// |beta3_hat|^2.  phi is a cubic on every unit interval, so each of the six
+// taps j = -2..3 of a particle at fraction f carries a cubic weight
+// w_j(f) = phi(j - f).
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace mps {
+namespace {
+
+constexpr int kFilterHalf = 64;       // c_n, |n| <= 64 (|c_64| ~ 1e-19)
+constexpr int kTrapezoid = 2048;      // periodic trapezoid rule, exponentially exact
+
+double autocorr7(double w) {
+  return (2416.0 + 2382.0 * std::cos(w) + 240.0 * std::cos(2.0 * w) +
+          2.0 * std::cos(3.0 * w)) / 5040.0;
+}
+
+// c_n = (1/2pi) int_0^{2pi} A(w)^(-1/2) cos(n w) dw by the trapezoid rule.
+std::vector<double> filter_coefficients() {
+  std::vector<double> c(kFilterHalf + 1, 0.0);
+  for (int k = 0; k < kTrapezoid; ++k) {
+    const double w = 2.0 * M_PI * k / kTrapezoid;
+    const double g = 1.0 / std::sqrt(autocorr7(w));
+    for (int n = 0; n <= kFilterHalf; ++n) c[n] += g * std::cos(n * w);
+  }
+  for (double& v : c) v /= kTrapezoid;
+  return c;
+}
+
+double cn(const std::vector<double>& c, int n) {
+  n = n < 0 ? -n : n;
+  return n <= kFilterHalf ? c[n] : 0.0;
+}
+
+// Cubic of phi on [m, m+1] in t = x - m: coefficients of 1, t, t^2, t^3.
+// On that interval only beta3(x - n) with n = m-1..m+2 are non-zero; their
+// pieces are (1-t)^3/6, 2/3 - t^2 + t^3/2, 1/6 + t/2 + t^2/2 - t^3/2, t^3/6.
+void piece(const std::vector<double>& c, int m, double out[4]) {
+  static const double basis[4][4] = {
+      {1.0 / 6, -0.5, 0.5, -1.0 / 6},
+      {2.0 / 3, 0.0, -1.0, 0.5},
+      {1.0 / 6, 0.5, 0.5, -0.5},
+      {0.0, 0.0, 0.0, 1.0 / 6}};
+  for (int p = 0; p < 4; ++p) out[p] = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    const double ci = cn(c, m - 1 + i);
+    for (int p = 0; p < 4; ++p) out[p] += ci * basis[i][p];
+  }
+}
+
+double horner(const double a[4], double t) {
+  return ((a[3] * t + a[2]) * t + a[1]) * t + a[0];
+}
+
+// 16-point Gauss-Legendre nodes/weights on [0, 1] via Newton on P_16.
+void gauss_legendre(int n, std::vector<double>* x, std::vector<double>* w) {
+  x->resize(n);
+  w->resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    (*x)[i] = 0.5 * (1.0 - z);
+    (*w)[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // = 0.5 * 2/((1-z^2) P'^2)
+  }
+}
+
+struct Pieces {
+  double a[6][4];  // intervals m = -3..2
+};
+
+Pieces bl3_pieces() {
+  const std::vector<double> c = filter_coefficients();
+  Pieces p;
+  for (int m = -3; m <= 2; ++m) piece(c, m, p.a[m + 3]);
+  return p;
+}
+
+}  // namespace
+
+TapPoly bl3_tap_polynomials() {
+  const Pieces pc = bl3_pieces();
+  TapPoly tp;
+  // tap j covers d = j - f in (j-1, j]: interval m = j-1 with t = 1 - f.
+  // Substitute t = 1 - f: sum_p a_p (1 - f)^p.
+  static const double binom[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+  for (int j = 0; j < kTaps; ++j) {
+    const double* a = pc.a[j];  // j index 0 <-> tap -2 <-> interval -3
+    for (int q = 0; q < 4; ++q) tp.c[j][q] = 0.0;
+    for (int p = 0; p < 4; ++p)
+      for (int q = 0; q <= p; ++q)
+        tp.c[j][q] += a[p] * binom[p][q] * ((q & 1) ? -1.0 : 1.0);
+  }
+  return tp;
+}
+
+void bl3_axis_tables(int n_grid, std::vector<double>* win2, std::vector<double>* alias) {
+  const Pieces pc = bl3_pieces();
+  std::vector<double> gx, gw;
+  gauss_legendre(16, &gx, &gw);
+  // truncated autocorrelation a_s = int phi_t(x) phi_t(x + s) dx, s = 0..5
+  double a[6];
+  for (int s = 0; s < 6; ++s) {
+    double acc = 0.0;
+    for (int m = -3; m + s <= 2; ++m)
+      for (size_t i = 0; i < gx.size(); ++i)
+        acc += gw[i] * horner(pc.a[m + 3], gx[i]) * horner(pc.a[m + s + 3], gx[i]);
+    a[s] = acc;
+  }
+  const int half = n_grid / 2;
+  win2->assign(half + 1, 0.0);
+  alias->assign(half + 1, 0.0);
+  for (int n = 0; n <= half; ++n) {
+    const double w = 2.0 * M_PI * n / n_grid;
+    double wt = 0.0;
+    for (int m = -3; m <= 2; ++m)
+      for (size_t i = 0; i < gx.size(); ++i)
+        wt += gw[i] * horner(pc.a[m + 3], gx[i]) * std::cos(w * (m + gx[i]));
+    (*win2)[n] = wt * wt;
+    double cs = a[0];
+    for (int s = 1; s < 6; ++s) cs += 2.0 * a[s] * std::cos(s * w);
+    (*alias)[n] = cs;
+  }
+}
+
+std::vector<double> twiddles(int n_grid) {
+  std::vector<double> t(2 * n_grid);
+  for (int m = 0; m < n_grid; ++m) {
+    const double ang = 2.0 * M_PI * m / n_grid;
+    t[2 * m] = std::cos(ang);
+    t[2 * m + 1] = -std::sin(ang);
+  }
+  return t;
+}
+
+bool bin_lut(int n_grid, double box, int n_bins, const double* k_edges,
+             std::vector<int32_t>* lut, std::vector<double>* edges_out) {
+  const int64_t half = n_grid / 2;
+  const int64_t h2 = half * half;
+  const double kf = 2.0 * M_PI / box;
+  const double k_nyq = kf * static_cast<double>(half);
+  lut->assign(static_cast<size_t>(h2), -1);
+  edges_out->assign(n_bins + 1, 0.0);
+  if (k_edges == nullptr) {
+    const int64_t nb2 = static_cast<int64_t>(n_bins) * n_bins;
+    for (int64_t n2 = 1; n2 < h2; ++n2) {
+      const int64_t scaled = nb2 * n2;
+      int64_t b = static_cast<int64_t>(std::floor(std::sqrt(static_cast<double>(scaled)) /
+                                                  static_cast<double>(half)));
+      while (b > 0 && (b * half) * (b * half) > scaled) --b;
+      while (((b + 1) * half) * ((b + 1) * half) <= scaled) ++b;
+      (*lut)[n2] = b < n_bins ? static_cast<int32_t>(b) : -1;
+    }
+    for (int b = 0; b <= n_bins; ++b) (*edges_out)[b] = k_nyq * b / n_bins;
+    return true;
+  }
+  for (int b = 0; b <= n_bins; ++b) {
+    if (!std::isfinite(k_edges[b]) || k_edges[b] < 0.0) return false;
+    if (b > 0 && !(k_edges[b] > k_edges[b - 1])) return false;
+  }
+  if (k_edges[n_bins] > k_nyq * (1.0 + 1e-12)) return false;
+  std::vector<double> t(n_bins + 1);
+  for (int b = 0; b <= n_bins; ++b) {
+    const double r = k_edges[b] / kf;
+    t[b] = r * r;
+    (*edges_out)[b] = k_edges[b];
+  }
+  for (int64_t n2 = 1; n2 < h2; ++n2) {
+    const double x = static_cast<double>(n2);
+    int b = -1;
+    while (b + 1 <= n_bins && t[b + 1] <= x) ++b;  // count of t_b <= x, minus 1
+    (*lut)[n2] = (b >= 0 && b < n_bins) ? b : -1;
+  }
+  return true;
+}
+
+}  // namespace mps

@@ -1,0 +1,30 @@
+"""Helpers shared by the GPU parity tests."""
+import numpy as np
+
+
+def guarded_rel(gpu, orc, sn):
+    """|dP| / (|P_orc| + SN): the per-bin error that stays meaningful when the
+    true signal is zero (shot-noise dominated bins)."""
+    gpu, orc, sn = map(np.asarray, (gpu, orc, sn))
+    ok = np.isfinite(orc)
+    return np.abs(gpu[ok] - orc[ok]) / (np.abs(orc[ok]) + np.abs(sn[ok]))
+
+
+def compare_spectra(g, o, tol, label=""):
+    """Assert GPU result dict g matches oracle Spectra o within tol (guarded)."""
+    assert np.array_equal(g["n_modes"], o.n_modes), (label, g["n_modes"], o.n_modes)
+    empty = o.n_modes == 0
+    for key in ("k_mean", "p_pp", "p_tt", "p_dt", "p_dd", "sn_pp", "sn_tt", "sn_dd"):
+        assert np.all(np.isnan(g[key][empty])), (label, key)
+    assert np.allclose(g["k_mean"][~empty], o.k_mean[~empty], rtol=1e-12), label
+    errs = {}
+    for key, sn in (("p_pp", o.sn_pp), ("p_tt", o.sn_tt), ("p_dd", o.sn_dd),
+                    ("p_dt", np.sqrt(o.sn_dd * o.sn_tt))):
+        e = guarded_rel(g[key], getattr(o, key), sn)
+        errs[key] = float(e.max()) if e.size else 0.0
+    for key in ("sn_pp", "sn_tt", "sn_dd"):
+        ov = getattr(o, key)[~empty]
+        errs[key] = float(np.max(np.abs(g[key][~empty] - ov) / np.abs(ov))) if ov.size else 0.0
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, (label, errs)
+    return errs

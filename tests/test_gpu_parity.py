@@ -1,0 +1,163 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: the FP64-grid path must agree with the oracle to 1e-5 per bin and
+the FP32 path to 3e-4 per bin, in the guarded metric |dP| / (|P| + SN) that
+stays meaningful for shot-noise dominated bins; mode counts agree exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import catalogs
+from gpu_common import compare_spectra
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-5, "f32": 3e-4}
+
+
+def _dev(*arrays):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays]
+
+
+@pytest.fixture(scope="module")
+def mps():
+    import paper_2005_06170_amd as m
+    return m
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,npart", [(8, 50), (16, 777), (32, 5000)])
+def test_assignment_matches_oracle(mps, prec, n, npart):
+    box = 1000.0
+    pos, vel, w = catalogs.uniform_gaussian(npart, box, seed=100 + n, with_weights=True)
+    pos[0] = [0.0, box, -1.0]            # node, x = L, negative: all wrap
+    pos[1] = [box * 0.5, 1e-7, box - 1e-3]
+    plan = mps.Plan(n, prec)
+    g = plan.assign(*_dev(pos, vel, w), box=box).cpu().numpy().astype(np.float64)
+    w64, v64 = w.astype(np.float64), vel.astype(np.float64)
+    q = np.stack([w64, w64 * v64[:, 0], w64 * v64[:, 1], w64 * v64[:, 2]])
+    want = oracle.assign(pos, q, box, n)
+    scale = np.abs(want).max(axis=(1, 2, 3), keepdims=True)
+    err = np.max(np.abs(g - want) / scale)
+    assert err < (1e-12 if prec == "f64" else 2e-6), err
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [8, 16, 64, 128])
+def test_fft_matches_rfftn(mps, prec, n):
+    rng = np.random.default_rng(n)
+    x = rng.normal(size=(4, n, n, n))
+    plan = mps.Plan(n, prec)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    g = torch.from_numpy(x).to(dt).cuda().contiguous()
+    F = plan.fft(g).cpu().numpy()
+    want = np.fft.rfftn(x.astype(np.float32 if prec == "f32" else np.float64).astype(np.float64),
+                        axes=(1, 2, 3))[..., : n // 2]
+    err = np.max(np.abs(F - want)) / np.max(np.abs(want))
+    assert err < (1e-13 if prec == "f64" else 2e-6), err
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_config1_uniform_gaussian(mps, prec):
+    """64^3 grid, L = 1000, 100,000 uniform particles, sigma_v = 300 km/s."""
+    box, n, haf = 1000.0, 64, 50.0
+    pos, vel = catalogs.uniform_gaussian(100_000, box, 300.0, seed=catalogs.seed_for(1))
+    o = oracle.estimate(pos, vel, box=box, n_grid=n, haf=haf)
+    g = mps.Plan(n, prec).estimate(*_dev(pos, vel), box=box, haf=haf)
+    errs = compare_spectra(g, o, TOL[prec], f"config1 {prec}")
+    print(prec, errs)
+    assert np.allclose(g["v_bulk"], o.v_bulk, rtol=1e-12, atol=1e-12)
+    assert math.isclose(g["sigma_v2"], o.sigma_v2, rel_tol=1e-12)
+    assert math.isclose(g["n_eff"], o.n_eff, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("flags", [
+    dict(bulk_flow=True), dict(no_shotnoise=True), dict(no_deconvolve=True),
+    dict(bulk_flow=True, no_deconvolve=True)])
+def test_flags_match_oracle(mps, prec, flags):
+    box, n, haf = 500.0, 32, 50.0
+    pos, vel, w = catalogs.uniform_gaussian(20_000, box, 300.0, seed=7,
+                                            bulk=catalogs.bulk_vector(341.0), with_weights=True)
+    of = ((oracle.FLAG_BULKFLOW_SUBTRACT if flags.get("bulk_flow") else 0)
+          | (oracle.FLAG_NO_SHOTNOISE if flags.get("no_shotnoise") else 0)
+          | (oracle.FLAG_NO_DECONVOLVE if flags.get("no_deconvolve") else 0))
+    o = oracle.estimate(pos, vel, w, box=box, n_grid=n, haf=haf, n_bins=16, flags=of)
+    g = mps.Plan(n, prec).estimate(*_dev(pos, vel, w), box=box, haf=haf, n_bins=16, **flags)
+    compare_spectra(g, o, TOL[prec], f"{flags} {prec}")
+    if flags.get("bulk_flow"):
+        assert math.isclose(g["sigma_v2"], o.sigma_v2, rel_tol=1e-10)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_user_edges_and_zeldovich(mps, prec):
+    box, n, haf = 1000.0, 64, 50.0
+    pos, vel = catalogs.zeldovich(48, box, 6.0, haf=haf, seed=9)
+    edges = np.array([0.0, 0.013, 0.02, 0.05, 0.08, 0.131, 0.2])
+    o = oracle.estimate(pos, vel, box=box, n_grid=n, haf=haf, k_edges=edges)
+    g = mps.Plan(n, prec).estimate(*_dev(pos, vel), box=box, haf=haf, k_edges=edges)
+    compare_spectra(g, o, TOL[prec], f"edges {prec}")
+
+
+def test_tiny_grid_and_single_particle(mps):
+    box = 10.0
+    pos = np.array([[3.3, 9.99, 0.0]], np.float32)
+    vel = np.array([[100.0, -50.0, 20.0]], np.float32)
+    for n in (8, 16):
+        o = oracle.estimate(pos, vel, box=box, n_grid=n, haf=50.0, n_bins=4,
+                            flags=oracle.FLAG_NO_SHOTNOISE)
+        g = mps.Plan(n, "f64").estimate(*_dev(pos, vel), box=box, haf=50.0, n_bins=4,
+                                        no_shotnoise=True)
+        compare_spectra(g, o, 1e-9, f"single particle n={n}")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ragged_many_tiles(mps, prec):
+    """128^3 grid (512 tiles of 16^3 or 4096 of 8^3) with a count that is not
+    a multiple of any launch width, clustered to load tiles unevenly."""
+    box, n, haf = 1000.0, 128, 50.0
+    rng = np.random.default_rng(5)
+    base = rng.random((3, 3)) * box
+    pos = (base[rng.integers(0, 3, 300_001)] + rng.normal(0, 40.0, (300_001, 3))) % box
+    pos = pos.astype(np.float32)
+    vel = rng.normal(0, 250.0, (300_001, 3)).astype(np.float32)
+    o = oracle.estimate(pos, vel, box=box, n_grid=n, haf=haf, n_bins=40)
+    g = mps.Plan(n, prec).estimate(*_dev(pos, vel), box=box, haf=haf, n_bins=40)
+    compare_spectra(g, o, TOL[prec], f"ragged {prec}")
+
+
+def test_error_paths(mps):
+    from paper_2005_06170_amd._lib import MpsError
+    box = 100.0
+    pos, vel = catalogs.uniform_gaussian(1000, box, seed=1)
+    plan = mps.Plan(16, "f32")
+    bad = pos.copy()
+    bad[17, 1] = np.nan
+    with pytest.raises(MpsError) as e:
+        plan.estimate(*_dev(bad, vel), box=box, haf=50.0)
+    assert e.value.status == -2
+    badv = vel.copy()
+    badv[3, 0] = np.inf
+    with pytest.raises(MpsError) as e:
+        plan.estimate(*_dev(pos, badv), box=box, haf=50.0)
+    assert e.value.status == -2
+    w0 = np.zeros(1000, np.float32)
+    with pytest.raises(MpsError) as e:
+        plan.estimate(*_dev(pos, vel, w0), box=box, haf=50.0)
+    assert e.value.status == -3
+    kn = math.pi * 16 / box
+    for kw in (dict(k_edges=[0.0, 0.5 * kn, 1.01 * kn]), dict(k_edges=[0.0, 0.2, 0.1]),
+               dict(n_bins=0), dict(n_bins=129)):
+        with pytest.raises(MpsError) as e:
+            plan.estimate(*_dev(pos, vel), box=box, haf=50.0, **kw)
+        assert e.value.status == -1, kw
+    with pytest.raises(MpsError):
+        plan.estimate(*_dev(pos, vel), box=-1.0, haf=50.0)
+    # the plan still works after errors
+    g = plan.estimate(*_dev(pos, vel), box=box, haf=50.0, n_bins=8)
+    o = oracle.estimate(pos, vel, box=box, n_grid=16, haf=50.0, n_bins=8)
+    compare_spectra(g, o, 3e-4, "after errors")
