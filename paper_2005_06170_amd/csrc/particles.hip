@@ -236,24 +236,256 @@ __device__ __forceinline__ double tap_weight(const TapPoly& tp, int j, double f)
   return ((tp.c[j][3] * f + tp.c[j][2]) * f + tp.c[j][1]) * f + tp.c[j][0];
 }
 
-// One workgroup per occupied tile.  LDS holds the four fields over the tile
-// plus a halo of 2 cells below and 3 above along each axis (taps -2..3).
-template <typename T, int TS, int NT>
-__global__ __launch_bounds__(NT) void scatter_kernel(
-    const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, T* __restrict__ grid,
-    KeyParams kp, int64_t n_tiles, int64_t xcd_chunk, TapPoly tp, Derived* dsrc, int bulk) {
+// Largest |phi_t(x) phi_t(y) phi_t(z)| over the truncated kernel: phi(0)^3
+// = 1.0890^3 = 1.2916, rounded up.
+constexpr double kPhiMax = 1.3;
+
+template <typename T>
+struct DepositQ {
+  T q[kNumFields];
+};
+
+// Charges (w, w v_x, w v_y, w v_z) of one particle record; bulk = 1 deposits
+// w (v - v_b) instead (the assign diagnostic's bulk-flow grids).
+template <typename T>
+__device__ __forceinline__ DepositQ<T> charges(const float4& a, const float4& v, int bulk, double vb0,
+                                               double vb1, double vb2) {
+  DepositQ<T> d;
+  if (bulk) {
+    const double w = a.w;
+    d.q[0] = static_cast<T>(w);
+    d.q[1] = static_cast<T>(w * (static_cast<double>(v.x) - vb0));
+    d.q[2] = static_cast<T>(w * (static_cast<double>(v.y) - vb1));
+    d.q[3] = static_cast<T>(w * (static_cast<double>(v.z) - vb2));
+  } else {
+    d.q[0] = static_cast<T>(a.w);
+    d.q[1] = static_cast<T>(a.w) * static_cast<T>(v.x);
+    d.q[2] = static_cast<T>(a.w) * static_cast<T>(v.y);
+    d.q[3] = static_cast<T>(a.w) * static_cast<T>(v.z);
+  }
+  return d;
+}
+
+// Tap weights and the particle's cell relative to the tile origin.
+template <typename T, int TS>
+__device__ __forceinline__ unsigned particle_taps(const float4& a, const KeyParams& kp, int ox, int oy, int oz,
+                                                  const TapPoly& tp, T* wx, T* wy, T* wz) {
   constexpr int E = TS + 5;
-  constexpr int VOL = E * E * E;
-  __shared__ T acc[kNumFields * VOL];
-  const int64_t b = blockIdx.x;
+  double fx, fy, fz;
+  bool ok;
+  int cx = locate(a.x, kp.scale, kp.n, &fx, &ok) - ox;
+  int cy = locate(a.y, kp.scale, kp.n, &fy, &ok) - oy;
+  int cz = locate(a.z, kp.scale, kp.n, &fz, &ok) - oz;
+  // the sort placed the particle in this tile with the same locate(); the
+  // clamp only keeps LDS indices in range
+  cx = min(max(cx, 0), TS - 1);
+  cy = min(max(cy, 0), TS - 1);
+  cz = min(max(cz, 0), TS - 1);
+#pragma unroll
+  for (int j = 0; j < kTaps; ++j) {
+    wx[j] = static_cast<T>(tap_weight(tp, j, fx));
+    wy[j] = static_cast<T>(tap_weight(tp, j, fy));
+    wz[j] = static_cast<T>(tap_weight(tp, j, fz));
+  }
+  return static_cast<unsigned>((cx * E + cy) * E + cz);
+}
+
+__device__ __forceinline__ int64_t tile_of_block(int64_t b, int64_t xcd_chunk) {
   // consecutive tiles (spatial neighbours, which share halo cache lines) go
   // to one XCD: workgroups are dealt to the 8 XCDs round robin
-  const int64_t tile = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
+  return xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
+}
+
+// Rounds wxy * qs to the nearest integer in two instructions: for
+// |x| < 2^22, x + 1.5 * 2^23 is an integer-valued float whose bit pattern
+// minus that of 1.5 * 2^23 is round(x).
+constexpr float kMagic = 12582912.0f;      // 1.5 * 2^23
+constexpr int kMagicBits = 0x4B400000;
+
+// Lane assignment that spreads a wave over the LDS banks.  Each chunk of NT
+// particles is counting-sorted by (LDS word index mod 64) of its tap origin;
+// lane l of wave w then takes bank-sorted position l * W + w, W = the number
+// of waves the chunk fills, so the 64 lanes of a wave come from 64
+// consecutive bank segments: about one lane per bank (two on a 32-bank LDS)
+// and never two lanes on one address.
+template <int NT>
+struct BankSort {
+  int cnt[64];
+  unsigned short idx[NT];
+};
+
+template <int NT>
+__device__ __forceinline__ int bank_sorted_index(BankSort<NT>& bs, bool valid, unsigned bank, int m) {
+  const int t = threadIdx.x;
+  if (t < 64) bs.cnt[t] = 0;
+  __syncthreads();
+  int slot = 0;
+  if (valid) slot = atomicAdd(&bs.cnt[bank], 1);
+  __syncthreads();
+  if (t < 64) {  // exclusive scan of 64 counters in one wave
+    int v = bs.cnt[t];
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(incl, off);
+      if (t >= off) incl += o;
+    }
+    bs.cnt[t] = incl - v;
+  }
+  __syncthreads();
+  if (valid) bs.idx[bs.cnt[bank] + slot] = static_cast<unsigned short>(t);
+  __syncthreads();
+  // a partial chunk (m < NT) occupies only ceil(m / 64) full waves
+  const int waves = (m + 63) >> 6;
+  const int w = t >> 6;
+  const int q = (t & 63) * waves + w;
+  return (w < waves && q < m) ? bs.idx[q] : -1;
+}
+
+// FP32 grids.  One workgroup per occupied tile.  LDS holds the four fields
+// over the tile plus a halo of 2 cells below and 3 above along each axis
+// (taps -2..3) as 32-bit fixed point: gfx950's LDS adds integers at ~14
+// lanes/clk/CU but FP32 at ~0.3.  Each field's scale is chosen per tile so
+// that no cell total can leave int32 (|cell| <= kPhiMax sum_tile |q|; the
+// final value is exact modulo 2^32 whatever the order of the adds) and no
+// single deposit reaches 2^22 (the rounding above).
+template <int TS, int NT>
+__global__ __launch_bounds__(NT) void scatter_fixed_kernel(
+    const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, float* __restrict__ grid,
+    KeyParams kp, int64_t n_tiles, int64_t xcd_chunk, TapPoly tp, const Derived* dsrc, int bulk) {
+  constexpr int E = TS + 5;
+  constexpr int VOL = E * E * E;
+  __shared__ int acc[kNumFields * VOL];
+  __shared__ BankSort<NT> bs;
+  __shared__ double red[NT / 64][2 * kNumFields];
+  __shared__ float scale_s[kNumFields], inv_s[kNumFields];
+  const int64_t tile = tile_of_block(blockIdx.x, xcd_chunk);
   if (tile >= n_tiles) return;
   const uint32_t p0 = offset[tile], p1 = offset[tile + 1];
   if (p0 == p1) return;
-  for (int i = threadIdx.x; i < kNumFields * VOL; i += NT) acc[i] = T(0);
-  // bulk-flow removal in the grid itself (the assign diagnostic): v - v_b
+  double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
+  if (bulk) {
+    vb0 = dsrc->vb[0];
+    vb1 = dsrc->vb[1];
+    vb2 = dsrc->vb[2];
+  }
+  // pass 1: per-field sum and max of |q| over the tile's particles (FP64)
+  double sq[kNumFields] = {0.0, 0.0, 0.0, 0.0}, mq[kNumFields] = {0.0, 0.0, 0.0, 0.0};
+  for (uint32_t p = p0 + threadIdx.x; p < p1; p += NT) {
+    const DepositQ<double> d =
+        charges<double>(sorted[2 * static_cast<int64_t>(p)], sorted[2 * static_cast<int64_t>(p) + 1], bulk,
+                        vb0, vb1, vb2);
+#pragma unroll
+    for (int f = 0; f < kNumFields; ++f) {
+      sq[f] += fabs(d.q[f]);
+      mq[f] = fmax(mq[f], fabs(d.q[f]));
+    }
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int f = 0; f < kNumFields; ++f) {
+    double t = wave_sum(sq[f]);
+    double m = mq[f];
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (lane == 0) {
+      red[wave][f] = t;
+      red[wave][kNumFields + f] = m;
+    }
+  }
+  for (int i = threadIdx.x; i < kNumFields * VOL; i += NT) acc[i] = 0;
+  __syncthreads();
+  if (threadIdx.x < kNumFields) {
+    double b = 0.0, m = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+      b += red[w][threadIdx.x];
+      m = fmax(m, red[w][kNumFields + threadIdx.x]);
+    }
+    const double by_sum = b > 0.0 ? 0.98 * 2147483648.0 / (kPhiMax * 1.0001 * b) : 0.0;
+    const double by_max = m > 0.0 ? 0.99 * 4194304.0 / (kPhiMax * m) : 0.0;
+    const double sc = fmin(by_sum, by_max);
+    scale_s[threadIdx.x] = static_cast<float>(sc);
+    inv_s[threadIdx.x] = sc > 0.0 ? static_cast<float>(1.0 / static_cast<double>(static_cast<float>(sc))) : 0.f;
+  }
+  __syncthreads();
+  float sc[kNumFields];
+#pragma unroll
+  for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
+  const int nt = kp.nt;
+  const int tz = static_cast<int>(tile % nt);
+  const int ty = static_cast<int>((tile / nt) % nt);
+  const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
+  const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
+  // pass 2: deposit, chunk by chunk in bank-sorted lane order
+  for (uint32_t c0 = p0; c0 < p1; c0 += NT) {
+    const int m = static_cast<int>(min(static_cast<uint32_t>(NT), p1 - c0));
+    const bool mine = static_cast<int>(threadIdx.x) < m;
+    unsigned bank = 0;
+    if (mine) {
+      float wx[kTaps], wy[kTaps], wz[kTaps];
+      bank = particle_taps<float, TS>(sorted[2 * static_cast<int64_t>(c0 + threadIdx.x)], kp, ox, oy, oz, tp, wx,
+                                      wy, wz) & 63u;
+    }
+    const int j = bank_sorted_index<NT>(bs, mine, bank, m);
+    if (j < 0) continue;
+    const uint32_t p = c0 + static_cast<uint32_t>(j);
+    const float4 a = sorted[2 * static_cast<int64_t>(p)];
+    const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
+    float wx[kTaps], wy[kTaps], wz[kTaps];
+    const unsigned base = particle_taps<float, TS>(a, kp, ox, oy, oz, tp, wx, wy, wz);
+    const DepositQ<float> d = charges<float>(a, v, bulk, vb0, vb1, vb2);
+    float qs[kNumFields][kTaps];
+#pragma unroll
+    for (int f = 0; f < kNumFields; ++f)
+#pragma unroll
+      for (int jj = 0; jj < kTaps; ++jj) qs[f][jj] = d.q[f] * sc[f] * wz[jj];
+    int* accf[kNumFields] = {acc + base, acc + VOL + base, acc + 2 * VOL + base, acc + 3 * VOL + base};
+#pragma unroll
+    for (int jx = 0; jx < kTaps; ++jx) {
+#pragma unroll
+      for (int jy = 0; jy < kTaps; ++jy) {
+        const float wxy = wx[jx] * wy[jy];
+#pragma unroll
+        for (int f = 0; f < kNumFields; ++f)
+#pragma unroll
+          for (int jz = 0; jz < kTaps; ++jz)
+            atomicAdd(accf[f] + (jx * E + jy) * E + jz,
+                      __float_as_int(fmaf(wxy, qs[f][jz], kMagic)) - kMagicBits);
+      }
+    }
+  }
+  __syncthreads();
+  const int n = kp.n;
+  const int64_t n3 = static_cast<int64_t>(n) * n * n;
+  float inv[kNumFields];
+#pragma unroll
+  for (int f = 0; f < kNumFields; ++f) inv[f] = inv_s[f];
+  for (int i = threadIdx.x; i < VOL; i += NT) {
+    const int ez = i % E, ey = (i / E) % E, ex = i / (E * E);
+    const int gx = (ox + ex - 2) & (n - 1);
+    const int gy = (oy + ey - 2) & (n - 1);
+    const int gz = (oz + ez - 2) & (n - 1);
+    const int64_t gi = (static_cast<int64_t>(gx) * n + gy) * n + gz;
+#pragma unroll
+    for (int f = 0; f < kNumFields; ++f) {
+      const int val = acc[f * VOL + i];
+      if (val != 0) atomicAdd(grid + f * n3 + gi, static_cast<float>(val) * inv[f]);
+    }
+  }
+}
+
+// FP64 grids: LDS accumulation with ds_add_f64 (~7 lanes/clk/CU on gfx950).
+template <int TS, int NT>
+__global__ __launch_bounds__(NT) void scatter_f64_kernel(
+    const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, double* __restrict__ grid,
+    KeyParams kp, int64_t n_tiles, int64_t xcd_chunk, TapPoly tp, const Derived* dsrc, int bulk) {
+  constexpr int E = TS + 5;
+  constexpr int VOL = E * E * E;
+  __shared__ double acc[kNumFields * VOL];
+  __shared__ BankSort<NT> bs;
+  const int64_t tile = tile_of_block(blockIdx.x, xcd_chunk);
+  if (tile >= n_tiles) return;
+  const uint32_t p0 = offset[tile], p1 = offset[tile + 1];
+  if (p0 == p1) return;
+  for (int i = threadIdx.x; i < kNumFields * VOL; i += NT) acc[i] = 0.0;
   double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
   if (bulk) {
     vb0 = dsrc->vb[0];
@@ -266,53 +498,40 @@ __global__ __launch_bounds__(NT) void scatter_kernel(
   const int ty = static_cast<int>((tile / nt) % nt);
   const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
   const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
-  for (uint32_t p = p0 + threadIdx.x; p < p1; p += NT) {
+  // bank-sorted lane order (see the FP32 kernel); one double spans two banks,
+  // so the bank key is the word index of the double mod 64 halved
+  for (uint32_t c0 = p0; c0 < p1; c0 += NT) {
+    const int m = static_cast<int>(min(static_cast<uint32_t>(NT), p1 - c0));
+    const bool mine = static_cast<int>(threadIdx.x) < m;
+    unsigned bank = 0;
+    if (mine) {
+      double wx[kTaps], wy[kTaps], wz[kTaps];
+      bank = particle_taps<double, TS>(sorted[2 * static_cast<int64_t>(c0 + threadIdx.x)], kp, ox, oy, oz, tp, wx,
+                                       wy, wz) & 31u;
+    }
+    const int j = bank_sorted_index<NT>(bs, mine, bank, m);
+    if (j < 0) continue;
+    const uint32_t p = c0 + static_cast<uint32_t>(j);
     const float4 a = sorted[2 * static_cast<int64_t>(p)];
     const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
-    double fx, fy, fz;
-    bool ok;
-    int cx = locate(a.x, kp.scale, kp.n, &fx, &ok) - ox;
-    int cy = locate(a.y, kp.scale, kp.n, &fy, &ok) - oy;
-    int cz = locate(a.z, kp.scale, kp.n, &fz, &ok) - oz;
-    cx = min(max(cx, 0), TS - 1);
-    cy = min(max(cy, 0), TS - 1);
-    cz = min(max(cz, 0), TS - 1);
-    T wx[kTaps], wy[kTaps], wz[kTaps];
-#pragma unroll
-    for (int j = 0; j < kTaps; ++j) {
-      wx[j] = static_cast<T>(tap_weight(tp, j, fx));
-      wy[j] = static_cast<T>(tap_weight(tp, j, fy));
-      wz[j] = static_cast<T>(tap_weight(tp, j, fz));
-    }
-    T q[kNumFields];
-    if (bulk) {
-      const double w = a.w;
-      q[0] = static_cast<T>(w);
-      q[1] = static_cast<T>(w * (static_cast<double>(v.x) - vb0));
-      q[2] = static_cast<T>(w * (static_cast<double>(v.y) - vb1));
-      q[3] = static_cast<T>(w * (static_cast<double>(v.z) - vb2));
-    } else {
-      q[0] = static_cast<T>(a.w);
-      q[1] = static_cast<T>(a.w) * static_cast<T>(v.x);
-      q[2] = static_cast<T>(a.w) * static_cast<T>(v.y);
-      q[3] = static_cast<T>(a.w) * static_cast<T>(v.z);
-    }
-    T qz[kNumFields][kTaps];
+    double wx[kTaps], wy[kTaps], wz[kTaps];
+    const unsigned base = particle_taps<double, TS>(a, kp, ox, oy, oz, tp, wx, wy, wz);
+    const DepositQ<double> d = charges<double>(a, v, bulk, vb0, vb1, vb2);
+    double qz[kNumFields][kTaps];
 #pragma unroll
     for (int f = 0; f < kNumFields; ++f)
 #pragma unroll
-      for (int j = 0; j < kTaps; ++j) qz[f][j] = q[f] * wz[j];
-    const int base = (cx * E + cy) * E + cz;
+      for (int j = 0; j < kTaps; ++j) qz[f][j] = d.q[f] * wz[j];
+    double* accf[kNumFields] = {acc + base, acc + VOL + base, acc + 2 * VOL + base, acc + 3 * VOL + base};
 #pragma unroll
     for (int jx = 0; jx < kTaps; ++jx) {
 #pragma unroll
       for (int jy = 0; jy < kTaps; ++jy) {
-        const T wxy = wx[jx] * wy[jy];
-        T* row = acc + base + (jx * E + jy) * E;
+        const double wxy = wx[jx] * wy[jy];
 #pragma unroll
         for (int f = 0; f < kNumFields; ++f)
 #pragma unroll
-          for (int jz = 0; jz < kTaps; ++jz) atomicAdd(row + f * VOL + jz, wxy * qz[f][jz]);
+          for (int jz = 0; jz < kTaps; ++jz) atomicAdd(accf[f] + (jx * E + jy) * E + jz, wxy * qz[f][jz]);
       }
     }
   }
@@ -327,8 +546,8 @@ __global__ __launch_bounds__(NT) void scatter_kernel(
     const int64_t gi = (static_cast<int64_t>(gx) * n + gy) * n + gz;
 #pragma unroll
     for (int f = 0; f < kNumFields; ++f) {
-      const T val = acc[f * VOL + i];
-      if (val != T(0)) atomicAdd(grid + f * n3 + gi, val);
+      const double val = acc[f * VOL + i];
+      if (val != 0.0) atomicAdd(grid + f * n3 + gi, val);
     }
   }
 }
@@ -408,21 +627,18 @@ hipError_t launch_clear_grid(Plan* p, hipStream_t s) {
 hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int bulk) {
   const KeyParams kp = key_params(p, c);
   const int64_t xcd_chunk = (p->n_tiles % 8 == 0) ? p->n_tiles / 8 : 0;
-  Derived* dsrc = &p->d_header->d;
+  const Derived* dsrc = &p->d_header->d;
   const unsigned grid = static_cast<unsigned>(p->n_tiles);
   if (p->prec == MPS_F32) {
     if (p->tile == 16)
-      scatter_kernel<float, 16, 1024><<<grid, 1024, 0, s>>>(p->sorted, p->tile_offset,
-                                                              static_cast<float*>(p->grid), kp, p->n_tiles,
-                                                              xcd_chunk, p->taps, dsrc, bulk);
+      scatter_fixed_kernel<16, 1024><<<grid, 1024, 0, s>>>(p->sorted, p->tile_offset, static_cast<float*>(p->grid),
+                                                            kp, p->n_tiles, xcd_chunk, p->taps, dsrc, bulk);
     else
-      scatter_kernel<float, 8, 512><<<grid, 512, 0, s>>>(p->sorted, p->tile_offset,
-                                                          static_cast<float*>(p->grid), kp, p->n_tiles,
-                                                          xcd_chunk, p->taps, dsrc, bulk);
+      scatter_fixed_kernel<8, 512><<<grid, 512, 0, s>>>(p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp,
+                                                         p->n_tiles, xcd_chunk, p->taps, dsrc, bulk);
   } else {
-    scatter_kernel<double, 8, 512><<<grid, 512, 0, s>>>(p->sorted, p->tile_offset,
-                                                         static_cast<double*>(p->grid), kp, p->n_tiles,
-                                                         xcd_chunk, p->taps, dsrc, bulk);
+    scatter_f64_kernel<8, 512><<<grid, 512, 0, s>>>(p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp,
+                                                     p->n_tiles, xcd_chunk, p->taps, dsrc, bulk);
   }
   return hipGetLastError();
 }

@@ -40,14 +40,14 @@ def uniform_gaussian(n: int, box: float, sigma_v: float = 300.0, seed: int = 0,
     vel = rng.normal(0.0, sigma_v, (n, 3))
     if bulk is not None:
         vel = vel + np.asarray(bulk, dtype=np.float64)[None, :]
-    out = (_wrap32(pos, box), vel.astype(np.float32))
+    out = (_wrap32(pos, box), np.ascontiguousarray(vel, dtype=np.float32))
     if with_weights:
         out = out + (rng.uniform(0.5, 1.5, n).astype(np.float32),)
     return out
 
 
 def _wrap32(pos, box):
-    p = np.mod(pos, box).astype(np.float32)
+    p = np.ascontiguousarray(np.mod(pos, box), dtype=np.float32)
     # rounding to float32 can land exactly on L; that is a legal periodic
     # coordinate, but keep generated catalogs inside [0, L)
     p[p >= np.float32(box)] = 0.0
@@ -115,7 +115,7 @@ def zeldovich(n_lattice: int, box: float, rms_disp: float, haf: float = 50.0,
     vel = haf * disp
     if bulk is not None:
         vel = vel + np.asarray(bulk, dtype=np.float64)[None, :]
-    return pos, vel.astype(np.float32)
+    return pos, np.ascontiguousarray(vel, dtype=np.float32)
 
 
 def plane_wave(n_lattice: int, box: float, amp: float, m_wave: int,
@@ -133,7 +133,7 @@ def plane_wave(n_lattice: int, box: float, amp: float, m_wave: int,
     pos[:, 0] += s
     vel = np.zeros_like(q)
     vel[:, 0] = haf * s
-    return _wrap32(pos, box), vel.astype(np.float32)
+    return _wrap32(pos, box), np.ascontiguousarray(vel, dtype=np.float32)
 
 
 def bulk_vector(speed: float, direction=(1.0, 2.0, 2.0)):
