@@ -102,6 +102,90 @@ def cpu_baseline():
                        f"bincount assignment is single-threaded, scipy FFTs use all cores")}
 
 
+def serving(args):
+    """Poisson request stream through the continuous-batching server.
+
+    Requests arrive at mean rate --rate for --duration seconds; each draws a
+    grid from {128, 256, 512, 1024}^3 and a catalog from a device-resident
+    pool whose particle counts are log-spaced over [1e6, 5e8] (Zel'dovich
+    lattices up to 392^3, uniform catalogs with Gaussian velocities above,
+    generated on the device).  Latency is submit -> result on the host.
+    """
+    import threading
+
+    import torch
+    import paper_2005_06170_amd as mps
+    from synth import catalogs
+
+    rng = np.random.default_rng(catalogs.seed_for(5))
+    sizes = [10 ** 6, 3 * 10 ** 6, 10 ** 7, 3 * 10 ** 7, 6 * 10 ** 7, 134217728, 2.5e8, 5e8]
+    pool = []
+    for i, n in enumerate(sizes):
+        n = int(n)
+        if i % 2 == 0 and n <= 6 * 10 ** 7:
+            nl = int(round(n ** (1.0 / 3.0)))
+            pos, vel = catalogs.zeldovich(nl, BOX, 3.0, haf=HAF, seed=catalogs.seed_for(5, i))
+            p, v = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
+        else:
+            g = torch.Generator(device="cuda").manual_seed(catalogs.seed_for(5, i))
+            p = torch.rand((n, 3), generator=g, device="cuda") * BOX
+            v = torch.randn((n, 3), generator=g, device="cuda") * 300.0
+        pool.append((p.contiguous(), v.contiguous()))
+        _log(f"pool catalog {i}: {p.shape[0]} particles")
+    grids = [128, 256, 512, 1024]
+    n_req = int(args.rate * args.duration)
+    gaps = rng.exponential(1.0 / args.rate, n_req)
+    picks = [(int(rng.integers(len(pool))), grids[int(rng.integers(len(grids)))]) for _ in range(n_req)]
+    out = {}
+    for prec in (["f32", "f64"] if not args.no_fp64 else ["f32"]):
+        srv = mps.Server(hbm_budget_bytes=int(args.budget_gb * 2 ** 30), max_inflight=args.inflight,
+                         small_particles=4_000_000)
+        # warm the plan pool with one request per grid size
+        for g in grids:
+            srv.wait(srv.submit(*pool[0], box=BOX, haf=HAF, n_grid=g, precision=prec), 600.0)
+        lat = [None] * n_req
+        done_t = [None] * n_req
+        tickets = [None] * n_req
+        t_sub = [None] * n_req
+        ready = threading.Semaphore(0)
+
+        def collect():
+            for j in range(n_req):
+                ready.acquire()
+                srv.wait(tickets[j], 600.0)
+                done_t[j] = time.perf_counter()
+                lat[j] = done_t[j] - t_sub[j]
+                if j % 100 == 0:
+                    _log(f"{prec}: {j}/{n_req} done")
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        nxt = t0
+        for j, (ci, g) in enumerate(picks):
+            nxt += gaps[j]
+            d = nxt - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            t_sub[j] = time.perf_counter()
+            tickets[j] = srv.submit(*pool[ci], box=BOX, haf=HAF, n_grid=g, precision=prec)
+            ready.release()
+        th.join()
+        elapsed = max(done_t) - t0
+        srv.close()
+        lat_ms = np.array(lat) * 1e3
+        out[prec] = {"catalogs_per_s": n_req / elapsed, "p50_ms": float(np.percentile(lat_ms, 50)),
+                     "p99_ms": float(np.percentile(lat_ms, 99)), "requests": n_req,
+                     "offered_rate": args.rate, "elapsed_s": elapsed}
+        _log(f"{prec}: {out[prec]}")
+    line = {"metric": "serving: catalogs/s and p50/p99 latency, Poisson arrivals", "value": out["f32"]["catalogs_per_s"],
+            "unit": "catalogs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "poisson_stream_grids_128-1024_particles_1e6-5e8", "rate": args.rate,
+                       "duration_s": args.duration, "inflight": args.inflight, "budget_gb": args.budget_gb},
+            "f32": out["f32"], "fp64": out.get("f64")}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +195,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--shuffle", action="store_true",
                     help="permute particle order randomly (no spatial coherence)")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the Poisson serving stream instead of the 512^3 benchmark")
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--duration", type=float, default=30.0)
+    ap.add_argument("--inflight", type=int, default=3)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, copy 1 GiB device-to-device once (calibrates HBM counters)")
     args = ap.parse_args()
@@ -118,6 +208,9 @@ def main():
         print("bench.py measures one GPU only: the estimator's catalogs are independent and "
               "multi-GPU runs are not part of this build (see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        serving(args)
+        return
 
     import torch
     import paper_2005_06170_amd as mps

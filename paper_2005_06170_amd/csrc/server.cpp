@@ -76,34 +76,62 @@ struct Server {
 
 namespace {
 
-// Find an idle pooled plan of this shape with capacity for np particles, or
-// make room (evicting idle plans, LRU) and create one.  Called with mu held;
-// returns nullptr if the budget cannot host it right now.
+// Evict idle plans (least recently used first, never `keep`) until `need`
+// more bytes fit the budget.  Returns false if running requests hold too much.
+bool make_room(Server* s, size_t need, const PooledPlan* keep) {
+  while (s->used + need > s->budget) {
+    auto victim = s->pool.end();
+    for (auto it = s->pool.begin(); it != s->pool.end(); ++it)
+      if (!it->busy && &*it != keep && (victim == s->pool.end() || it->last_use < victim->last_use)) victim = it;
+    if (victim == s->pool.end()) return false;
+    mps_plan_destroy(victim->plan);
+    s->used -= victim->bytes;
+    s->pool.erase(victim);
+  }
+  return true;
+}
+
+// An idle pooled plan of this shape with room for np particles: reuse one
+// that is large enough, else grow the largest idle one of the shape, else
+// create one.  Called with mu held; returns nullptr if the budget cannot host
+// it right now (*status stays MPS_OK) or never can / creation failed.
 PooledPlan* acquire_plan(Server* s, int n_grid, mps_precision prec, int64_t np, int* status) {
   *status = MPS_OK;
-  PooledPlan* best = nullptr;
-  for (auto& pp : s->pool)
-    if (!pp.busy && pp.n_grid == n_grid && pp.prec == prec && pp.cap >= np)
-      if (!best || pp.cap < best->cap) best = &pp;
-  if (best) {
-    best->busy = true;
-    best->last_use = ++s->clock;
-    return best;
-  }
   const size_t need = mps_footprint(n_grid, prec, np);
   if (need > s->budget) {
     *status = MPS_E_TOOBIG;
     return nullptr;
   }
-  while (s->used + need > s->budget) {
-    auto victim = s->pool.end();
-    for (auto it = s->pool.begin(); it != s->pool.end(); ++it)
-      if (!it->busy && (victim == s->pool.end() || it->last_use < victim->last_use)) victim = it;
-    if (victim == s->pool.end()) return nullptr;  // wait for a running request
-    mps_plan_destroy(victim->plan);
-    s->used -= victim->bytes;
-    s->pool.erase(victim);
+  PooledPlan* fit = nullptr;
+  PooledPlan* grow = nullptr;
+  for (auto& pp : s->pool) {
+    if (pp.busy || pp.n_grid != n_grid || pp.prec != prec) continue;
+    if (pp.cap >= np) {
+      if (!fit || pp.cap < fit->cap) fit = &pp;
+    } else if (!grow || pp.cap > grow->cap) {
+      grow = &pp;
+    }
   }
+  if (fit) {
+    fit->busy = true;
+    fit->last_use = ++s->clock;
+    return fit;
+  }
+  if (grow) {
+    if (!make_room(s, need - grow->bytes, grow)) return nullptr;
+    const int st = mps_plan_reserve(grow->plan, np);
+    if (st != MPS_OK) {
+      *status = st;
+      return nullptr;
+    }
+    s->used += need - grow->bytes;
+    grow->bytes = need;
+    grow->cap = np;
+    grow->busy = true;
+    grow->last_use = ++s->clock;
+    return grow;
+  }
+  if (!make_room(s, need, nullptr)) return nullptr;
   mps_plan* plan = nullptr;
   int st = mps_plan_create(&plan, n_grid, prec);
   if (st == MPS_OK) st = mps_plan_reserve(plan, np);
