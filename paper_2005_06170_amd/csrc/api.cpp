@@ -52,6 +52,7 @@ void release(Plan* p) {
   dfree(p->tile_count);
   dfree(p->tile_offset);
   dfree(p->tile_cursor);
+  dfree(p->tile_queue);
   dfree(p->moment_partials);
   dfree(p->d_header);
   dfree(p->d_win2);
@@ -216,13 +217,15 @@ int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec) {
   const int half = n_grid / 2;
   const int items = x_bin_items(n_grid, prec);
   const int cus = num_cus();
+  p->num_cus = cus;
   p->bin_blocks = items < cus ? items : cus;
   bool ok = true;
   ok = ok && dalloc(&p->grid, static_cast<size_t>(kNumFields) * n3 * p->real_size) == hipSuccess;
   ok = ok && dalloc(&p->tile_count, sizeof(uint32_t) * p->n_tiles) == hipSuccess;
   ok = ok && dalloc(&p->tile_offset, sizeof(uint32_t) * (p->n_tiles + 1)) == hipSuccess;
   ok = ok && dalloc(&p->tile_cursor, sizeof(uint32_t) * p->n_tiles) == hipSuccess;
-  ok = ok && dalloc(&p->moment_partials, sizeof(double) * kMomentBlocks * kMomentSums) == hipSuccess;
+  ok = ok && dalloc(&p->tile_queue, sizeof(uint32_t) * 8) == hipSuccess;
+  ok = ok && dalloc(&p->moment_partials, sizeof(double) * kMomentBlocks * (kMomentSums + kMomentMax)) == hipSuccess;
   ok = ok && dalloc(&p->d_header, sizeof(ResultHeader)) == hipSuccess;
   ok = ok && dalloc(&p->d_win2, sizeof(double) * (half + 1)) == hipSuccess;
   ok = ok && dalloc(&p->d_alias, sizeof(double) * (half + 1)) == hipSuccess;
@@ -238,6 +241,7 @@ int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec) {
     return MPS_E_NOMEM;
   }
   p->taps = bl3_tap_polynomials();
+  p->tap_bound = bl3_tap_bounds(p->taps);
   std::vector<double> win2, alias;
   bl3_axis_tables(n_grid, &win2, &alias);
   const std::vector<double> tw = twiddles(n_grid);
@@ -280,7 +284,7 @@ size_t mps_footprint(int n_grid, mps_precision prec, int64_t n_particles) {
   b += sizeof(uint32_t) * (3 * tiles + 1);                           // tile tables
   b += sizeof(int32_t) * half * half;                                // bin LUT
   b += sizeof(double) * (static_cast<size_t>(256) + 1) * kMaxBins * kNumQ;
-  b += sizeof(double) * (kMomentBlocks * kMomentSums + 2 * (half + 1)) + 2 * rs * n_grid + sizeof(ResultHeader);
+  b += sizeof(double) * (kMomentBlocks * (kMomentSums + kMomentMax) + 2 * (half + 1)) + 2 * rs * n_grid + sizeof(ResultHeader);
   return b;
 }
 

@@ -16,6 +16,7 @@ constexpr int kTapLo = -2;
 constexpr int kNumQ = 9;          // per-bin accumulators (see BinQ)
 constexpr int kMaxBins = MPS_MAX_BINS;
 constexpr int kMomentSums = 14;   // W, W2, sum w v (3), sum w^2 v (3), sum w^2 v v^T (6)
+constexpr int kMomentMax = 4;     // max |w|, max |w v_a| (a = x, y, z)
 constexpr int kNumStages = 9;
 
 // Per-bin accumulators, in order.
@@ -27,6 +28,11 @@ struct TapPoly {
   double c[kTaps][4];
 };
 
+// Upper bounds of |w_j(f)| over f in [0, 1) for the six taps.
+struct TapBound {
+  float k[kTaps];
+};
+
 // Scalars derived on the device from the moment sums (FP64).
 struct Derived {
   double W, W2;
@@ -36,6 +42,7 @@ struct Derived {
   double s_pp;           // trace S
   double inv_W;          // 1 / W
   double sigma_v2;       // trace(sum w^2 v v^T) / W2 of the velocities used
+  double qmax[kNumFields];  // max |w|, max |w v_a| over the catalog
   int bulk;              // 1 if p is replaced by p - v_b delta
 };
 
@@ -52,6 +59,8 @@ struct Plan;
 // ----------------------------------------------------------------- tables
 // Host-side FP64 construction of the truncated cubic Battle-Lemarie kernel.
 TapPoly bl3_tap_polynomials();
+// Bounds of |w_j| on [0, 1] (ends and stationary points), with a small margin.
+TapBound bl3_tap_bounds(const TapPoly& tp);
 // W_t(2 pi n / N)^2 and C_t(2 pi n / N) for n = 0..N/2.
 void bl3_axis_tables(int n_grid, std::vector<double>* win2, std::vector<double>* alias);
 // e^{-2 pi i m / N}, m = 0..N-1, interleaved (re, im).
@@ -75,7 +84,9 @@ struct Plan {
   uint32_t* tile_count = nullptr;    // n_tiles
   uint32_t* tile_offset = nullptr;   // n_tiles + 1
   uint32_t* tile_cursor = nullptr;   // n_tiles
-  double* moment_partials = nullptr; // kMomentBlocks x kMomentSums
+  uint32_t* tile_queue = nullptr;    // 8 work-queue counters of the scatter
+  int num_cus = 256;
+  double* moment_partials = nullptr; // kMomentBlocks x (kMomentSums + kMomentMax)
   ResultHeader* d_header = nullptr;
   double* d_win2 = nullptr;          // N/2 + 1
   double* d_alias = nullptr;         // N/2 + 1
@@ -96,6 +107,7 @@ struct Plan {
   std::vector<double> edges_used;    // n_bins + 1 edges actually used
 
   TapPoly taps;
+  TapBound tap_bound;
 
   // stage timing
   bool timing = false;

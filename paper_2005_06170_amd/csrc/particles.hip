@@ -86,6 +86,7 @@ __global__ __launch_bounds__(kCountThreads) void count_kernel(
   double acc[kMomentSums];
 #pragma unroll
   for (int q = 0; q < kMomentSums; ++q) acc[q] = 0.0;
+  double mx[kMomentMax] = {0.0, 0.0, 0.0, 0.0};
   bool bad = false;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kCountThreads;
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * kCountThreads; base < np; base += stride) {
@@ -114,21 +115,36 @@ __global__ __launch_bounds__(kCountThreads) void count_kernel(
       acc[11] += w2 * vx * vy;
       acc[12] += w2 * vx * vz;
       acc[13] += w2 * vy * vz;
+      mx[0] = fmax(mx[0], fabs(w));
+      mx[1] = fmax(mx[1], fabs(w * vx));
+      mx[2] = fmax(mx[2], fabs(w * vy));
+      mx[3] = fmax(mx[3], fabs(w * vz));
     }
     wave_run_atomic(key, valid, tile_count);
   }
-  __shared__ double red[kCountThreads / 64][kMomentSums];
+  __shared__ double red[kCountThreads / 64][kMomentSums + kMomentMax];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int q = 0; q < kMomentSums; ++q) {
     const double s = wave_sum(acc[q]);
     if (lane == 0) red[wave][q] = s;
   }
+#pragma unroll
+  for (int q = 0; q < kMomentMax; ++q) {
+    double m = mx[q];
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (lane == 0) red[wave][kMomentSums + q] = m;
+  }
   __syncthreads();
   if (threadIdx.x < kMomentSums) {
     double s = 0.0;
     for (int w = 0; w < kCountThreads / 64; ++w) s += red[w][threadIdx.x];
     partials[blockIdx.x * kMomentSums + threadIdx.x] = s;
+  } else if (threadIdx.x < kMomentSums + kMomentMax) {
+    const int q = threadIdx.x - kMomentSums;
+    double m = 0.0;
+    for (int w = 0; w < kCountThreads / 64; ++w) m = fmax(m, red[w][threadIdx.x]);
+    partials[kMomentBlocks * kMomentSums + blockIdx.x * kMomentMax + q] = m;
   }
   if (bad) atomicOr(&hdr->flags, 1u);
 }
@@ -138,11 +154,17 @@ __global__ __launch_bounds__(kCountThreads) void count_kernel(
 __global__ __launch_bounds__(64) void derive_kernel(const double* __restrict__ partials, int nblocks,
                                                     ResultHeader* hdr, int bulk) {
   __shared__ double sums[kMomentSums];
+  __shared__ double maxes[kMomentMax];
   if (threadIdx.x < kMomentSums) {
     double s = 0.0;
     for (int b = 0; b < nblocks; ++b) s += partials[b * kMomentSums + threadIdx.x];
     sums[threadIdx.x] = s;
     hdr->sums[threadIdx.x] = s;
+  } else if (threadIdx.x < kMomentSums + kMomentMax) {
+    const int q = threadIdx.x - kMomentSums;
+    double m = 0.0;
+    for (int b = 0; b < nblocks; ++b) m = fmax(m, partials[nblocks * kMomentSums + b * kMomentMax + q]);
+    maxes[q] = m;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -168,6 +190,7 @@ __global__ __launch_bounds__(64) void derive_kernel(const double* __restrict__ p
   d.s_pp = d.S[0] + d.S[1] + d.S[2];
   d.inv_W = iw;
   d.sigma_v2 = (m2[0] + m2[1] + m2[2]) / d.W2;
+  for (int q = 0; q < kMomentMax; ++q) d.qmax[q] = maxes[q];
   d.bulk = bulk;
   hdr->d = d;
 }
@@ -236,10 +259,6 @@ __device__ __forceinline__ double tap_weight(const TapPoly& tp, int j, double f)
   return ((tp.c[j][3] * f + tp.c[j][2]) * f + tp.c[j][1]) * f + tp.c[j][0];
 }
 
-// Largest |phi_t(x) phi_t(y) phi_t(z)| over the truncated kernel: phi(0)^3
-// = 1.0890^3 = 1.2916, rounded up.
-constexpr double kPhiMax = 1.3;
-
 template <typename T>
 struct DepositQ {
   T q[kNumFields];
@@ -296,34 +315,50 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t b, int64_t xcd_chunk) {
   return xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
 }
 
-// Rounds wxy * qs to the nearest integer in two instructions: for
-// |x| < 2^22, x + 1.5 * 2^23 is an integer-valued float whose bit pattern
-// minus that of 1.5 * 2^23 is round(x).
-constexpr float kMagic = 12582912.0f;      // 1.5 * 2^23
-constexpr int kMagicBits = 0x4B400000;
+// Nearest integer of an FP32 value with |x| < 2^31 in one instruction:
+// v_cvt_rpi_i32_f32 returns floor(x + 0.5).
+__device__ __forceinline__ int round_to_int(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
 
-// Lane assignment that spreads a wave over the LDS banks.  Each chunk of NT
-// particles is counting-sorted by (LDS word index mod 64) of its tap origin;
-// lane l of wave w then takes bank-sorted position l * W + w, W = the number
-// of waves the chunk fills, so the 64 lanes of a wave come from 64
-// consecutive bank segments: about one lane per bank (two on a 32-bank LDS)
-// and never two lanes on one address.
-template <int NT>
+// LDS word index of a particle's tap origin (cell relative to the tile
+// origin, halo offset included) without the tap weights.
+template <int TS>
+__device__ __forceinline__ unsigned tap_origin(const float4& a, const KeyParams& kp, int ox, int oy, int oz) {
+  constexpr int E = TS + 5;
+  double f;
+  bool ok;
+  int cx = locate(a.x, kp.scale, kp.n, &f, &ok) - ox;
+  int cy = locate(a.y, kp.scale, kp.n, &f, &ok) - oy;
+  int cz = locate(a.z, kp.scale, kp.n, &f, &ok) - oz;
+  cx = min(max(cx, 0), TS - 1);
+  cy = min(max(cy, 0), TS - 1);
+  cz = min(max(cz, 0), TS - 1);
+  return static_cast<unsigned>((cx * E + cy) * E + cz);
+}
+
+// Lane assignment that spreads a wave over the LDS banks.  A super-chunk of
+// up to kPer * NT particles is counting-sorted by the LDS bank of its tap
+// origin (word index mod 64; for doubles, index mod 32); with W = ceil(m/64)
+// wave slots, lane l of slot s takes bank-sorted position l * W + s, so the
+// 64 lanes of a wave come from 64 consecutive bank segments: about one lane
+// per bank (two on a 32-bank LDS) and never two lanes on one address.
+template <int NT, int kPer>
 struct BankSort {
   int cnt[64];
-  unsigned short idx[NT];
+  unsigned short idx[NT * kPer];
 };
 
-template <int NT>
-__device__ __forceinline__ int bank_sorted_index(BankSort<NT>& bs, bool valid, unsigned bank, int m) {
+// Phase 1: each thread registers up to kPer particles (local indices
+// t + r NT) with their bank; returns per-particle slots within their bank.
+// Phase 2 (bank_place): after the scan, write the sorted index array.
+template <int NT, int kPer>
+__device__ __forceinline__ void bank_scan(BankSort<NT, kPer>& bs) {
   const int t = threadIdx.x;
-  if (t < 64) bs.cnt[t] = 0;
-  __syncthreads();
-  int slot = 0;
-  if (valid) slot = atomicAdd(&bs.cnt[bank], 1);
-  __syncthreads();
   if (t < 64) {  // exclusive scan of 64 counters in one wave
-    int v = bs.cnt[t];
+    const int v = bs.cnt[t];
     int incl = v;
     for (int off = 1; off < 64; off <<= 1) {
       const int o = __shfl_up(incl, off);
@@ -331,214 +366,389 @@ __device__ __forceinline__ int bank_sorted_index(BankSort<NT>& bs, bool valid, u
     }
     bs.cnt[t] = incl - v;
   }
-  __syncthreads();
-  if (valid) bs.idx[bs.cnt[bank] + slot] = static_cast<unsigned short>(t);
-  __syncthreads();
-  // a partial chunk (m < NT) occupies only ceil(m / 64) full waves
-  const int waves = (m + 63) >> 6;
-  const int w = t >> 6;
-  const int q = (t & 63) * waves + w;
-  return (w < waves && q < m) ? bs.idx[q] : -1;
 }
 
-// FP32 grids.  One workgroup per occupied tile.  LDS holds the four fields
-// over the tile plus a halo of 2 cells below and 3 above along each axis
-// (taps -2..3) as 32-bit fixed point: gfx950's LDS adds integers at ~14
-// lanes/clk/CU but FP32 at ~0.3.  Each field's scale is chosen per tile so
-// that no cell total can leave int32 (|cell| <= kPhiMax sum_tile |q|; the
-// final value is exact modulo 2^32 whatever the order of the adds) and no
-// single deposit reaches 2^22 (the rounding above).
+// Work queues of the persistent scatter: 8 (one per XCD, each over a
+// contiguous range of tiles, so that halo lines shared by neighbouring tiles
+// stay in one L2) or 1.  A block takes tiles from its own queue, then from
+// the others.  Block 0..G-1 runs on XCD (b mod 8): workgroups are dealt to the
+// XCDs round robin.
+struct TileQueues {
+  uint32_t* counter;  // nq counters, zeroed before the launch
+  int nq;
+  int64_t per_queue;
+};
+
+template <int NT>
+__device__ __forceinline__ int64_t next_tile(const TileQueues& tq, int64_t n_tiles, long long* s_tile) {
+  if (threadIdx.x == 0) {
+    long long got = -1;
+    const int mine = static_cast<int>(blockIdx.x % tq.nq);
+    for (int k = 0; k < tq.nq && got < 0; ++k) {
+      const int q = (mine + k) % tq.nq;
+      const uint32_t i = atomicAdd(tq.counter + q, 1u);
+      const int64_t tl = q * tq.per_queue + static_cast<int64_t>(i);
+      if (static_cast<int64_t>(i) < tq.per_queue && tl < n_tiles) got = tl;
+    }
+    *s_tile = got;
+  }
+  __syncthreads();
+  const int64_t v = *s_tile;
+  __syncthreads();
+  // uniform: keep the tile index and everything derived from it in SGPRs
+  const uint64_t u = static_cast<uint64_t>(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// One line of the separable bound convolution: out[g] = sum_j k_j in[g - j]
+// over taps j = -2..3, with in = 0 outside the E-long line.
+template <int E>
+__device__ __forceinline__ void bound_line(const float (&in)[E], const TapBound& kb, float (&out)[E]) {
+#pragma unroll
+  for (int g = 0; g < E; ++g) {
+    float o = 0.f;
+#pragma unroll
+    for (int j = -2; j <= 3; ++j)
+      if (g - j >= 0 && g - j < E) o = fmaf(kb.k[j + 2], in[g - j], o);
+    out[g] = o;
+  }
+}
+
+// FP32 grids.  A persistent grid of one workgroup per CU walks the occupied
+// T^3 tiles.  LDS holds the four fields over the tile plus a halo of 2 cells
+// below and 3 above along each axis (taps -2..3) as 32-bit fixed point:
+// gfx950's LDS adds integers at ~14 lanes/clk/CU but FP32 at ~0.3.
+//
+// Sums of fixed-point deposits are exact modulo 2^32 in any order, so only
+// the final value of each cell has to fit int32.  Per tile and field the
+// scale comes from a bound on that value: every cell c of the tile gets
+// C(c) = sum of |q| over the tile's particles in c (upper-rounded integer
+// adds); then A(g) = sum_j C(g - j) k_j, convolved along x, y and z with
+// k_j >= |w_j(f)| for all f, bounds sum_p |q_p phi(g - x_p)| at every cell g
+// of the tile and halo.  The scale maps max_g A(g) to just under 2^31, less
+// the worst-case sum of the per-deposit rounding errors (half a unit per
+// particle).  A single pass over LDS gives both the bound and the zeroed
+// accumulator.
 template <int TS, int NT>
 __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, float* __restrict__ grid,
-    KeyParams kp, int64_t n_tiles, int64_t xcd_chunk, TapPoly tp, const Derived* dsrc, int bulk) {
+    KeyParams kp, int64_t n_tiles, TileQueues tq, TapPoly tp, TapBound kb, const Derived* dsrc, int bulk) {
   constexpr int E = TS + 5;
   constexpr int VOL = E * E * E;
+  constexpr int kPer = 6;
+  constexpr int kSuper = kPer * NT;
+  constexpr int kWaves = NT / 64;
+  constexpr int kCellOff = (2 * E + 2) * E + 2;  // tap origin -> the particle's own cell
   __shared__ int acc[kNumFields * VOL];
-  __shared__ BankSort<NT> bs;
-  __shared__ double red[NT / 64][2 * kNumFields];
+  __shared__ BankSort<NT, kPer> bs;
+  __shared__ float red[kWaves][kNumFields];
   __shared__ float scale_s[kNumFields], inv_s[kNumFields];
-  const int64_t tile = tile_of_block(blockIdx.x, xcd_chunk);
-  if (tile >= n_tiles) return;
-  const uint32_t p0 = offset[tile], p1 = offset[tile + 1];
-  if (p0 == p1) return;
+  __shared__ long long s_tile;
   double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
   if (bulk) {
     vb0 = dsrc->vb[0];
     vb1 = dsrc->vb[1];
     vb2 = dsrc->vb[2];
   }
-  // pass 1: per-field sum and max of |q| over the tile's particles (FP64)
-  double sq[kNumFields] = {0.0, 0.0, 0.0, 0.0}, mq[kNumFields] = {0.0, 0.0, 0.0, 0.0};
-  for (uint32_t p = p0 + threadIdx.x; p < p1; p += NT) {
-    const DepositQ<double> d =
-        charges<double>(sorted[2 * static_cast<int64_t>(p)], sorted[2 * static_cast<int64_t>(p) + 1], bulk,
-                        vb0, vb1, vb2);
-#pragma unroll
-    for (int f = 0; f < kNumFields; ++f) {
-      sq[f] += fabs(d.q[f]);
-      mq[f] = fmax(mq[f], fabs(d.q[f]));
-    }
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int f = 0; f < kNumFields; ++f) {
-    double t = wave_sum(sq[f]);
-    double m = mq[f];
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-    if (lane == 0) {
-      red[wave][f] = t;
-      red[wave][kNumFields + f] = m;
-    }
-  }
-  for (int i = threadIdx.x; i < kNumFields * VOL; i += NT) acc[i] = 0;
-  __syncthreads();
-  if (threadIdx.x < kNumFields) {
-    double b = 0.0, m = 0.0;
-    for (int w = 0; w < NT / 64; ++w) {
-      b += red[w][threadIdx.x];
-      m = fmax(m, red[w][kNumFields + threadIdx.x]);
-    }
-    const double by_sum = b > 0.0 ? 0.98 * 2147483648.0 / (kPhiMax * 1.0001 * b) : 0.0;
-    const double by_max = m > 0.0 ? 0.99 * 4194304.0 / (kPhiMax * m) : 0.0;
-    const double sc = fmin(by_sum, by_max);
-    scale_s[threadIdx.x] = static_cast<float>(sc);
-    inv_s[threadIdx.x] = sc > 0.0 ? static_cast<float>(1.0 / static_cast<double>(static_cast<float>(sc))) : 0.f;
-  }
-  __syncthreads();
-  float sc[kNumFields];
-#pragma unroll
-  for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
+  // catalog-wide bound of |q| per field for the charges deposited here
+  double qmax[kNumFields];
+  qmax[0] = dsrc->qmax[0];
+  qmax[1] = dsrc->qmax[1] + (bulk ? dsrc->qmax[0] * fabs(vb0) : 0.0);
+  qmax[2] = dsrc->qmax[2] + (bulk ? dsrc->qmax[0] * fabs(vb1) : 0.0);
+  qmax[3] = dsrc->qmax[3] + (bulk ? dsrc->qmax[0] * fabs(vb2) : 0.0);
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
   const int nt = kp.nt;
-  const int tz = static_cast<int>(tile % nt);
-  const int ty = static_cast<int>((tile / nt) % nt);
-  const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
-  const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
-  // pass 2: deposit, chunk by chunk in bank-sorted lane order
-  for (uint32_t c0 = p0; c0 < p1; c0 += NT) {
-    const int m = static_cast<int>(min(static_cast<uint32_t>(NT), p1 - c0));
-    const bool mine = static_cast<int>(threadIdx.x) < m;
-    unsigned bank = 0;
-    if (mine) {
-      float wx[kTaps], wy[kTaps], wz[kTaps];
-      bank = particle_taps<float, TS>(sorted[2 * static_cast<int64_t>(c0 + threadIdx.x)], kp, ox, oy, oz, tp, wx,
-                                      wy, wz) & 63u;
-    }
-    const int j = bank_sorted_index<NT>(bs, mine, bank, m);
-    if (j < 0) continue;
-    const uint32_t p = c0 + static_cast<uint32_t>(j);
-    const float4 a = sorted[2 * static_cast<int64_t>(p)];
-    const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
-    float wx[kTaps], wy[kTaps], wz[kTaps];
-    const unsigned base = particle_taps<float, TS>(a, kp, ox, oy, oz, tp, wx, wy, wz);
-    const DepositQ<float> d = charges<float>(a, v, bulk, vb0, vb1, vb2);
-    float qs[kNumFields][kTaps];
-#pragma unroll
-    for (int f = 0; f < kNumFields; ++f)
-#pragma unroll
-      for (int jj = 0; jj < kTaps; ++jj) qs[f][jj] = d.q[f] * sc[f] * wz[jj];
-    int* accf[kNumFields] = {acc + base, acc + VOL + base, acc + 2 * VOL + base, acc + 3 * VOL + base};
-#pragma unroll
-    for (int jx = 0; jx < kTaps; ++jx) {
-#pragma unroll
-      for (int jy = 0; jy < kTaps; ++jy) {
-        const float wxy = wx[jx] * wy[jy];
-#pragma unroll
-        for (int f = 0; f < kNumFields; ++f)
-#pragma unroll
-          for (int jz = 0; jz < kTaps; ++jz)
-            atomicAdd(accf[f] + (jx * E + jy) * E + jz,
-                      __float_as_int(fmaf(wxy, qs[f][jz], kMagic)) - kMagicBits);
-      }
-    }
-  }
-  __syncthreads();
   const int n = kp.n;
   const int64_t n3 = static_cast<int64_t>(n) * n * n;
-  float inv[kNumFields];
+  unsigned* cnt_u = reinterpret_cast<unsigned*>(acc);
+
+  int64_t tile = next_tile<NT>(tq, n_tiles, &s_tile);
+  for (int i = t; i < kNumFields * VOL; i += NT) acc[i] = 0;
+  if (t < 64) bs.cnt[t] = 0;
+  __syncthreads();
+
+  while (tile >= 0) {
+    const uint32_t p0 = offset[tile], p1 = offset[tile + 1];
+    const uint32_t cnt = p1 - p0;
+    const int tz = static_cast<int>(tile % nt);
+    const int ty = static_cast<int>((tile / nt) % nt);
+    const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
+    const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
+    // integer scale of the cell sums C: n_tile * qmax maps just under 2^32,
+    // and upper rounding adds at most one unit per particle
+    float csc[kNumFields];
 #pragma unroll
-  for (int f = 0; f < kNumFields; ++f) inv[f] = inv_s[f];
-  for (int i = threadIdx.x; i < VOL; i += NT) {
-    const int ez = i % E, ey = (i / E) % E, ex = i / (E * E);
-    const int gx = (ox + ex - 2) & (n - 1);
-    const int gy = (oy + ey - 2) & (n - 1);
-    const int gz = (oz + ez - 2) & (n - 1);
-    const int64_t gi = (static_cast<int64_t>(gx) * n + gy) * n + gz;
+    for (int f = 0; f < kNumFields; ++f)
+      csc[f] = (qmax[f] > 0.0 && cnt > 0)
+                   ? static_cast<float>((4294967295.0 - cnt) * (1.0 - 1e-6) / (static_cast<double>(cnt) * qmax[f]))
+                   : 0.f;
+    auto add_cell_sums = [&](const float4& a, const float4& v, unsigned cell) {
+      const DepositQ<float> d = charges<float>(a, v, bulk, vb0, vb1, vb2);
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) {
+        const unsigned u = static_cast<unsigned>(ceilf(fabsf(d.q[f]) * csc[f]));
+        if (u) atomicAdd(cnt_u + f * VOL + cell, u);
+      }
+    };
+    // first super-chunk: bank keys (the counters were zeroed before the
+    // previous flush) and cell sums; then the cell sums of the rest
+    const int m0 = static_cast<int>(min(static_cast<uint32_t>(kSuper), cnt));
+    unsigned key0[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      key0[r] = 0;
+      if (t + r * NT < m0) {
+        const int64_t p = static_cast<int64_t>(p0) + t + r * NT;
+        const float4 a = sorted[2 * p];
+        const unsigned base = tap_origin<TS>(a, kp, ox, oy, oz);
+        const unsigned b = base & 63u;
+        key0[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
+        add_cell_sums(a, sorted[2 * p + 1], base + kCellOff);
+      }
+    }
+    for (uint32_t p = p0 + static_cast<uint32_t>(m0) + t; p < p1; p += NT) {
+      const float4 a = sorted[2 * static_cast<int64_t>(p)];
+      add_cell_sums(a, sorted[2 * static_cast<int64_t>(p) + 1], tap_origin<TS>(a, kp, ox, oy, oz) + kCellOff);
+    }
+    __syncthreads();
+    // bound convolution along z (lines of the tile's interior x, y), then y
+    // (interior x), as floats in place
+    for (int rr = t; rr < kNumFields * TS * TS; rr += NT) {
+      const int f = rr / (TS * TS);
+      const int x = 2 + (rr / TS) % TS, y = 2 + rr % TS;
+      int* line = acc + f * VOL + (x * E + y) * E;
+      float in[E], out[E];
+#pragma unroll
+      for (int g = 0; g < E; ++g) in[g] = static_cast<float>(static_cast<unsigned>(line[g]));
+      bound_line<E>(in, kb, out);
+#pragma unroll
+      for (int g = 0; g < E; ++g) line[g] = __float_as_int(out[g]);
+    }
+    __syncthreads();
+    for (int rr = t; rr < kNumFields * TS * E; rr += NT) {
+      const int f = rr / (TS * E);
+      const int x = 2 + (rr / E) % TS, z = rr % E;
+      int* line = acc + f * VOL + x * E * E + z;
+      float in[E], out[E];
+#pragma unroll
+      for (int g = 0; g < E; ++g) in[g] = __int_as_float(line[g * E]);
+      bound_line<E>(in, kb, out);
+#pragma unroll
+      for (int g = 0; g < E; ++g) line[g * E] = __float_as_int(out[g]);
+    }
+    __syncthreads();
+    // along x: the maximum only; the lines are cleared for the deposits
+    float amax[kNumFields] = {0.f, 0.f, 0.f, 0.f};
+    for (int rr = t; rr < kNumFields * E * E; rr += NT) {
+      const int f = rr / (E * E);
+      int* line = acc + f * VOL + rr % (E * E);
+      float in[E], out[E];
+#pragma unroll
+      for (int g = 0; g < E; ++g) {
+        in[g] = __int_as_float(line[g * E * E]);
+        line[g * E * E] = 0;
+      }
+      bound_line<E>(in, kb, out);
+      float m = 0.f;
+#pragma unroll
+      for (int g = 0; g < E; ++g) m = fmaxf(m, out[g]);
+#pragma unroll
+      for (int ff = 0; ff < kNumFields; ++ff)
+        if (ff == f) amax[ff] = fmaxf(amax[ff], m);
+    }
 #pragma unroll
     for (int f = 0; f < kNumFields; ++f) {
-      const int val = acc[f * VOL + i];
-      if (val != 0) atomicAdd(grid + f * n3 + gi, static_cast<float>(val) * inv[f]);
+      float m = amax[f];
+      for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+      if (lane == 0) red[wave][f] = m;
     }
+    // One super-chunk: scan the bank counters, place local indices in bank
+    // order, deposit.  key[r] = bank | slot << 6 of local particle t + r NT.
+    auto deposit_chunk = [&](uint32_t c0, int m, const unsigned (&key)[kPer], bool first) {
+      __syncthreads();
+      if (first && t < kNumFields) {
+        float mx = 0.f;
+        for (int w = 0; w < kWaves; ++w) mx = fmaxf(mx, red[w][t]);
+        // A in charge units (with a margin for the FP32 convolution); room
+        // for the rounding errors of up to cnt deposits per cell
+        const double bound = static_cast<double>(mx) * 1.00001 / static_cast<double>(csc[t]);
+        const double room = 0.99 * 2147483648.0 - 0.5 * static_cast<double>(cnt) - 64.0;
+        const double scl = (mx > 0.f && csc[t] > 0.f) ? fmin(room / bound, 1e30) : 0.0;
+        scale_s[t] = static_cast<float>(scl);
+        inv_s[t] = scl > 0.0 ? static_cast<float>(1.0 / static_cast<double>(static_cast<float>(scl))) : 0.f;
+      }
+      bank_scan<NT, kPer>(bs);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        const int i = t + r * NT;
+        if (i < m) bs.idx[bs.cnt[key[r] & 63u] + (key[r] >> 6)] = static_cast<unsigned short>(i);
+      }
+      float sc[kNumFields];
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
+      __syncthreads();
+      const int slots = (m + 63) >> 6;
+      for (int sl = wave; sl < slots; sl += kWaves) {
+        const int q = lane * slots + sl;
+        if (q >= m) continue;
+        const uint32_t p = c0 + bs.idx[q];
+        const float4 a = sorted[2 * static_cast<int64_t>(p)];
+        const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
+        float wx[kTaps], wy[kTaps], wz[kTaps];
+        const unsigned base = particle_taps<float, TS>(a, kp, ox, oy, oz, tp, wx, wy, wz);
+        const DepositQ<float> d = charges<float>(a, v, bulk, vb0, vb1, vb2);
+        float qs[kNumFields];
+#pragma unroll
+        for (int f = 0; f < kNumFields; ++f) qs[f] = d.q[f] * sc[f];
+        int* accf[kNumFields] = {acc + base, acc + VOL + base, acc + 2 * VOL + base, acc + 3 * VOL + base};
+#pragma unroll
+        for (int jx = 0; jx < kTaps; ++jx) {
+#pragma unroll
+          for (int jy = 0; jy < kTaps; ++jy) {
+            const float wxy = wx[jx] * wy[jy];
+#pragma unroll
+            for (int f = 0; f < kNumFields; ++f) {
+              const float wq = wxy * qs[f];
+#pragma unroll
+              for (int jz = 0; jz < kTaps; ++jz)
+                atomicAdd(accf[f] + (jx * E + jy) * E + jz, round_to_int(wq * wz[jz]));
+            }
+          }
+        }
+      }
+      __syncthreads();
+    };
+    deposit_chunk(p0, m0, key0, true);
+    for (uint32_t c0 = p0 + kSuper; c0 < p1; c0 += kSuper) {
+      const int m = static_cast<int>(min(static_cast<uint32_t>(kSuper), p1 - c0));
+      if (t < 64) bs.cnt[t] = 0;
+      __syncthreads();
+      unsigned key[kPer];
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        key[r] = 0;
+        if (t + r * NT < m) {
+          const unsigned b =
+              tap_origin<TS>(sorted[2 * static_cast<int64_t>(c0 + t + r * NT)], kp, ox, oy, oz) & 63u;
+          key[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
+        }
+      }
+      deposit_chunk(c0, m, key, false);
+    }
+    // take the next tile, then flush this one (clearing it)
+    tile = next_tile<NT>(tq, n_tiles, &s_tile);
+    if (t < 64) bs.cnt[t] = 0;
+    float inv[kNumFields];
+#pragma unroll
+    for (int f = 0; f < kNumFields; ++f) inv[f] = inv_s[f];
+    for (int i = t; i < VOL; i += NT) {
+      const int ez = i % E, ey = (i / E) % E, ex = i / (E * E);
+      const int gx = (ox + ex - 2) & (n - 1);
+      const int gy = (oy + ey - 2) & (n - 1);
+      const int gz = (oz + ez - 2) & (n - 1);
+      const int64_t gi = (static_cast<int64_t>(gx) * n + gy) * n + gz;
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) {
+        const int val = acc[f * VOL + i];
+        acc[f * VOL + i] = 0;
+        if (val != 0) atomicAdd(grid + f * n3 + gi, static_cast<float>(val) * inv[f]);
+      }
+    }
+    __syncthreads();
   }
 }
 
-// FP64 grids: LDS accumulation with ds_add_f64 (~7 lanes/clk/CU on gfx950).
+// FP64 grids: LDS accumulation with ds_add_f64 (~7 lanes/clk/CU on gfx950),
+// same tiles and bank-sorted lane order as the FP32 kernel (a double spans
+// two banks, so the key is the element index mod 32).
 template <int TS, int NT>
 __global__ __launch_bounds__(NT) void scatter_f64_kernel(
     const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, double* __restrict__ grid,
     KeyParams kp, int64_t n_tiles, int64_t xcd_chunk, TapPoly tp, const Derived* dsrc, int bulk) {
   constexpr int E = TS + 5;
   constexpr int VOL = E * E * E;
+  constexpr int kPer = 4;
+  constexpr int kSuper = kPer * NT;
+  constexpr int kWaves = NT / 64;
   __shared__ double acc[kNumFields * VOL];
-  __shared__ BankSort<NT> bs;
+  __shared__ BankSort<NT, kPer> bs;
   const int64_t tile = tile_of_block(blockIdx.x, xcd_chunk);
   if (tile >= n_tiles) return;
   const uint32_t p0 = offset[tile], p1 = offset[tile + 1];
   if (p0 == p1) return;
-  for (int i = threadIdx.x; i < kNumFields * VOL; i += NT) acc[i] = 0.0;
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+  for (int i = t; i < kNumFields * VOL; i += NT) acc[i] = 0.0;
   double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
   if (bulk) {
     vb0 = dsrc->vb[0];
     vb1 = dsrc->vb[1];
     vb2 = dsrc->vb[2];
   }
-  __syncthreads();
   const int nt = kp.nt;
   const int tz = static_cast<int>(tile % nt);
   const int ty = static_cast<int>((tile / nt) % nt);
   const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
   const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
-  // bank-sorted lane order (see the FP32 kernel); one double spans two banks,
-  // so the bank key is the word index of the double mod 64 halved
-  for (uint32_t c0 = p0; c0 < p1; c0 += NT) {
-    const int m = static_cast<int>(min(static_cast<uint32_t>(NT), p1 - c0));
-    const bool mine = static_cast<int>(threadIdx.x) < m;
-    unsigned bank = 0;
-    if (mine) {
-      double wx[kTaps], wy[kTaps], wz[kTaps];
-      bank = particle_taps<double, TS>(sorted[2 * static_cast<int64_t>(c0 + threadIdx.x)], kp, ox, oy, oz, tp, wx,
-                                       wy, wz) & 31u;
-    }
-    const int j = bank_sorted_index<NT>(bs, mine, bank, m);
-    if (j < 0) continue;
-    const uint32_t p = c0 + static_cast<uint32_t>(j);
-    const float4 a = sorted[2 * static_cast<int64_t>(p)];
-    const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
-    double wx[kTaps], wy[kTaps], wz[kTaps];
-    const unsigned base = particle_taps<double, TS>(a, kp, ox, oy, oz, tp, wx, wy, wz);
-    const DepositQ<double> d = charges<double>(a, v, bulk, vb0, vb1, vb2);
-    double qz[kNumFields][kTaps];
+  for (uint32_t c0 = p0; c0 < p1; c0 += kSuper) {
+    const int m = static_cast<int>(min(static_cast<uint32_t>(kSuper), p1 - c0));
+    if (t < 64) bs.cnt[t] = 0;
+    __syncthreads();
+    unsigned bank[kPer], slot[kPer];
 #pragma unroll
-    for (int f = 0; f < kNumFields; ++f)
-#pragma unroll
-      for (int j = 0; j < kTaps; ++j) qz[f][j] = d.q[f] * wz[j];
-    double* accf[kNumFields] = {acc + base, acc + VOL + base, acc + 2 * VOL + base, acc + 3 * VOL + base};
-#pragma unroll
-    for (int jx = 0; jx < kTaps; ++jx) {
-#pragma unroll
-      for (int jy = 0; jy < kTaps; ++jy) {
-        const double wxy = wx[jx] * wy[jy];
-#pragma unroll
-        for (int f = 0; f < kNumFields; ++f)
-#pragma unroll
-          for (int jz = 0; jz < kTaps; ++jz) atomicAdd(accf[f] + (jx * E + jy) * E + jz, wxy * qz[f][jz]);
+    for (int r = 0; r < kPer; ++r) {
+      const int i = t + r * NT;
+      if (i < m) {
+        bank[r] = tap_origin<TS>(sorted[2 * static_cast<int64_t>(c0 + i)], kp, ox, oy, oz) & 31u;
+        slot[r] = static_cast<unsigned>(atomicAdd(&bs.cnt[bank[r]], 1));
       }
     }
+    __syncthreads();
+    bank_scan<NT, kPer>(bs);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int i = t + r * NT;
+      if (i < m) bs.idx[bs.cnt[bank[r]] + slot[r]] = static_cast<unsigned short>(i);
+    }
+    __syncthreads();
+    const int slots = (m + 63) >> 6;
+    for (int sl = wave; sl < slots; sl += kWaves) {
+      const int q = lane * slots + sl;
+      if (q >= m) continue;
+      const uint32_t p = c0 + bs.idx[q];
+      const float4 a = sorted[2 * static_cast<int64_t>(p)];
+      const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
+      double wx[kTaps], wy[kTaps], wz[kTaps];
+      const unsigned base = particle_taps<double, TS>(a, kp, ox, oy, oz, tp, wx, wy, wz);
+      const DepositQ<double> d = charges<double>(a, v, bulk, vb0, vb1, vb2);
+      double qz[kNumFields][kTaps];
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f)
+#pragma unroll
+        for (int j = 0; j < kTaps; ++j) qz[f][j] = d.q[f] * wz[j];
+      double* accf[kNumFields] = {acc + base, acc + VOL + base, acc + 2 * VOL + base, acc + 3 * VOL + base};
+#pragma unroll
+      for (int jx = 0; jx < kTaps; ++jx) {
+#pragma unroll
+        for (int jy = 0; jy < kTaps; ++jy) {
+          const double wxy = wx[jx] * wy[jy];
+#pragma unroll
+          for (int f = 0; f < kNumFields; ++f)
+#pragma unroll
+            for (int jz = 0; jz < kTaps; ++jz) atomicAdd(accf[f] + (jx * E + jy) * E + jz, wxy * qz[f][jz]);
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int n = kp.n;
   const int64_t n3 = static_cast<int64_t>(n) * n * n;
-  for (int i = threadIdx.x; i < VOL; i += NT) {
+  for (int i = t; i < VOL; i += NT) {
     const int ez = i % E, ey = (i / E) % E, ex = i / (E * E);
     const int gx = (ox + ex - 2) & (n - 1);
     const int gy = (oy + ey - 2) & (n - 1);
@@ -628,17 +838,29 @@ hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int
   const KeyParams kp = key_params(p, c);
   const int64_t xcd_chunk = (p->n_tiles % 8 == 0) ? p->n_tiles / 8 : 0;
   const Derived* dsrc = &p->d_header->d;
-  const unsigned grid = static_cast<unsigned>(p->n_tiles);
-  if (p->prec == MPS_F32) {
-    if (p->tile == 16)
-      scatter_fixed_kernel<16, 1024><<<grid, 1024, 0, s>>>(p->sorted, p->tile_offset, static_cast<float*>(p->grid),
-                                                            kp, p->n_tiles, xcd_chunk, p->taps, dsrc, bulk);
-    else
-      scatter_fixed_kernel<8, 512><<<grid, 512, 0, s>>>(p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp,
-                                                         p->n_tiles, xcd_chunk, p->taps, dsrc, bulk);
+  if (p->prec == MPS_F32 && p->tile == 16) {
+    TileQueues tq;
+    tq.counter = p->tile_queue;
+    tq.nq = xcd_chunk > 0 ? 8 : 1;
+    tq.per_queue = xcd_chunk > 0 ? xcd_chunk : p->n_tiles;
+    clear_kernel<uint32_t><<<1, 64, 0, s>>>(p->tile_queue, 8);
+    // one workgroup per CU (the LDS holds one), never more than the tiles
+    const int64_t blocks = p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus;
+    scatter_fixed_kernel<16, 1024><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+        p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, p->taps, p->tap_bound, dsrc, bulk);
+  } else if (p->prec == MPS_F32) {
+    TileQueues tq;
+    tq.counter = p->tile_queue;
+    tq.nq = xcd_chunk > 0 ? 8 : 1;
+    tq.per_queue = xcd_chunk > 0 ? xcd_chunk : p->n_tiles;
+    clear_kernel<uint32_t><<<1, 64, 0, s>>>(p->tile_queue, 8);
+    const int64_t cap = 4 * static_cast<int64_t>(p->num_cus);
+    const int64_t blocks = p->n_tiles < cap ? p->n_tiles : cap;
+    scatter_fixed_kernel<8, 512><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
+        p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, p->taps, p->tap_bound, dsrc, bulk);
   } else {
-    scatter_f64_kernel<8, 512><<<grid, 512, 0, s>>>(p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp,
-                                                     p->n_tiles, xcd_chunk, p->taps, dsrc, bulk);
+    scatter_f64_kernel<8, 512><<<static_cast<unsigned>(p->n_tiles), 512, 0, s>>>(
+        p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, xcd_chunk, p->taps, dsrc, bulk);
   }
   return hipGetLastError();
 }

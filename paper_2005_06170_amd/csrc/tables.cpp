@@ -10,6 +10,7 @@
 // |beta3_hat|^2.  phi is a cubic on every unit interval, so each of the six
 // taps j = -2..3 of a particle at fraction f carries a cubic weight
 // w_j(f) = phi(j - f).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -114,6 +115,34 @@ TapPoly bl3_tap_polynomials() {
         tp.c[j][q] += a[p] * binom[p][q] * ((q & 1) ? -1.0 : 1.0);
   }
   return tp;
+}
+
+TapBound bl3_tap_bounds(const TapPoly& tp) {
+  TapBound b;
+  for (int j = 0; j < kTaps; ++j) {
+    const double* c = tp.c[j];
+    // |w_j| on [0, 1] peaks at an end or where w_j' = c1 + 2 c2 f + 3 c3 f^2 vanishes
+    double cand[4] = {0.0, 1.0, -1.0, -1.0};
+    const double qa = 3.0 * c[3], qb = 2.0 * c[2], qc = c[1];
+    if (qa != 0.0) {
+      const double disc = qb * qb - 4.0 * qa * qc;
+      if (disc >= 0.0) {
+        const double r = std::sqrt(disc);
+        cand[2] = (-qb + r) / (2.0 * qa);
+        cand[3] = (-qb - r) / (2.0 * qa);
+      }
+    } else if (qb != 0.0) {
+      cand[2] = -qc / qb;
+    }
+    double m = 0.0;
+    for (double f : cand) {
+      if (f < 0.0 || f > 1.0) continue;
+      m = std::max(m, std::fabs(((c[3] * f + c[2]) * f + c[1]) * f + c[0]));
+    }
+    // margin for the FP32 evaluation of the taps on the device
+    b.k[j] = static_cast<float>(m * 1.0001);
+  }
+  return b;
 }
 
 void bl3_axis_tables(int n_grid, std::vector<double>* win2, std::vector<double>* alias) {

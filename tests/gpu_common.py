@@ -25,6 +25,7 @@ def compare_spectra(g, o, tol, label=""):
     for key in ("sn_pp", "sn_tt", "sn_dd"):
         ov = getattr(o, key)[~empty]
         errs[key] = float(np.max(np.abs(g[key][~empty] - ov) / np.abs(ov))) if ov.size else 0.0
+    print(f"{label} max guarded error: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
     bad = {k: v for k, v in errs.items() if not v <= tol}
     assert not bad, (label, errs)
     return errs
