@@ -323,6 +323,20 @@ __device__ __forceinline__ int round_to_int(float x) {
   return r;
 }
 
+// Two int32 deposits (lo, hi) as the int64 hi 2^32 + lo, added with one
+// 64-bit LDS atomic.  The 64-bit sum is hi_sum 2^32 + lo_sum modulo 2^64:
+// as long as the final lo_sum fits int32, its low word is lo_sum and the high
+// word, corrected for lo_sum's sign, is hi_sum modulo 2^32.
+__device__ __forceinline__ unsigned long long pack_pair(int lo, int hi) {
+  const unsigned h = static_cast<unsigned>(hi + (lo >> 31));
+  return (static_cast<unsigned long long>(h) << 32) | static_cast<unsigned>(lo);
+}
+
+__device__ __forceinline__ void unpack_pair(unsigned long long s, int* lo, int* hi) {
+  *lo = static_cast<int>(static_cast<unsigned>(s));
+  *hi = static_cast<int>(static_cast<unsigned>(s >> 32) + (*lo < 0 ? 1u : 0u));
+}
+
 // LDS word index of a particle's tap origin (cell relative to the tile
 // origin, halo offset included) without the tap weights.
 template <int TS>
@@ -340,20 +354,22 @@ __device__ __forceinline__ unsigned tap_origin(const float4& a, const KeyParams&
 }
 
 // Lane assignment that spreads a wave over the LDS banks.  A super-chunk of
-// up to kPer * NT particles is counting-sorted by the LDS bank of its tap
-// origin (word index mod 64; for doubles, index mod 32); with W = ceil(m/64)
-// wave slots, lane l of slot s takes bank-sorted position l * W + s, so the
-// 64 lanes of a wave come from 64 consecutive bank segments: about one lane
-// per bank (two on a 32-bank LDS) and never two lanes on one address.
+// up to kPer * NT particles is counting-sorted by the bank pair of its tap
+// origin (64-bit element index mod 32: the 8-byte accumulators of both
+// kernels span two 4-byte banks); with W = ceil(m/64) wave slots, lane l of
+// slot s takes bank-sorted position l' W + s with l' = 2 (l mod 32) + l / 32,
+// so that each half-wave draws one lane from each of 32 consecutive bank
+// segments: one access per bank pair, two lanes on one address only when
+// two particles share a cell.
 template <int NT, int kPer>
 struct BankSort {
   int cnt[64];
   unsigned short idx[NT * kPer];
 };
 
-// Phase 1: each thread registers up to kPer particles (local indices
-// t + r NT) with their bank; returns per-particle slots within their bank.
-// Phase 2 (bank_place): after the scan, write the sorted index array.
+// Threads first count their particles per bank pair (bs.cnt, taking slots
+// with LDS atomics); this turns the counts into bucket starts, after which
+// each particle's local index goes to bs.idx[start + slot].
 template <int NT, int kPer>
 __device__ __forceinline__ void bank_scan(BankSort<NT, kPer>& bs) {
   const int t = threadIdx.x;
@@ -418,8 +434,9 @@ __device__ __forceinline__ void bound_line(const float (&in)[E], const TapBound&
 
 // FP32 grids.  A persistent grid of one workgroup per CU walks the occupied
 // T^3 tiles.  LDS holds the four fields over the tile plus a halo of 2 cells
-// below and 3 above along each axis (taps -2..3) as 32-bit fixed point:
-// gfx950's LDS adds integers at ~14 lanes/clk/CU but FP32 at ~0.3.
+// below and 3 above along each axis (taps -2..3) as 32-bit fixed point, two
+// fields per 64-bit word: gfx950's LDS adds 64-bit integers at ~9.4
+// lanes/clk/CU and 32-bit ones at ~14, but FP32 at ~0.3.
 //
 // Sums of fixed-point deposits are exact modulo 2^32 in any order, so only
 // the final value of each cell has to fit int32.  Per tile and field the
@@ -441,7 +458,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   constexpr int kSuper = kPer * NT;
   constexpr int kWaves = NT / 64;
   constexpr int kCellOff = (2 * E + 2) * E + 2;  // tap origin -> the particle's own cell
-  __shared__ int acc[kNumFields * VOL];
+  __shared__ __align__(16) int acc[kNumFields * VOL];
   __shared__ BankSort<NT, kPer> bs;
   __shared__ float red[kWaves][kNumFields];
   __shared__ float scale_s[kNumFields], inv_s[kNumFields];
@@ -464,6 +481,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   const int n = kp.n;
   const int64_t n3 = static_cast<int64_t>(n) * n * n;
   unsigned* cnt_u = reinterpret_cast<unsigned*>(acc);
+  unsigned long long* acc2 = reinterpret_cast<unsigned long long*>(acc);
 
   int64_t tile = next_tile<NT>(tq, n_tiles, &s_tile);
   for (int i = t; i < kNumFields * VOL; i += NT) acc[i] = 0;
@@ -504,7 +522,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         const int64_t p = static_cast<int64_t>(p0) + t + r * NT;
         const float4 a = sorted[2 * p];
         const unsigned base = tap_origin<TS>(a, kp, ox, oy, oz);
-        const unsigned b = base & 63u;
+        const unsigned b = base & 31u;
         key0[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
         add_cell_sums(a, sorted[2 * p + 1], base + kCellOff);
       }
@@ -592,8 +610,10 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
       __syncthreads();
       const int slots = (m + 63) >> 6;
+      // each half-wave takes one lane from each of the 32 bank pairs
+      const int lr = ((lane & 31) << 1) | (lane >> 5);
       for (int sl = wave; sl < slots; sl += kWaves) {
-        const int q = lane * slots + sl;
+        const int q = lr * slots + sl;
         if (q >= m) continue;
         const uint32_t p = c0 + bs.idx[q];
         const float4 a = sorted[2 * static_cast<int64_t>(p)];
@@ -604,18 +624,19 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         float qs[kNumFields];
 #pragma unroll
         for (int f = 0; f < kNumFields; ++f) qs[f] = d.q[f] * sc[f];
-        int* accf[kNumFields] = {acc + base, acc + VOL + base, acc + 2 * VOL + base, acc + 3 * VOL + base};
+        unsigned long long* accp[2] = {acc2 + base, acc2 + VOL + base};
 #pragma unroll
         for (int jx = 0; jx < kTaps; ++jx) {
 #pragma unroll
           for (int jy = 0; jy < kTaps; ++jy) {
             const float wxy = wx[jx] * wy[jy];
 #pragma unroll
-            for (int f = 0; f < kNumFields; ++f) {
-              const float wq = wxy * qs[f];
+            for (int k = 0; k < 2; ++k) {
+              const float wlo = wxy * qs[2 * k], whi = wxy * qs[2 * k + 1];
 #pragma unroll
               for (int jz = 0; jz < kTaps; ++jz)
-                atomicAdd(accf[f] + (jx * E + jy) * E + jz, round_to_int(wq * wz[jz]));
+                atomicAdd(accp[k] + (jx * E + jy) * E + jz,
+                          pack_pair(round_to_int(wlo * wz[jz]), round_to_int(whi * wz[jz])));
             }
           }
         }
@@ -633,7 +654,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         key[r] = 0;
         if (t + r * NT < m) {
           const unsigned b =
-              tap_origin<TS>(sorted[2 * static_cast<int64_t>(c0 + t + r * NT)], kp, ox, oy, oz) & 63u;
+              tap_origin<TS>(sorted[2 * static_cast<int64_t>(c0 + t + r * NT)], kp, ox, oy, oz) & 31u;
           key[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
         }
       }
@@ -652,10 +673,13 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       const int gz = (oz + ez - 2) & (n - 1);
       const int64_t gi = (static_cast<int64_t>(gx) * n + gy) * n + gz;
 #pragma unroll
-      for (int f = 0; f < kNumFields; ++f) {
-        const int val = acc[f * VOL + i];
-        acc[f * VOL + i] = 0;
-        if (val != 0) atomicAdd(grid + f * n3 + gi, static_cast<float>(val) * inv[f]);
+      for (int k = 0; k < 2; ++k) {
+        const unsigned long long sum = acc2[k * VOL + i];
+        acc2[k * VOL + i] = 0ull;
+        int lo, hi;
+        unpack_pair(sum, &lo, &hi);
+        if (lo != 0) atomicAdd(grid + (2 * k) * n3 + gi, static_cast<float>(lo) * inv[2 * k]);
+        if (hi != 0) atomicAdd(grid + (2 * k + 1) * n3 + gi, static_cast<float>(hi) * inv[2 * k + 1]);
       }
     }
     __syncthreads();
@@ -717,8 +741,9 @@ __global__ __launch_bounds__(NT) void scatter_f64_kernel(
     }
     __syncthreads();
     const int slots = (m + 63) >> 6;
+    const int lr = ((lane & 31) << 1) | (lane >> 5);
     for (int sl = wave; sl < slots; sl += kWaves) {
-      const int q = lane * slots + sl;
+      const int q = lr * slots + sl;
       if (q >= m) continue;
       const uint32_t p = c0 + bs.idx[q];
       const float4 a = sorted[2 * static_cast<int64_t>(p)];
