@@ -138,6 +138,90 @@ __device__ __forceinline__ void load_twiddles(cpx<T>* tw, const cpx<T>* __restri
   for (int i = threadIdx.x; i < N; i += NT) tw[i] = gtw[i];
 }
 
+// 16-byte vectors of complex values: two FP32 or one FP64.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 2;
+  __device__ static cpx<float> get(const float4& v, int e) { return e == 0 ? cpx<float>{v.x, v.y} : cpx<float>{v.z, v.w}; }
+  __device__ static float4 make(const cpx<float>* c) { return make_float4(c[0].re, c[0].im, c[1].re, c[1].im); }
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 1;
+  __device__ static cpx<double> get(const double2& v, int) { return {v.x, v.y}; }
+  __device__ static double2 make(const cpx<double>* c) { return make_double2(c[0].re, c[0].im); }
+};
+
+// Global -> LDS staging of ROWS rows of COLS consecutive complex values (row r
+// starts at src(r), 16-byte aligned): each thread issues GROUP 16-byte loads
+// before writing any of them to LDS element put(r, c), so that many loads
+// are in flight per wave.
+template <typename T, int ROWS, int COLS, int NT, int MAXG = 16, typename Src, typename Put>
+__device__ __forceinline__ void gather_rows(Src src, Put put) {
+  using V = Vec16<T>;
+  static_assert(COLS % V::n == 0, "rows must hold whole 16-byte vectors");
+  constexpr int CV = COLS / V::n;
+  constexpr int TOTAL = ROWS * CV;
+  constexpr int ITER = (TOTAL + NT - 1) / NT;
+  constexpr int GROUP = ITER < MAXG ? ITER : MAXG;
+  constexpr bool kExact = TOTAL % NT == 0 && ITER % GROUP == 0;
+  for (int k0 = 0; k0 < ITER; k0 += GROUP) {
+    typename V::type v[GROUP];
+#pragma unroll
+    for (int k = 0; k < GROUP; ++k) {
+      const int i = threadIdx.x + (k0 + k) * NT;
+      if (kExact || (k0 + k < ITER && i < TOTAL))
+        v[k] = *reinterpret_cast<const typename V::type*>(src(i / CV) + (i % CV) * V::n);
+    }
+#pragma unroll
+    for (int k = 0; k < GROUP; ++k) {
+      const int i = threadIdx.x + (k0 + k) * NT;
+      if (kExact || (k0 + k < ITER && i < TOTAL)) {
+        const int r = i / CV, c = (i % CV) * V::n;
+#pragma unroll
+        for (int e = 0; e < V::n; ++e) put(r, c + e, V::get(v[k], e));
+      }
+    }
+  }
+}
+
+// LDS -> global: value(r, c) for ROWS rows of COLS consecutive complex values
+// stored from dst(r), GROUP vectors gathered per thread before the stores.
+template <typename T, int ROWS, int COLS, int NT, typename Dst, typename Get>
+__device__ __forceinline__ void scatter_rows(Dst dst, Get value) {
+  using V = Vec16<T>;
+  static_assert(COLS % V::n == 0, "rows must hold whole 16-byte vectors");
+  constexpr int CV = COLS / V::n;
+  constexpr int TOTAL = ROWS * CV;
+  constexpr int ITER = (TOTAL + NT - 1) / NT;
+  constexpr int GROUP = ITER < 8 ? ITER : 8;
+  constexpr bool kExact = TOTAL % NT == 0 && ITER % GROUP == 0;
+  for (int k0 = 0; k0 < ITER; k0 += GROUP) {
+    typename V::type v[GROUP];
+#pragma unroll
+    for (int k = 0; k < GROUP; ++k) {
+      const int i = threadIdx.x + (k0 + k) * NT;
+      if (kExact || (k0 + k < ITER && i < TOTAL)) {
+        const int r = i / CV, c = (i % CV) * V::n;
+        cpx<T> e[V::n];
+#pragma unroll
+        for (int q = 0; q < V::n; ++q) e[q] = value(r, c + q);
+        v[k] = V::make(e);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < GROUP; ++k) {
+      const int i = threadIdx.x + (k0 + k) * NT;
+      if (kExact || (k0 + k < ITER && i < TOTAL))
+        *reinterpret_cast<typename V::type*>(dst(i / CV) + (i % CV) * V::n) = v[k];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- z pass
 // P rows of N reals per workgroup: complex FFT of length N/2 on the packed
 // even/odd samples, then the real-to-complex split.
@@ -149,22 +233,19 @@ __global__ __launch_bounds__(NT) void fft_z_kernel(T* __restrict__ grid, const c
   __shared__ cpx<T> tw[N];
   load_twiddles<T, N, NT>(tw, gtw);
   cpx<T>* rows = reinterpret_cast<cpx<T>*>(grid) + static_cast<int64_t>(blockIdx.x) * P * M;
-  for (int i = threadIdx.x; i < P * M; i += NT) {
-    const int q = i / M, j = i % M;
-    buf[q * TS + j] = rows[i];
-  }
+  gather_rows<T, P, M, NT>([&](int q) { return rows + q * M; },
+                           [&](int q, int j, cpx<T> v) { buf[q * TS + j] = v; });
   __syncthreads();
   fft_passes<T, M, 1, P, NT, 2>(buf, TS, tw);
   const T half = static_cast<T>(0.5);
-  for (int i = threadIdx.x; i < P * M; i += NT) {
-    const int q = i / M, k = i % M;
+  scatter_rows<T, P, M, NT>([&](int q) { return rows + q * M; }, [&](int q, int k) {
     const cpx<T> a = buf[q * TS + k];
     const cpx<T> z2 = buf[q * TS + (M - k) % M];
     const cpx<T> b = {z2.re, -z2.im};
     const cpx<T> s = a + b, d = a - b;
     const cpx<T> t = cmul(tw[k], mul_mi(d));
-    rows[i] = {half * (s.re + t.re), half * (s.im + t.im)};
-  }
+    return cpx<T>{half * (s.re + t.re), half * (s.im + t.im)};
+  });
 }
 
 // ------------------------------------------------------------- y, x passes
@@ -187,16 +268,12 @@ __global__ __launch_bounds__(NT) void fft_cols_kernel(T* __restrict__ grid, cons
   const int64_t f = fo / N, o = fo % N;
   cpx<T>* base = reinterpret_cast<cpx<T>*>(grid) + f * static_cast<int64_t>(N) * N * M + o * outer_stride +
                  kb * B;
-  for (int i = threadIdx.x; i < N * B; i += NT) {
-    const int r = i / B, c = i % B;
-    buf[c * TS + r] = base[r * stride + c];
-  }
+  gather_rows<T, N, B, NT>([&](int r) { return base + r * stride; },
+                           [&](int r, int c, cpx<T> v) { buf[c * TS + r] = v; });
   __syncthreads();
   fft_passes<T, N, 1, B, NT, 1>(buf, TS, tw);
-  for (int i = threadIdx.x; i < N * B; i += NT) {
-    const int r = i / B, c = i % B;
-    base[r * stride + c] = buf[c * TS + r];
-  }
+  scatter_rows<T, N, B, NT>([&](int r) { return base + r * stride; },
+                            [&](int r, int c) { return buf[c * TS + r]; });
 }
 
 // ------------------------------------------------- x pass fused with bins
@@ -251,12 +328,10 @@ __global__ __launch_bounds__(NT) void fft_x_bin_kernel(const T* __restrict__ gri
     const int kz0 = kb * B;
     if (static_cast<int64_t>(ny) * ny + static_cast<int64_t>(kz0) * kz0 >= H2) continue;
     __syncthreads();  // previous item's LDS reads are done
-    for (int i = threadIdx.x; i < kNumFields * N * B; i += NT) {
-      const int c = i % B;
-      const int r = (i / B) % N;
-      const int f = i / (B * N);
-      buf[(f * B + c) * TS + r] = g[f * field_stride + r * xstride + static_cast<int64_t>(y) * M + kz0 + c];
-    }
+    const cpx<T>* col0 = g + static_cast<int64_t>(y) * M + kz0;
+    gather_rows<T, kNumFields * N, B, NT, 8>(
+        [&](int fr) { return col0 + (fr / N) * field_stride + (fr % N) * xstride; },
+        [&](int fr, int c, cpx<T> v) { buf[((fr / N) * B + c) * TS + fr % N] = v; });
     __syncthreads();
     fft_passes<T, N, 1, COUNT, NT, 1>(buf, TS, tw);
 
