@@ -28,7 +28,8 @@ __device__ __forceinline__ int locate(float x, double scale, int n, double* frac
   if (!fin) u = 0.0;
   const double uf = floor(u);
   *frac = u - uf;
-  const double m = uf - static_cast<double>(n) * floor(uf / static_cast<double>(n));
+  // n is a power of two: uf * (1 / n) is exactly uf / n
+  const double m = uf - static_cast<double>(n) * floor(uf * (1.0 / static_cast<double>(n)));
   int c = static_cast<int>(m);
   c = c < 0 ? 0 : (c >= n ? n - 1 : c);
   *ok = fin;
@@ -55,6 +56,35 @@ __device__ __forceinline__ uint32_t wave_run_atomic(uint32_t key, bool valid, ui
   return base + static_cast<uint32_t>(lane - start);
 }
 
+// wave_run_atomic split in two, so that several claims can be in flight:
+// the run heads' atomics, then each lane's slot from its head's result.
+struct WaveRun {
+  uint32_t base;  // the head's atomic result (valid in head lanes)
+  int start;      // lane of this lane's run head
+};
+
+__device__ __forceinline__ WaveRun wave_run_claim(uint32_t key, bool valid, uint32_t* counters) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t prev = __shfl_up(key, 1);
+  const bool head = valid && (lane == 0 || key != prev);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long vmask = __ballot(valid);
+  const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const unsigned long long mine = heads & upto;
+  WaveRun r;
+  r.start = mine ? 63 - __clzll(static_cast<long long>(mine)) : lane;
+  const unsigned long long after = (heads | ~vmask) & ~upto;
+  const int end = after ? __ffsll(static_cast<long long>(after)) - 1 : 64;
+  r.base = 0;
+  if (head) r.base = atomicAdd(&counters[key], static_cast<uint32_t>(end - lane));
+  return r;
+}
+
+__device__ __forceinline__ uint32_t wave_run_slot(const WaveRun& r) {
+  const int lane = threadIdx.x & 63;
+  return __shfl(r.base, r.start) + static_cast<uint32_t>(lane - r.start);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   return v;
@@ -77,7 +107,11 @@ __device__ __forceinline__ uint32_t tile_key(float x, float y, float z, const Ke
   return static_cast<uint32_t>(((cx >> kp.tshift) * kp.nt + (cy >> kp.tshift)) * kp.nt + (cz >> kp.tshift));
 }
 
-// Moments (FP64) and tile histogram in one pass over the catalog.
+// Moments (FP64) and tile histogram in one pass over the catalog.  Each
+// thread takes kUnroll particles per step (one per wave-wide slab, so that a
+// wave still sees consecutive particles) and issues all their loads first.
+constexpr int kUnroll = 4;
+
 template <bool kHasW>
 __global__ __launch_bounds__(kCountThreads) void count_kernel(
     const float* __restrict__ pos, const float* __restrict__ vel, const float* __restrict__ wgt,
@@ -88,39 +122,57 @@ __global__ __launch_bounds__(kCountThreads) void count_kernel(
   for (int q = 0; q < kMomentSums; ++q) acc[q] = 0.0;
   double mx[kMomentMax] = {0.0, 0.0, 0.0, 0.0};
   bool bad = false;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kCountThreads;
-  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kCountThreads; base < np; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    const bool valid = i < np;
-    uint32_t key = 0xffffffffu;
-    if (valid) {
-      const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
-      bool ok;
-      key = tile_key(x, y, z, kp, &ok);
-      bad |= !ok;
-      const double w = kHasW ? static_cast<double>(wgt[i]) : 1.0;
-      const double vx = vel[3 * i], vy = vel[3 * i + 1], vz = vel[3 * i + 2];
-      const double w2 = w * w;
-      acc[0] += w;
-      acc[1] += w2;
-      acc[2] += w * vx;
-      acc[3] += w * vy;
-      acc[4] += w * vz;
-      acc[5] += w2 * vx;
-      acc[6] += w2 * vy;
-      acc[7] += w2 * vz;
-      acc[8] += w2 * vx * vx;
-      acc[9] += w2 * vy * vy;
-      acc[10] += w2 * vz * vz;
-      acc[11] += w2 * vx * vy;
-      acc[12] += w2 * vx * vz;
-      acc[13] += w2 * vy * vz;
-      mx[0] = fmax(mx[0], fabs(w));
-      mx[1] = fmax(mx[1], fabs(w * vx));
-      mx[2] = fmax(mx[2], fabs(w * vy));
-      mx[3] = fmax(mx[3], fabs(w * vz));
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kCountThreads * kUnroll;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kCountThreads * kUnroll; base < np; base += stride) {
+    float x[kUnroll], y[kUnroll], z[kUnroll], vx[kUnroll], vy[kUnroll], vz[kUnroll], wf[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + u * kCountThreads + threadIdx.x;
+      x[u] = y[u] = z[u] = vx[u] = vy[u] = vz[u] = 0.f;
+      wf[u] = 1.f;
+      if (i < np) {
+        x[u] = pos[3 * i];
+        y[u] = pos[3 * i + 1];
+        z[u] = pos[3 * i + 2];
+        vx[u] = vel[3 * i];
+        vy[u] = vel[3 * i + 1];
+        vz[u] = vel[3 * i + 2];
+        if (kHasW) wf[u] = wgt[i];
+      }
     }
-    wave_run_atomic(key, valid, tile_count);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + u * kCountThreads + threadIdx.x;
+      const bool valid = i < np;
+      uint32_t key = 0xffffffffu;
+      if (valid) {
+        bool ok;
+        key = tile_key(x[u], y[u], z[u], kp, &ok);
+        bad |= !ok;
+        const double w = wf[u];
+        const double dvx = vx[u], dvy = vy[u], dvz = vz[u];
+        const double w2 = w * w;
+        acc[0] += w;
+        acc[1] += w2;
+        acc[2] += w * dvx;
+        acc[3] += w * dvy;
+        acc[4] += w * dvz;
+        acc[5] += w2 * dvx;
+        acc[6] += w2 * dvy;
+        acc[7] += w2 * dvz;
+        acc[8] += w2 * dvx * dvx;
+        acc[9] += w2 * dvy * dvy;
+        acc[10] += w2 * dvz * dvz;
+        acc[11] += w2 * dvx * dvy;
+        acc[12] += w2 * dvx * dvz;
+        acc[13] += w2 * dvy * dvz;
+        mx[0] = fmax(mx[0], fabs(w));
+        mx[1] = fmax(mx[1], fabs(w * dvx));
+        mx[2] = fmax(mx[2], fabs(w * dvy));
+        mx[3] = fmax(mx[3], fabs(w * dvz));
+      }
+      wave_run_atomic(key, valid, tile_count);
+    }
   }
   __shared__ double red[kCountThreads / 64][kMomentSums + kMomentMax];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -227,24 +279,46 @@ template <bool kHasW>
 __global__ __launch_bounds__(kCountThreads) void permute_kernel(
     const float* __restrict__ pos, const float* __restrict__ vel, const float* __restrict__ wgt,
     int64_t np, KeyParams kp, uint32_t* __restrict__ cursor, float4* __restrict__ sorted) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kCountThreads;
-  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kCountThreads; base < np; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    const bool valid = i < np;
-    uint32_t key = 0xffffffffu;
-    float x = 0.f, y = 0.f, z = 0.f;
-    if (valid) {
-      x = pos[3 * i];
-      y = pos[3 * i + 1];
-      z = pos[3 * i + 2];
-      bool ok;
-      key = tile_key(x, y, z, kp, &ok);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kCountThreads * kUnroll;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kCountThreads * kUnroll; base < np; base += stride) {
+    float4 a[kUnroll], v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + u * kCountThreads + threadIdx.x;
+      a[u] = make_float4(0.f, 0.f, 0.f, 1.f);
+      v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (i < np) {
+        a[u].x = pos[3 * i];
+        a[u].y = pos[3 * i + 1];
+        a[u].z = pos[3 * i + 2];
+        if (kHasW) a[u].w = wgt[i];
+        v[u].x = vel[3 * i];
+        v[u].y = vel[3 * i + 1];
+        v[u].z = vel[3 * i + 2];
+      }
     }
-    const uint32_t slot = wave_run_atomic(key, valid, cursor);
-    if (valid) {
-      const float w = kHasW ? wgt[i] : 1.0f;
-      sorted[2 * static_cast<int64_t>(slot)] = make_float4(x, y, z, w);
-      sorted[2 * static_cast<int64_t>(slot) + 1] = make_float4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.f);
+    // all slots are claimed before any record is written, so the returning
+    // atomics of the kUnroll slabs overlap
+    WaveRun run[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + u * kCountThreads + threadIdx.x;
+      const bool valid = i < np;
+      uint32_t key = 0xffffffffu;
+      if (valid) {
+        bool ok;
+        key = tile_key(a[u].x, a[u].y, a[u].z, kp, &ok);
+      }
+      run[u] = wave_run_claim(key, valid, cursor);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + u * kCountThreads + threadIdx.x;
+      const uint32_t slot = wave_run_slot(run[u]);
+      if (i < np) {
+        sorted[2 * static_cast<int64_t>(slot)] = a[u];
+        sorted[2 * static_cast<int64_t>(slot) + 1] = v[u];
+      }
     }
   }
 }
@@ -799,7 +873,7 @@ KeyParams key_params(const Plan* p, const mps_catalog* c) {
 }
 
 int count_blocks(int64_t np) {
-  int64_t b = (np + kCountThreads - 1) / kCountThreads;
+  int64_t b = (np + kCountThreads * kUnroll - 1) / (kCountThreads * kUnroll);
   return static_cast<int>(b < kMomentBlocks ? (b < 1 ? 1 : b) : kMomentBlocks);
 }
 
