@@ -27,10 +27,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# The scatter is bound by the LDS atomic unit, not HBM: one 64-lane ds_add
-# wave-instruction retires every 4 clocks per CU (16 int32 lanes/clk/CU;
-# measured 14.1), so the peak is 256 CUs x 16 x 2.4 GHz deposits/s.
-LDS_DEPOSIT_PEAK = 256 * 16 * 2.4e9
+# The FP32 scatter is bound by the LDS atomic unit, not HBM.  Each 64-bit
+# ds_add_u64 lane carries two 32-bit fixed-point deposits; the LDS pipe
+# accepts one 64-lane instruction per 4 clocks per CU (16 lanes/clk/CU), so
+# the peak is 256 CUs x 16 lanes x 2 deposits x 2.4 GHz.  The probe's
+# measured ds_add_u64 ceiling (9.44 lanes/clk/CU) is reported beside it.
+LDS_DEPOSIT_PEAK = 256 * 16 * 2 * 2.4e9
+LDS_DEPOSIT_PROBE = 256 * 9.44 * 2 * 2.4e9
 DEPOSITS_PER_PARTICLE = 216 * 4
 N_GRID = 512
 N_LAT = 512
@@ -256,6 +259,8 @@ def main():
         roofline = {"kernel": dom, "bound": "alu", "achieved": dep_rate / 1e12,
                     "peak": LDS_DEPOSIT_PEAK / 1e12, "unit": "Tdeposit/s",
                     "frac": dep_rate / LDS_DEPOSIT_PEAK, "traffic": None,
+                    "probe_ceiling": LDS_DEPOSIT_PROBE / 1e12,
+                    "frac_of_probe_ceiling": dep_rate / LDS_DEPOSIT_PROBE,
                     "hbm_frac": per_stage[dom].get("frac_hbm")}
     else:
         dom_gbs = abytes[dom] / (stages[dom] * 1e-3) / 1e9

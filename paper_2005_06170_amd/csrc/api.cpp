@@ -245,6 +245,8 @@ int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec) {
   std::vector<double> win2, alias;
   bl3_axis_tables(n_grid, &win2, &alias);
   const std::vector<double> tw = twiddles(n_grid);
+  // the x pass multiplies by W_t^-2 per axis
+  for (double& w : win2) w = 1.0 / w;
   bool up = hipMemcpy(p->d_win2, win2.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) == hipSuccess;
   up = up && hipMemcpy(p->d_alias, alias.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) == hipSuccess;
   if (prec == MPS_F32) {

@@ -88,7 +88,7 @@ struct Plan {
   int num_cus = 256;
   double* moment_partials = nullptr; // kMomentBlocks x (kMomentSums + kMomentMax)
   ResultHeader* d_header = nullptr;
-  double* d_win2 = nullptr;          // N/2 + 1
+  double* d_win2 = nullptr;          // N/2 + 1: 1 / W_t(2 pi n / N)^2
   double* d_alias = nullptr;         // N/2 + 1
   void* d_twiddle = nullptr;         // N complex of the plan's precision
   int32_t* d_lut = nullptr;          // (N/2)^2

@@ -280,15 +280,19 @@ __global__ __launch_bounds__(NT) void fft_cols_kernel(T* __restrict__ grid, cons
 struct BinParams {
   double kf;        // 2 pi / L
   double haf;
+  double inv_haf;   // 1 / Haf
+  double inv_haf2;  // 1 / Haf^2
   int n_bins;
   int no_shot;
   int no_deconv;
   int bulk;
 };
 
-__device__ __forceinline__ void flush_bin(double* lbins, int bin, const double* acc) {
+// Adds one run of unweighted per-mode sums to the workgroup's LDS bins, with
+// the half-space weight w (1 on the kz = 0 plane, else 2) and k = kf |n|.
+__device__ __forceinline__ void flush_bin(double* lbins, int bin, const double* acc, double w, double kf) {
 #pragma unroll
-  for (int q = 0; q < kNumQ; ++q) atomicAdd(lbins + bin * kNumQ + q, acc[q]);
+  for (int q = 0; q < kNumQ; ++q) atomicAdd(lbins + bin * kNumQ + q, (q == QKsum ? w * kf : w) * acc[q]);
 }
 
 // Persistent: workgroup g handles items g, g + G, ... where an item is one
@@ -299,7 +303,7 @@ __device__ __forceinline__ void flush_bin(double* lbins, int bin, const double* 
 template <typename T, int N, int B, int NT>
 __global__ __launch_bounds__(NT) void fft_x_bin_kernel(const T* __restrict__ grid, const cpx<T>* __restrict__ gtw,
                                                        const ResultHeader* __restrict__ hdr,
-                                                       const double* __restrict__ win2_tab,
+                                                       const double* __restrict__ iwin2_tab,
                                                        const double* __restrict__ alias_tab,
                                                        const int32_t* __restrict__ lut, BinParams bp,
                                                        double* __restrict__ partials) {
@@ -313,16 +317,38 @@ __global__ __launch_bounds__(NT) void fft_x_bin_kernel(const T* __restrict__ gri
   __shared__ cpx<T> buf[COUNT * TS];
   __shared__ cpx<T> tw[N];
   __shared__ double lbins[kMaxBins * kNumQ];
+  // per-axis window and alias tables in LDS when they fit beside the pencils
+  constexpr size_t kBase = sizeof(cpx<T>) * (COUNT * TS + N) + sizeof(double) * kMaxBins * kNumQ;
+  constexpr bool kTabLds = kBase + 2 * sizeof(double) * (M + 1) <= 163840;
+  __shared__ double s_tab[kTabLds ? 2 * (M + 1) : 1];
+  const double* s_iwin2 = kTabLds ? s_tab : iwin2_tab;
+  const double* s_alias = kTabLds ? s_tab + M + 1 : alias_tab;
   load_twiddles<T, N, NT>(tw, gtw);
   for (int i = threadIdx.x; i < kMaxBins * kNumQ; i += NT) lbins[i] = 0.0;
+  if constexpr (kTabLds) {
+    for (int i = threadIdx.x; i <= M; i += NT) {
+      s_tab[i] = iwin2_tab[i];
+      s_tab[M + 1 + i] = alias_tab[i];
+    }
+  }
 
   const Derived d = hdr->d;
-  const double haf2 = bp.haf * bp.haf;
   const int64_t field_stride = static_cast<int64_t>(N) * N * M;
   const int64_t xstride = static_cast<int64_t>(N) * M;
   const cpx<T>* g = reinterpret_cast<const cpx<T>*>(grid);
   const int n_items = N * KB;
-  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+  // Items 2j and 2j+1 (kz blocks 2i, 2i+1 of one y row) read the two halves
+  // of the same 128-byte lines; with a grid of 16m workgroups they go to
+  // workgroups g and g + 8, which sit on the same XCD (workgroups are dealt
+  // to the 8 XCDs round robin), so the second read hits that XCD's L2.
+  const int G = gridDim.x, wg = blockIdx.x;
+  const bool paired = KB % 2 == 0 && G % 16 == 0;
+  const int lane_id = paired ? (wg % 8) + 8 * (wg / 16) : wg;
+  const int half = paired ? (wg / 8) % 2 : 0;
+  const int per_it = paired ? G / 2 : G;
+  for (int it = 0;; ++it) {
+    const int item = paired ? 2 * (it * per_it + lane_id) + half : it * per_it + lane_id;
+    if (item >= n_items) break;
     const int y = item / KB, kb = item % KB;
     const int ny = y < M ? y : y - N;
     const int kz0 = kb * B;
@@ -335,31 +361,41 @@ __global__ __launch_bounds__(NT) void fft_x_bin_kernel(const T* __restrict__ gri
     __syncthreads();
     fft_passes<T, N, 1, COUNT, NT, 1>(buf, TS, tw);
 
-    // per-mode estimator; each thread walks RUN consecutive kx of one column
+    // per-mode estimator; each thread walks RUN consecutive kx of one column,
+    // with the column's y and z factors hoisted; sums are unweighted until a
+    // bin is flushed (the half-space weight is constant along the column)
     int cur = -1;
     double acc[kNumQ];
 #pragma unroll
     for (int q = 0; q < kNumQ; ++q) acc[q] = 0.0;
     const int m0 = threadIdx.x * RUN;
+    double wgt = 0.0;
     if (m0 < MODES) {
       const int c = m0 / N;
       const int nz = kz0 + c;
-      const double wgt = nz == 0 ? 1.0 : 2.0;
+      wgt = nz == 0 ? 1.0 : 2.0;
+      const int ay = ny < 0 ? -ny : ny;
+      const double col_iw = bp.no_deconv ? 1.0 : s_iwin2[ay] * s_iwin2[nz];
+      const double col_cal = s_alias[ay] * s_alias[nz];
+      const double ky_ = bp.kf * ny, kz_ = bp.kf * nz;
+      const double ksk0 = d.S[1] * ky_ * ky_ + d.S[2] * kz_ * kz_ + 2.0 * d.S[5] * ky_ * kz_;
+      const double ksk1 = 2.0 * (d.S[3] * ky_ + d.S[4] * kz_);
+      const int64_t n2yz = static_cast<int64_t>(ny) * ny + static_cast<int64_t>(nz) * nz;
+      const cpx<T>* col = buf + c * TS;
       for (int r = 0; r < RUN; ++r) {
         const int kx = (m0 % N) + r;
         const int nx = kx < M ? kx : kx - N;
-        const int64_t n2 = static_cast<int64_t>(nx) * nx + static_cast<int64_t>(ny) * ny +
-                           static_cast<int64_t>(nz) * nz;
+        const int64_t n2 = static_cast<int64_t>(nx) * nx + n2yz;
         if (n2 == 0 || n2 >= H2) continue;
         const int bin = lut[n2];
         if (bin < 0) continue;
-        const int ax = nx < 0 ? -nx : nx, ay = ny < 0 ? -ny : ny;
-        const double w2 = bp.no_deconv ? 1.0 : win2_tab[ax] * win2_tab[ay] * win2_tab[nz];
-        const double cal = alias_tab[ax] * alias_tab[ay] * alias_tab[nz];
-        const cpx<T> F0 = buf[(0 * B + c) * TS + kx];
-        const cpx<T> F1 = buf[(1 * B + c) * TS + kx];
-        const cpx<T> F2 = buf[(2 * B + c) * TS + kx];
-        const cpx<T> F3 = buf[(3 * B + c) * TS + kx];
+        const int ax = nx < 0 ? -nx : nx;
+        const double iw2 = bp.no_deconv ? 1.0 : col_iw * s_iwin2[ax];
+        const double cal = col_cal * s_alias[ax];
+        const cpx<T> F0 = col[kx];
+        const cpx<T> F1 = col[B * TS + kx];
+        const cpx<T> F2 = col[2 * B * TS + kx];
+        const cpx<T> F3 = col[3 * B * TS + kx];
         const double dr = static_cast<double>(F0.re) * d.inv_W, di = static_cast<double>(F0.im) * d.inv_W;
         double pxr = static_cast<double>(F1.re) * d.inv_W, pxi = static_cast<double>(F1.im) * d.inv_W;
         double pyr = static_cast<double>(F2.re) * d.inv_W, pyi = static_cast<double>(F2.im) * d.inv_W;
@@ -372,40 +408,36 @@ __global__ __launch_bounds__(NT) void fft_x_bin_kernel(const T* __restrict__ gri
           pzr -= d.vb[2] * dr;
           pzi -= d.vb[2] * di;
         }
-        const double kx_ = bp.kf * nx, ky_ = bp.kf * ny, kz_ = bp.kf * nz;
+        const double kx_ = bp.kf * nx;
         const double kpr = kx_ * pxr + ky_ * pyr + kz_ * pzr;
         const double kpi = kx_ * pxi + ky_ * pyi + kz_ * pzi;
-        const double iw2 = 1.0 / w2;
         const double raw_dd = (dr * dr + di * di) * iw2;
         const double raw_pp = (pxr * pxr + pxi * pxi + pyr * pyr + pyi * pyi + pzr * pzr + pzi * pzi) * iw2;
-        const double raw_tt = (kpr * kpr + kpi * kpi) * iw2 / haf2;
-        const double raw_dt = (dr * kpi - di * kpr) * iw2 / bp.haf;
-        const double ksk = d.S[0] * kx_ * kx_ + d.S[1] * ky_ * ky_ + d.S[2] * kz_ * kz_ +
-                           2.0 * (d.S[3] * kx_ * ky_ + d.S[4] * kx_ * kz_ + d.S[5] * ky_ * kz_);
-        const double sdd = d.s_dd * cal * iw2;
-        const double spp = d.s_pp * cal * iw2;
-        const double stt = ksk * cal * iw2 / haf2;
-        const double pdd = bp.no_shot ? raw_dd : raw_dd - sdd;
-        const double ppp = bp.no_shot ? raw_pp : raw_pp - spp;
-        const double ptt = bp.no_shot ? raw_tt : raw_tt - stt;
+        const double raw_tt = (kpr * kpr + kpi * kpi) * iw2 * bp.inv_haf2;
+        const double raw_dt = (dr * kpi - di * kpr) * iw2 * bp.inv_haf;
+        const double ksk = (d.S[0] * kx_ + ksk1) * kx_ + ksk0;
+        const double ciw = cal * iw2;
+        const double sdd = d.s_dd * ciw;
+        const double spp = d.s_pp * ciw;
+        const double stt = ksk * ciw * bp.inv_haf2;
         if (bin != cur) {
-          if (cur >= 0) flush_bin(lbins, cur, acc);
+          if (cur >= 0) flush_bin(lbins, cur, acc, wgt, bp.kf);
 #pragma unroll
           for (int q = 0; q < kNumQ; ++q) acc[q] = 0.0;
           cur = bin;
         }
-        acc[QCount] += wgt;
-        acc[QKsum] += wgt * bp.kf * sqrt(static_cast<double>(n2));
-        acc[QPdd] += wgt * pdd;
-        acc[QPpp] += wgt * ppp;
-        acc[QPtt] += wgt * ptt;
-        acc[QPdt] += wgt * raw_dt;
-        acc[QSdd] += wgt * sdd;
-        acc[QSpp] += wgt * spp;
-        acc[QStt] += wgt * stt;
+        acc[QCount] += 1.0;
+        acc[QKsum] += sqrt(static_cast<double>(n2));
+        acc[QPdd] += bp.no_shot ? raw_dd : raw_dd - sdd;
+        acc[QPpp] += bp.no_shot ? raw_pp : raw_pp - spp;
+        acc[QPtt] += bp.no_shot ? raw_tt : raw_tt - stt;
+        acc[QPdt] += raw_dt;
+        acc[QSdd] += sdd;
+        acc[QSpp] += spp;
+        acc[QStt] += stt;
       }
     }
-    if (cur >= 0) flush_bin(lbins, cur, acc);
+    if (cur >= 0) flush_bin(lbins, cur, acc, wgt, bp.kf);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < bp.n_bins * kNumQ; i += NT)
@@ -479,6 +511,8 @@ hipError_t run_x_bin(Plan* p, const mps_catalog* c, hipStream_t s) {
   BinParams bp;
   bp.kf = 2.0 * M_PI / c->box;
   bp.haf = c->haf;
+  bp.inv_haf = 1.0 / c->haf;
+  bp.inv_haf2 = bp.inv_haf * bp.inv_haf;
   bp.n_bins = c->n_bins;
   bp.no_shot = (c->flags & MPS_NO_SHOTNOISE) ? 1 : 0;
   bp.no_deconv = (c->flags & MPS_NO_DECONVOLVE) ? 1 : 0;

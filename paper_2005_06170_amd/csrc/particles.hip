@@ -202,24 +202,39 @@ __global__ __launch_bounds__(kCountThreads) void count_kernel(
 }
 
 // Fixed-order sum of the per-block moment partials, then the derived shot
-// and bulk-flow scalars.
-__global__ __launch_bounds__(64) void derive_kernel(const double* __restrict__ partials, int nblocks,
-                                                    ResultHeader* hdr, int bulk) {
+// and bulk-flow scalars.  One workgroup of kMomentBlocks threads: thread b
+// holds block b's partials and a fixed reduction tree combines them.
+__global__ __launch_bounds__(kMomentBlocks) void derive_kernel(const double* __restrict__ partials,
+                                                               ResultHeader* hdr, int bulk) {
+  constexpr int kW = kMomentBlocks / 64;
+  __shared__ double red[kW][kMomentSums + kMomentMax];
   __shared__ double sums[kMomentSums];
   __shared__ double maxes[kMomentMax];
-  if (threadIdx.x < kMomentSums) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partials[b * kMomentSums + threadIdx.x];
-    sums[threadIdx.x] = s;
-    hdr->sums[threadIdx.x] = s;
-  } else if (threadIdx.x < kMomentSums + kMomentMax) {
-    const int q = threadIdx.x - kMomentSums;
-    double m = 0.0;
-    for (int b = 0; b < nblocks; ++b) m = fmax(m, partials[nblocks * kMomentSums + b * kMomentMax + q]);
-    maxes[q] = m;
+  const int b = threadIdx.x, wave = b >> 6, lane = b & 63;
+#pragma unroll
+  for (int q = 0; q < kMomentSums; ++q) {
+    const double v = wave_sum(partials[b * kMomentSums + q]);
+    if (lane == 0) red[wave][q] = v;
+  }
+#pragma unroll
+  for (int q = 0; q < kMomentMax; ++q) {
+    double m = partials[kMomentBlocks * kMomentSums + b * kMomentMax + q];
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (lane == 0) red[wave][kMomentSums + q] = m;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (b < kMomentSums) {
+    double v = 0.0;
+    for (int w = 0; w < kW; ++w) v += red[w][b];
+    sums[b] = v;
+    hdr->sums[b] = v;
+  } else if (b < kMomentSums + kMomentMax) {
+    double m = 0.0;
+    for (int w = 0; w < kW; ++w) m = fmax(m, red[w][b]);
+    maxes[b - kMomentSums] = m;
+  }
+  __syncthreads();
+  if (b != 0) return;
   Derived d;
   d.W = sums[0];
   d.W2 = sums[1];
@@ -898,7 +913,7 @@ hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
 }
 
 hipError_t launch_derive(Plan* p, const mps_catalog* c, hipStream_t s) {
-  derive_kernel<<<1, 64, 0, s>>>(p->moment_partials, kMomentBlocks, p->d_header,
+  derive_kernel<<<1, kMomentBlocks, 0, s>>>(p->moment_partials, p->d_header,
                                  (c->flags & MPS_BULKFLOW_SUBTRACT) ? 1 : 0);
   return hipGetLastError();
 }
