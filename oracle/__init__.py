@@ -6,6 +6,6 @@ GPU product path never calls it and shares no code with it.
 """
 from .estimator import (  # noqa: F401
     FLAG_BULKFLOW_SUBTRACT, FLAG_NO_DECONVOLVE, FLAG_NO_SHOTNOISE, Spectra,
-    assign, bin_modes, cell_and_fraction, default_bin_index, edge_thresholds,
+    assign, assign_cells, bin_modes, cell_and_fraction, default_bin_index, edge_thresholds,
     edges_bin_index, estimate, fourier_fields, mode_quantities, moments)
 from . import bl3  # noqa: F401

@@ -109,6 +109,33 @@ def assign(pos, charges, box: float, n_grid: int):
 
 
 # -------------------------------------------------------------- binning
+def assign_cells(pos, charges, box: float, n_grid: int, cells):
+    """Assigned grid values at the listed nodes only, from the definition.
+
+    G_c(g) = sum_p q_{c,p} phi_t(g_x - u_x) phi_t(g_y - u_y) phi_t(g_z - u_z)
+    with u = x N / L, the separation taken periodically and phi_t the BL3
+    function on its support (-3, 3] (Eq. rawFFTed with the BL3 window of
+    Sec. 2.4.1).  Each node is a direct sum over the particles, with no tap
+    decomposition; `cells` is an (m, 3) integer array; returns (n_charge, m).
+    """
+    charges = np.atleast_2d(np.asarray(charges, dtype=np.float64))
+    cells = np.atleast_2d(np.asarray(cells, dtype=np.int64))
+    cell, frac = cell_and_fraction(pos, box, n_grid)
+    out = np.zeros((charges.shape[0], cells.shape[0]))
+    half = n_grid // 2
+    for i, g in enumerate(cells):
+        # integer part of g - u, wrapped to [-N/2, N/2); g - u = d - f
+        d = (g[None, :] - cell + half) % n_grid - half
+        near = np.all((d >= -2) & (d <= 3), axis=1)
+        if not near.any():
+            continue
+        sep = d[near].astype(np.float64) - frac[near]
+        phi3 = (bl3.phi_trunc(sep[:, 0]) * bl3.phi_trunc(sep[:, 1])
+                * bl3.phi_trunc(sep[:, 2]))
+        out[:, i] = charges[:, near] @ phi3
+    return out
+
+
 def default_bin_index(n2, n_grid: int, n_bins: int = 32):
     """Linear bins of width k_N / n_bins on [0, k_N) by exact integers.
 

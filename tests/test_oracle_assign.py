@@ -83,3 +83,22 @@ def test_cell_index_wraps_periodically():
     assert cell.min() >= 0 and cell.max() < 64
     assert cell[0, 2] == 0 and cell[1, 1] == 0 and cell[1, 2] == 32
     assert np.all((frac >= 0) & (frac < 1))
+
+
+def test_single_node_sums_match_brute_force(rng):
+    """oracle.assign_cells (a per-node sum over particles, used to check the
+    library at full size on sampled nodes) equals the brute force at every
+    node of small grids, including wrapped particles."""
+    for n in (8, 16):
+        box = 100.0
+        pos = (rng.random((40, 3)) * box).astype(np.float32)
+        pos[0] = [0.0, 50.0, 12.5]
+        pos[1] = [box, 0.0, -25.0]
+        pos[2] = [-3.0, 99.999, 37.5]
+        q = rng.normal(size=(2, 40))
+        g = np.arange(n)
+        cells = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+        got = oracle.assign_cells(pos, q, box, n, cells)
+        for c in range(2):
+            want = _brute_force(pos, q[c], box, n).reshape(-1)
+            assert np.max(np.abs(got[c] - want)) < 1e-12 * np.max(np.abs(want)), (n, c)
