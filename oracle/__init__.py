@@ -9,3 +9,4 @@ from .estimator import (  # noqa: F401
     assign, assign_cells, bin_modes, cell_and_fraction, default_bin_index, edge_thresholds,
     edges_bin_index, estimate, fourier_fields, mode_quantities, moments)
 from . import bl3  # noqa: F401
+from .anisotropic import estimate_mu, mu_bin, unit_axis  # noqa: F401
