@@ -107,6 +107,39 @@ typedef struct {
   double n_eff;     /* W^2 / sum w^2 (= N for unit weights) */
 } mps_result;
 
+/* Results of mps_estimate_mu: the spectra of Sec. 3 binned in (k, mu_b),
+ * mu_b the cosine between k and a unit axis a (by default the bulk flow
+ * direction v_b / |v_b|).  Array members are caller-allocated host arrays of
+ * n_bins * n_mu values, element [b * n_mu + m] for k bin b and mu bin m
+ * (mu bins uniform on [-1, 1]); any may be NULL.  Complex cross spectra are
+ * given in the paper's Fourier convention (fields sum_j w_j ... e^{+ik.r_j},
+ * Eq. 4): P_dt = delta theta^* (Eq. rawPx) and P_dpb = delta conj(a.p')
+ * with p' the momentum of v - v_b (Eq. bfpp). */
+typedef struct {
+  double* k_mean;    /* mode-averaged |k| */
+  double* mu_mean;   /* mode-averaged mu_b */
+  double* p_pp;      /* as in mps_result */
+  double* p_tt;
+  double* p_dd;
+  double* p_dt_re;   /* Re P_delta-theta (no shot term) */
+  double* p_dt_im;   /* Im P_delta-theta, shot term subtracted */
+  double* p_dpb_re;  /* Re P_{delta p'_b}, shot term subtracted */
+  double* p_dpb_im;  /* Im P_{delta p'_b} (no shot term) */
+  double* sn_pp;     /* bin-averaged shot terms, after deconvolution */
+  double* sn_tt;
+  double* sn_dd;
+  double* sn_dt_im;  /* -(k.s) C / (Haf W^2), s = sum w^2 v / W^2 (v used) */
+  double* sn_dpb;    /* (a.s') C / W^2, s' = sum w^2 (v - v_b) / W^2 */
+  int64_t* n_modes;  /* modes in the cell (k and -k counted separately) */
+  double axis[3];    /* the unit axis used */
+  double v_bulk[3];
+  double sigma_v2;
+  double n_eff;
+} mps_result_mu;
+
+#define MPS_MAX_MU_BINS 64
+#define MPS_MAX_MU_CELLS 512   /* n_bins * n_mu */
+
 typedef struct mps_plan mps_plan;
 typedef struct mps_server mps_server;
 
@@ -134,6 +167,20 @@ int mps_estimate(mps_plan* plan, const mps_catalog* cat, mps_result* out,
  * launched together so that small catalogs share the device. */
 int mps_estimate_batch(mps_plan* const* plans, const mps_catalog* cats,
                        mps_result* outs, int n, hipStream_t stream);
+
+/* Anisotropic spectra (Sec. 3: the bulk-flow terms of Eqs. thetanoise,
+ * rawPx, bfpp and bfpdpx resolved by mu_b).  n_mu in [1, MPS_MAX_MU_BINS]
+ * with n_bins * n_mu <= MPS_MAX_MU_CELLS.  axis: host pointer to 3 doubles
+ * (need not be unit; must be non-zero), or NULL to use v_b, in which case a
+ * catalog with v_b = 0 exactly returns MPS_E_ARG.  mu is computed in FP64 as
+ * (n.a)/|n| with a = axis/|axis| and every operation separately rounded, and
+ * mode n goes to mu bin min(floor((mu + 1) n_mu / 2), n_mu - 1).  The flags
+ * act as in mps_estimate (MPS_BULKFLOW_SUBTRACT: p' replaces p in P_pp,
+ * P_tt and P_dt).  Same stream semantics as mps_estimate; the x transform is
+ * stored and binned by a separate pass, so the call costs one extra pass
+ * over the grid. */
+int mps_estimate_mu(mps_plan* plan, const mps_catalog* cat, int n_mu,
+                    const double* axis, mps_result_mu* out, hipStream_t stream);
 
 /* Diagnostics of the hot path's first stages, using the same kernels as
  * mps_estimate.  mps_assign writes the four assigned real grids

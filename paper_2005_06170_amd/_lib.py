@@ -35,6 +35,18 @@ class Result(C.Structure):
                 ("sigma_v2", C.c_double), ("n_eff", C.c_double)]
 
 
+MU_KEYS = ("k_mean", "mu_mean", "p_pp", "p_tt", "p_dd", "p_dt_re", "p_dt_im", "p_dpb_re",
+           "p_dpb_im", "sn_pp", "sn_tt", "sn_dd", "sn_dt_im", "sn_dpb")
+MAX_MU_BINS = 64
+MAX_MU_CELLS = 512
+
+
+class ResultMu(C.Structure):
+    _fields_ = ([(k, C.POINTER(C.c_double)) for k in MU_KEYS]
+                + [("n_modes", C.POINTER(C.c_int64)), ("axis", C.c_double * 3),
+                   ("v_bulk", C.c_double * 3), ("sigma_v2", C.c_double), ("n_eff", C.c_double)])
+
+
 class MpsError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
@@ -62,6 +74,7 @@ def lib():
         "mps_footprint": (C.c_size_t, [i32, i32, i64]),
         "mps_estimate": (i32, [vp, C.POINTER(Catalog), C.POINTER(Result), vp]),
         "mps_estimate_batch": (i32, [C.POINTER(vp), C.POINTER(Catalog), C.POINTER(Result), i32, vp]),
+        "mps_estimate_mu": (i32, [vp, C.POINTER(Catalog), i32, C.POINTER(dbl), C.POINTER(ResultMu), vp]),
         "mps_assign": (i32, [vp, C.POINTER(Catalog), vp, vp]),
         "mps_fft": (i32, [vp, vp, vp]),
         "mps_plan_set_timing": (i32, [vp, i32]),
@@ -102,7 +115,7 @@ def exported_symbols():
     """Names declared in include/mps.h that the loaded library exports."""
     L = lib()
     names = ["mps_plan_create", "mps_plan_destroy", "mps_plan_reserve", "mps_footprint",
-             "mps_estimate", "mps_estimate_batch", "mps_assign", "mps_fft",
+             "mps_estimate", "mps_estimate_batch", "mps_estimate_mu", "mps_assign", "mps_fft",
              "mps_plan_set_timing", "mps_plan_stage_times", "mps_server_create",
              "mps_submit", "mps_wait", "mps_server_destroy", "mps_strerror"]
     return {n: hasattr(L, n) for n in names}

@@ -141,6 +141,43 @@ class Plan:
         del keep
         return unpack_result(res, arrays, box, self.n_grid, k_edges, cat.n_bins)
 
+    def estimate_mu(self, pos, vel, weight=None, *, box, haf, n_mu, axis=None, n_bins=32,
+                    k_edges=None, bulk_flow=False, no_shotnoise=False, no_deconvolve=False,
+                    stream=None):
+        """(k, mu_b)-binned spectra (Sec. 3); arrays of shape (n_bins, n_mu).
+
+        mu_b is the cosine to `axis` (3 numbers) or, by default, to the bulk
+        flow.  Complex cross spectra follow the paper's Fourier convention.
+        """
+        cat, keep = make_catalog(pos, vel, weight, box=box, haf=haf, n_bins=n_bins,
+                                 k_edges=k_edges,
+                                 flags=_flags(bulk_flow, no_shotnoise, no_deconvolve))
+        nb = cat.n_bins
+        ncell = nb * int(n_mu)
+        arrays = {k: np.full(ncell, np.nan) for k in L.MU_KEYS}
+        arrays["n_modes"] = np.zeros(ncell, np.int64)
+        res = L.ResultMu()
+        for k in L.MU_KEYS:
+            setattr(res, k, arrays[k].ctypes.data_as(C.POINTER(C.c_double)))
+        res.n_modes = arrays["n_modes"].ctypes.data_as(C.POINTER(C.c_int64))
+        ax = None
+        if axis is not None:
+            ax = np.ascontiguousarray(axis, dtype=np.float64)
+            if ax.shape != (3,):
+                raise ValueError("axis must have 3 components")
+            keep.append(ax)
+        L.check(L.lib().mps_estimate_mu(
+            self._h, C.byref(cat), int(n_mu),
+            ax.ctypes.data_as(C.POINTER(C.c_double)) if ax is not None else None,
+            C.byref(res), _stream(stream)), "mps_estimate_mu")
+        del keep
+        out = {k: v.reshape(nb, int(n_mu)) for k, v in arrays.items()}
+        out["axis"] = np.array(res.axis[:])
+        out["v_bulk"] = np.array(res.v_bulk[:])
+        out["sigma_v2"] = float(res.sigma_v2)
+        out["n_eff"] = float(res.n_eff)
+        return out
+
     def assign(self, pos, vel, weight=None, *, box, bulk_flow=False, stream=None):
         """The four assigned real grids, torch tensor (4, N, N, N) [field, x, y, z]."""
         n = self.n_grid

@@ -61,6 +61,9 @@ void release(Plan* p) {
   dfree(p->d_lut);
   dfree(p->d_bin_partials);
   dfree(p->d_bins);
+  dfree(p->d_mu_partials);
+  dfree(p->d_mu_bins);
+  if (p->h_stage_mu) (void)hipHostFree(p->h_stage_mu);
   if (p->h_stage) (void)hipHostFree(p->h_stage);
   for (auto& e : p->ev)
     if (e) (void)hipEventDestroy(e);
@@ -301,6 +304,90 @@ int mps_estimate(mps_plan* plan, const mps_catalog* cat, mps_result* out, hipStr
   if ((st = enqueue_estimate(p, cat, stream)) != MPS_OK) return st;
   if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
   return unpack(p, cat, out);
+}
+
+int mps_estimate_mu(mps_plan* plan, const mps_catalog* cat, int n_mu, const double* axis, mps_result_mu* out,
+                    hipStream_t stream) {
+  if (!plan || !out) return MPS_E_ARG;
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  int st = validate_catalog(p, cat);
+  if (st != MPS_OK) return st;
+  if (n_mu < 1 || n_mu > MPS_MAX_MU_BINS || cat->n_bins * n_mu > kMaxMuCells) return MPS_E_ARG;
+  // the unit axis, rounded operation by operation as documented (no fused
+  // multiply-adds), so that every mode's mu bin is reproducible
+#pragma clang fp contract(off)
+  double ahat[3] = {0.0, 0.0, 0.0};
+  if (axis) {
+    const double nrm = std::sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return MPS_E_ARG;
+    for (int a = 0; a < 3; ++a) ahat[a] = axis[a] / nrm;
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return MPS_E_HIP;
+  if (!p->d_mu_partials) {
+    const size_t cells = static_cast<size_t>(kMaxMuCells) * kNumQMu;
+    bool ok = dalloc(&p->d_mu_partials, sizeof(double) * cells * p->num_cus) == hipSuccess;
+    ok = ok && dalloc(&p->d_mu_bins, sizeof(double) * cells) == hipSuccess;
+    ok = ok && hipHostMalloc(&p->h_stage_mu, sizeof(ResultHeader) + sizeof(double) * cells,
+                             hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+      dfree(p->d_mu_partials);
+      dfree(p->d_mu_bins);
+      if (p->h_stage_mu) (void)hipHostFree(p->h_stage_mu);
+      p->d_mu_partials = nullptr;
+      p->d_mu_bins = nullptr;
+      p->h_stage_mu = nullptr;
+      return MPS_E_NOMEM;
+    }
+  }
+  if ((st = ensure_bins(p, cat)) != MPS_OK) return st;
+  if ((st = ensure_particles(p, cat->n_particles)) != MPS_OK) return st;
+  if ((st = enqueue_particles(p, cat, stream, 0)) != MPS_OK) return st;
+  MPS_TRY(launch_fft_z(p, p->grid, stream));
+  mark(p, 6, stream);
+  MPS_TRY(launch_fft_y(p, p->grid, stream));
+  mark(p, 7, stream);
+  MPS_TRY(launch_fft_x_store(p, p->grid, stream));
+  MPS_TRY(launch_mu_bin(p, cat, n_mu, axis ? ahat : nullptr, stream));
+  mark(p, 8, stream);
+  MPS_TRY(launch_finalize_mu(p, cat, n_mu, stream));
+  mark(p, 9, stream);
+  const int ncell = cat->n_bins * n_mu;
+  MPS_TRY(hipMemcpyAsync(p->h_stage_mu, p->d_header, sizeof(ResultHeader), hipMemcpyDeviceToHost, stream));
+  MPS_TRY(hipMemcpyAsync(static_cast<char*>(p->h_stage_mu) + sizeof(ResultHeader), p->d_mu_bins,
+                         sizeof(double) * kNumQMu * ncell, hipMemcpyDeviceToHost, stream));
+  if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
+
+  const ResultHeader* h = static_cast<const ResultHeader*>(p->h_stage_mu);
+  if ((st = check_header(h)) != MPS_OK) return st;
+  if (!axis) {
+    const double* vb = h->d.vb;
+    const double nrm = std::sqrt(vb[0] * vb[0] + vb[1] * vb[1] + vb[2] * vb[2]);
+    if (!(nrm > 0.0)) return MPS_E_ARG;  // no bulk flow to define mu_b
+    for (int a = 0; a < 3; ++a) ahat[a] = vb[a] / nrm;
+  }
+  const double* cells = reinterpret_cast<const double*>(static_cast<const char*>(p->h_stage_mu) + sizeof(ResultHeader));
+  for (int i = 0; i < ncell; ++i) {
+    const double* q = cells + static_cast<size_t>(i) * kNumQMu;
+    if (out->n_modes) out->n_modes[i] = static_cast<int64_t>(std::llround(q[MCount]));
+    double* dst[] = {out->k_mean, out->mu_mean, out->p_dd, out->p_pp, out->p_tt, out->p_dt_re, out->p_dt_im,
+                     out->p_dpb_re, out->p_dpb_im, out->sn_dd, out->sn_pp, out->sn_tt, out->sn_dt_im, out->sn_dpb};
+    const int src[] = {MKsum, MMusum, MPdd, MPpp, MPtt, MPdtRe, MPdtIm, MPdpbRe, MPdpbIm, MSdd, MSpp, MStt,
+                       MSdtIm, MSdpb};
+    for (int k = 0; k < 14; ++k)
+      if (dst[k]) dst[k][i] = q[src[k]];
+  }
+  for (int a = 0; a < 3; ++a) {
+    out->axis[a] = ahat[a];
+    out->v_bulk[a] = h->d.vb[a];
+  }
+  out->sigma_v2 = h->d.sigma_v2;
+  out->n_eff = h->d.W * h->d.W / h->d.W2;
+  if (p->timing)
+    for (int i = 0; i < kNumStages; ++i) {
+      float ms = 0.f;
+      p->stage_ms[i] = hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]) == hipSuccess ? ms : -1.0;
+    }
+  return MPS_OK;
 }
 
 int mps_estimate_batch(mps_plan* const* plans, const mps_catalog* cats, mps_result* outs, int n,

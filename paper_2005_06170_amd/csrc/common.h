@@ -22,6 +22,13 @@ constexpr int kNumStages = 9;
 // Per-bin accumulators, in order.
 enum BinQ { QCount = 0, QKsum, QPdd, QPpp, QPtt, QPdt, QSdd, QSpp, QStt };
 
+// Per-(k, mu) cell accumulators of the anisotropic estimate, in order.
+enum MuQ {
+  MCount = 0, MKsum, MMusum, MPdd, MPpp, MPtt, MPdtRe, MPdtIm, MPdpbRe, MPdpbIm,
+  MSdd, MSpp, MStt, MSdtIm, MSdpb, kNumQMu
+};
+constexpr int kMaxMuCells = MPS_MAX_MU_CELLS;
+
 // Polynomial weights of the six taps: w_j(f) = sum_p coef[j][p] f^p with
 // f = u - floor(u) in [0, 1).  FP64.
 struct TapPoly {
@@ -43,6 +50,8 @@ struct Derived {
   double inv_W;          // 1 / W
   double sigma_v2;       // trace(sum w^2 v v^T) / W2 of the velocities used
   double qmax[kNumFields];  // max |w|, max |w v_a| over the catalog
+  double s[3];           // sum w^2 v / W^2 of the velocities used
+  double sp[3];          // sum w^2 (v - v_b) / W^2
   int bulk;              // 1 if p is replaced by p - v_b delta
 };
 
@@ -96,6 +105,11 @@ struct Plan {
   double* d_bins = nullptr;          // kMaxBins x kNumQ (final sums)
   int bin_blocks = 0;
 
+  // anisotropic estimate (allocated on first use)
+  double* d_mu_partials = nullptr;   // bin_blocks x kMaxMuCells x kNumQMu
+  double* d_mu_bins = nullptr;       // kMaxMuCells x kNumQMu
+  void* h_stage_mu = nullptr;        // pinned: header + kMaxMuCells x kNumQMu
+
   // host staging (pinned): header + bins
   void* h_stage = nullptr;
   size_t stage_bytes = 0;
@@ -138,5 +152,9 @@ hipError_t launch_fft_y(Plan* p, void* grid, hipStream_t s);
 hipError_t launch_fft_x_store(Plan* p, void* grid, hipStream_t s);
 hipError_t launch_fft_x_bin(Plan* p, const mps_catalog* c, hipStream_t s);
 hipError_t launch_finalize(Plan* p, const mps_catalog* c, hipStream_t s);
+// (k, mu) binning of the stored transform; axis is a host unit vector or
+// NULL for the bulk-flow direction (computed on the device).
+hipError_t launch_mu_bin(Plan* p, const mps_catalog* c, int n_mu, const double* axis, hipStream_t s);
+hipError_t launch_finalize_mu(Plan* p, const mps_catalog* c, int n_mu, hipStream_t s);
 
 }  // namespace mps

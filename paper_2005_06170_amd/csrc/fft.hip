@@ -444,6 +444,211 @@ __global__ __launch_bounds__(NT) void fft_x_bin_kernel(const T* __restrict__ gri
     partials[static_cast<int64_t>(blockIdx.x) * kMaxBins * kNumQ + i] = lbins[i];
 }
 
+// ------------------------------------------- anisotropic (k, mu_b) binning
+struct MuParams {
+  double kf, inv_haf, inv_haf2;
+  double axis[3];   // unit axis from the host, if axis_given
+  int axis_given;
+  int n_bins, n_mu, no_shot, no_deconv, bulk;
+};
+
+// Running sums of one (k, mu) cell, flushed to the workgroup's LDS cells
+// when the cell changes.
+struct MuRun {
+  int cell = -1;
+  double q[kNumQMu];
+  __device__ void reset(int c) {
+    cell = c;
+#pragma unroll
+    for (int i = 0; i < kNumQMu; ++i) q[i] = 0.0;
+  }
+  __device__ void flush(double* lbins) const {
+    if (cell < 0) return;
+#pragma unroll
+    for (int i = 0; i < kNumQMu; ++i) atomicAdd(lbins + cell * kNumQMu + i, q[i]);
+  }
+};
+
+// mu = (n.a) / |n| with each operation rounded separately, and its bin
+// min(floor((mu + 1) n_mu / 2), n_mu - 1) clamped at 0.
+__device__ __forceinline__ int mu_cell(double mu, int n_mu) {
+  const double t = __dmul_rn(__dadd_rn(mu, 1.0), 0.5 * n_mu);
+  int m = static_cast<int>(floor(t));
+  m = m < 0 ? 0 : m;
+  return m > n_mu - 1 ? n_mu - 1 : m;
+}
+
+// Every stored mode (kx, ky, kz < N/2) of the fully transformed grid, with
+// kz > 0 modes also standing for -n (real fields: F(-n) = conj F(n), so the
+// auto spectra and real parts repeat and the imaginary parts change sign).
+// Each thread walks RUN consecutive kz of one (kx, ky) row.  Per mode, in
+// the paper's Fourier convention (fields e^{+ik.r}, the complex conjugates
+// of the stored e^{-ik.r} transforms):
+//   Re P_dt = (dr kpi - di kpr) / (Haf W^2),  Im P_dt = -(dr kpr + di kpi) /
+//   (Haf W^2) less its shot term -(k.s) C / (Haf W^2) (Eq. rawPx),
+//   P_dpb = (dr pbr + di pbi, dr pbi - di pbr) / W^2 with pb = a.(p - v_b
+//   delta), the real part less (a.s') C / W^2 (Eq. bfpp),
+// and P_dd, P_pp, P_tt as in the isotropic pass.
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void mu_bin_kernel(const T* __restrict__ grid, const ResultHeader* __restrict__ hdr,
+                                                    const double* __restrict__ iwin2_tab,
+                                                    const double* __restrict__ alias_tab,
+                                                    const int32_t* __restrict__ lut, MuParams mp,
+                                                    double* __restrict__ partials) {
+  constexpr int M = N / 2;
+  constexpr int RUN = M >= 8 ? 8 : M;
+  constexpr int CH = M / RUN;
+  constexpr int64_t H2 = static_cast<int64_t>(M) * M;
+  __shared__ double lbins[kMaxMuCells * kNumQMu];
+  __shared__ double s_iwin2[M + 1], s_alias[M + 1];
+  for (int i = threadIdx.x; i < kMaxMuCells * kNumQMu; i += NT) lbins[i] = 0.0;
+  for (int i = threadIdx.x; i <= M; i += NT) {
+    s_iwin2[i] = mp.no_deconv ? 1.0 : iwin2_tab[i];
+    s_alias[i] = alias_tab[i];
+  }
+  __syncthreads();
+  const Derived d = hdr->d;
+  double a0, a1, a2;
+  if (mp.axis_given) {
+    a0 = mp.axis[0];
+    a1 = mp.axis[1];
+    a2 = mp.axis[2];
+  } else {
+    const double nrm =
+        __dsqrt_rn(__dadd_rn(__dadd_rn(__dmul_rn(d.vb[0], d.vb[0]), __dmul_rn(d.vb[1], d.vb[1])),
+                             __dmul_rn(d.vb[2], d.vb[2])));
+    a0 = nrm > 0.0 ? __ddiv_rn(d.vb[0], nrm) : 0.0;
+    a1 = nrm > 0.0 ? __ddiv_rn(d.vb[1], nrm) : 0.0;
+    a2 = nrm > 0.0 ? __ddiv_rn(d.vb[2], nrm) : 0.0;
+  }
+  const double sa = (d.sp[0] * a0 + d.sp[1] * a1) + d.sp[2] * a2;   // a.s'
+  const int64_t fstride = static_cast<int64_t>(N) * N * M;
+  const cpx<T>* g = reinterpret_cast<const cpx<T>*>(grid);
+  const int64_t items = static_cast<int64_t>(N) * N * CH;
+  for (int64_t it = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; it < items;
+       it += static_cast<int64_t>(gridDim.x) * NT) {
+    const int ch = static_cast<int>(it % CH);
+    const int64_t row = it / CH;
+    const int ky = static_cast<int>(row % N), kx = static_cast<int>(row / N);
+    const int nx = kx < M ? kx : kx - N, ny = ky < M ? ky : ky - N;
+    const int nz0 = ch * RUN;
+    const int64_t n2xy = static_cast<int64_t>(nx) * nx + static_cast<int64_t>(ny) * ny;
+    if (n2xy + static_cast<int64_t>(nz0) * nz0 >= H2) continue;
+    const int ax = nx < 0 ? -nx : nx, ay = ny < 0 ? -ny : ny;
+    const double col_iw = s_iwin2[ax] * s_iwin2[ay];
+    const double col_cal = s_alias[ax] * s_alias[ay];
+    const double kx_ = mp.kf * nx, ky_ = mp.kf * ny;
+    const cpx<T>* base = g + row * M;
+    MuRun ra, rb;
+    for (int r = 0; r < RUN; ++r) {
+      const int nz = nz0 + r;
+      const int64_t n2 = n2xy + static_cast<int64_t>(nz) * nz;
+      if (n2 == 0 || n2 >= H2) continue;
+      const int kb = lut[n2];
+      if (kb < 0) continue;
+      const double iw2 = col_iw * s_iwin2[nz];
+      const double cal = col_cal * s_alias[nz];
+      const cpx<T> F0 = base[nz], F1 = base[fstride + nz], F2 = base[2 * fstride + nz],
+                   F3 = base[3 * fstride + nz];
+      const double dr = static_cast<double>(F0.re) * d.inv_W, di = static_cast<double>(F0.im) * d.inv_W;
+      const double qxr = static_cast<double>(F1.re) * d.inv_W, qxi = static_cast<double>(F1.im) * d.inv_W;
+      const double qyr = static_cast<double>(F2.re) * d.inv_W, qyi = static_cast<double>(F2.im) * d.inv_W;
+      const double qzr = static_cast<double>(F3.re) * d.inv_W, qzi = static_cast<double>(F3.im) * d.inv_W;
+      // p' = p - v_b delta (exact by linearity of the assignment)
+      const double bxr = qxr - d.vb[0] * dr, bxi = qxi - d.vb[0] * di;
+      const double byr = qyr - d.vb[1] * dr, byi = qyi - d.vb[1] * di;
+      const double bzr = qzr - d.vb[2] * dr, bzi = qzi - d.vb[2] * di;
+      const double pxr = mp.bulk ? bxr : qxr, pxi = mp.bulk ? bxi : qxi;
+      const double pyr = mp.bulk ? byr : qyr, pyi = mp.bulk ? byi : qyi;
+      const double pzr = mp.bulk ? bzr : qzr, pzi = mp.bulk ? bzi : qzi;
+      const double kz_ = mp.kf * nz;
+      const double kpr = kx_ * pxr + ky_ * pyr + kz_ * pzr;
+      const double kpi = kx_ * pxi + ky_ * pyi + kz_ * pzi;
+      const double pbr = a0 * bxr + a1 * byr + a2 * bzr;
+      const double pbi = a0 * bxi + a1 * byi + a2 * bzi;
+      const double ciw = cal * iw2;
+      const double raw_dd = (dr * dr + di * di) * iw2;
+      const double raw_pp = (pxr * pxr + pxi * pxi + pyr * pyr + pyi * pyi + pzr * pzr + pzi * pzi) * iw2;
+      const double raw_tt = (kpr * kpr + kpi * kpi) * iw2 * mp.inv_haf2;
+      const double dt_re = (dr * kpi - di * kpr) * iw2 * mp.inv_haf;
+      const double dt_im = -(dr * kpr + di * kpi) * iw2 * mp.inv_haf;
+      const double dpb_re = (dr * pbr + di * pbi) * iw2;
+      const double dpb_im = (dr * pbi - di * pbr) * iw2;
+      const double ksk = d.S[0] * kx_ * kx_ + d.S[1] * ky_ * ky_ + d.S[2] * kz_ * kz_ +
+                         2.0 * (d.S[3] * kx_ * ky_ + d.S[4] * kx_ * kz_ + d.S[5] * ky_ * kz_);
+      const double sdd = d.s_dd * ciw, spp = d.s_pp * ciw, stt = ksk * ciw * mp.inv_haf2;
+      const double sdt = -(kx_ * d.s[0] + ky_ * d.s[1] + kz_ * d.s[2]) * ciw * mp.inv_haf;
+      const double sdpb = sa * ciw;
+      const double pdd = mp.no_shot ? raw_dd : raw_dd - sdd;
+      const double ppp = mp.no_shot ? raw_pp : raw_pp - spp;
+      const double ptt = mp.no_shot ? raw_tt : raw_tt - stt;
+      const double pim = mp.no_shot ? dt_im : dt_im - sdt;
+      const double pbre = mp.no_shot ? dpb_re : dpb_re - sdpb;
+      const double kmag = mp.kf * sqrt(static_cast<double>(n2));
+      const double mu = __ddiv_rn(__dadd_rn(__dadd_rn(__dmul_rn(static_cast<double>(nx), a0),
+                                                      __dmul_rn(static_cast<double>(ny), a1)),
+                                            __dmul_rn(static_cast<double>(nz), a2)),
+                                  __dsqrt_rn(static_cast<double>(n2)));
+      // this mode and, for kz > 0, its mirror -n
+      for (int side = 0; side < (nz > 0 ? 2 : 1); ++side) {
+        const double sg = side ? -1.0 : 1.0;
+        const double mus = side ? -mu : mu;
+        const int cell = kb * mp.n_mu + mu_cell(mus, mp.n_mu);
+        MuRun& run = side ? rb : ra;
+        if (cell != run.cell) {
+          run.flush(lbins);
+          run.reset(cell);
+        }
+        run.q[MCount] += 1.0;
+        run.q[MKsum] += kmag;
+        run.q[MMusum] += mus;
+        run.q[MPdd] += pdd;
+        run.q[MPpp] += ppp;
+        run.q[MPtt] += ptt;
+        run.q[MPdtRe] += dt_re;
+        run.q[MPdtIm] += sg * pim;
+        run.q[MPdpbRe] += pbre;
+        run.q[MPdpbIm] += sg * dpb_im;
+        run.q[MSdd] += sdd;
+        run.q[MSpp] += spp;
+        run.q[MStt] += stt;
+        run.q[MSdtIm] += sg * sdt;
+        run.q[MSdpb] += sdpb;
+      }
+    }
+    ra.flush(lbins);
+    rb.flush(lbins);
+  }
+  __syncthreads();
+  const int ncell = mp.n_bins * mp.n_mu;
+  for (int i = threadIdx.x; i < ncell * kNumQMu; i += NT)
+    partials[static_cast<int64_t>(blockIdx.x) * kMaxMuCells * kNumQMu + i] = lbins[i];
+}
+
+// Fixed-order sum of the (k, mu) partials, then means (times V); empty cells
+// NaN.
+__global__ __launch_bounds__(256) void finalize_mu_kernel(const double* __restrict__ partials, int nblocks,
+                                                          int ncell, double volume, double* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= ncell) return;
+  double s[kNumQMu];
+#pragma unroll
+  for (int q = 0; q < kNumQMu; ++q) s[q] = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    const double* pb = partials + (static_cast<int64_t>(b) * kMaxMuCells + c) * kNumQMu;
+#pragma unroll
+    for (int q = 0; q < kNumQMu; ++q) s[q] += pb[q];
+  }
+  const double cnt = s[MCount];
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  const double inv = cnt > 0 ? 1.0 / cnt : 0.0;
+  double* o = out + static_cast<int64_t>(c) * kNumQMu;
+  o[MCount] = cnt;
+  o[MKsum] = cnt > 0 ? s[MKsum] * inv : nan;
+  o[MMusum] = cnt > 0 ? s[MMusum] * inv : nan;
+  for (int q = MPdd; q < kNumQMu; ++q) o[q] = cnt > 0 ? volume * s[q] * inv : nan;
+}
+
 // Fixed-order reduction of the workgroup partials and the final per-bin
 // means (times V = L^3); empty bins are NaN.
 __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ partials, int nblocks,
@@ -523,6 +728,39 @@ hipError_t run_x_bin(Plan* p, const mps_catalog* c, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int N>
+hipError_t run_mu_bin(Plan* p, const mps_catalog* c, int n_mu, const double* axis, hipStream_t s) {
+  MuParams mp;
+  mp.kf = 2.0 * M_PI / c->box;
+  mp.inv_haf = 1.0 / c->haf;
+  mp.inv_haf2 = mp.inv_haf * mp.inv_haf;
+  mp.axis_given = axis ? 1 : 0;
+  for (int a = 0; a < 3; ++a) mp.axis[a] = axis ? axis[a] : 0.0;
+  mp.n_bins = c->n_bins;
+  mp.n_mu = n_mu;
+  mp.no_shot = (c->flags & MPS_NO_SHOTNOISE) ? 1 : 0;
+  mp.no_deconv = (c->flags & MPS_NO_DECONVOLVE) ? 1 : 0;
+  mp.bulk = (c->flags & MPS_BULKFLOW_SUBTRACT) ? 1 : 0;
+  mu_bin_kernel<T, N, 512><<<static_cast<unsigned>(p->num_cus), 512, 0, s>>>(
+      static_cast<const T*>(p->grid), p->d_header, p->d_win2, p->d_alias, p->d_lut, mp, p->d_mu_partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_mu(Plan* p, const mps_catalog* c, int n_mu, const double* axis, hipStream_t s) {
+  switch (p->n) {
+    case 8: return run_mu_bin<T, 8>(p, c, n_mu, axis, s);
+    case 16: return run_mu_bin<T, 16>(p, c, n_mu, axis, s);
+    case 32: return run_mu_bin<T, 32>(p, c, n_mu, axis, s);
+    case 64: return run_mu_bin<T, 64>(p, c, n_mu, axis, s);
+    case 128: return run_mu_bin<T, 128>(p, c, n_mu, axis, s);
+    case 256: return run_mu_bin<T, 256>(p, c, n_mu, axis, s);
+    case 512: return run_mu_bin<T, 512>(p, c, n_mu, axis, s);
+    case 1024: return run_mu_bin<T, 1024>(p, c, n_mu, axis, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t dispatch_z(Plan* p, void* g, hipStream_t s) {
   switch (p->n) {
@@ -584,6 +822,17 @@ hipError_t launch_fft_x_store(Plan* p, void* grid, hipStream_t s) {
 
 hipError_t launch_fft_x_bin(Plan* p, const mps_catalog* c, hipStream_t s) {
   return p->prec == MPS_F32 ? dispatch_x_bin<float>(p, c, s) : dispatch_x_bin<double>(p, c, s);
+}
+
+hipError_t launch_mu_bin(Plan* p, const mps_catalog* c, int n_mu, const double* axis, hipStream_t s) {
+  return p->prec == MPS_F32 ? dispatch_mu<float>(p, c, n_mu, axis, s) : dispatch_mu<double>(p, c, n_mu, axis, s);
+}
+
+hipError_t launch_finalize_mu(Plan* p, const mps_catalog* c, int n_mu, hipStream_t s) {
+  const int ncell = c->n_bins * n_mu;
+  const double vol = c->box * c->box * c->box;
+  finalize_mu_kernel<<<(ncell + 255) / 256, 256, 0, s>>>(p->d_mu_partials, p->num_cus, ncell, vol, p->d_mu_bins);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(Plan* p, const mps_catalog* c, hipStream_t s) {

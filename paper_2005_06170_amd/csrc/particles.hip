@@ -254,6 +254,11 @@ __global__ __launch_bounds__(kMomentBlocks) void derive_kernel(const double* __r
       m2[q] = m2[q] - s[ia[q]] * vb[ib[q]] - vb[ia[q]] * s[ib[q]] + d.W2 * vb[ia[q]] * vb[ib[q]];
   }
   for (int q = 0; q < 6; ++q) d.S[q] = m2[q] * iw2;
+  // sum w^2 (v - v_b) = sum w^2 v - v_b W2
+  for (int a = 0; a < 3; ++a) {
+    d.sp[a] = (sums[5 + a] - d.vb[a] * d.W2) * iw2;
+    d.s[a] = bulk ? d.sp[a] : sums[5 + a] * iw2;
+  }
   d.s_pp = d.S[0] + d.S[1] + d.S[2];
   d.inv_W = iw;
   d.sigma_v2 = (m2[0] + m2[1] + m2[2]) / d.W2;

@@ -29,3 +29,34 @@ def compare_spectra(g, o, tol, label=""):
     bad = {k: v for k, v in errs.items() if not v <= tol}
     assert not bad, (label, errs)
     return errs
+
+
+MU_GUARDS = {"p_dd": ("sn_dd",), "p_pp": ("sn_pp",), "p_tt": ("sn_tt",),
+             "p_dt_re": ("sn_dd", "sn_tt"), "p_dt_im": ("sn_dd", "sn_tt"),
+             "p_dpb_re": ("sn_dd", "sn_pp"), "p_dpb_im": ("sn_dd", "sn_pp")}
+
+
+def compare_mu(g, o, tol, label=""):
+    """(k, mu) cells of the library against oracle.estimate_mu: exact mode
+    counts, NaN in the same empty cells, guarded errors for the spectra (the
+    guard of a cross spectrum is the geometric mean of its two shot terms)."""
+    assert np.array_equal(g["n_modes"], o["n_modes"]), (label, g["n_modes"], o["n_modes"])
+    empty = o["n_modes"] == 0
+    full = ~empty
+    for key in MU_GUARDS:
+        assert np.all(np.isnan(g[key][empty])), (label, key)
+    assert np.allclose(g["k_mean"][full], o["k_mean"][full], rtol=1e-12), label
+    assert np.allclose(g["mu_mean"][full], o["mu_mean"][full], rtol=1e-12, atol=1e-12), label
+    errs = {}
+    for key, guards in MU_GUARDS.items():
+        sn = np.sqrt(np.prod([np.abs(o[k]) for k in guards], axis=0))
+        errs[key] = float(np.max(guarded_rel(g[key], o[key], sn)))
+    for key in ("sn_dd", "sn_pp", "sn_tt", "sn_dt_im"):
+        ref = np.abs(o[key][full]).max()
+        errs[key] = float(np.max(np.abs(g[key][full] - o[key][full])) / ref) if ref > 0 else 0.0
+    ref = np.sqrt(np.abs(o["sn_dd"][full] * o["sn_pp"][full]))
+    errs["sn_dpb"] = float(np.max(np.abs(g["sn_dpb"][full] - o["sn_dpb"][full]) / ref))
+    print(f"{label} max guarded error: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, (label, errs)
+    return errs
