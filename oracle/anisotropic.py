@@ -36,7 +36,6 @@ import math
 
 import numpy as np
 
-from . import bl3
 from . import estimator as E
 
 
@@ -61,12 +60,12 @@ def mu_bin(nx, ny, nz, n2, ahat, n_mu):
 
 
 def estimate_mu(pos, vel, weight=None, *, box, n_grid, haf, n_mu, axis=None,
-                k_edges=None, n_bins=32, flags=0, keep_modes=False):
+                k_edges=None, n_bins=32, flags=0, keep_modes=False, kernel="bl3"):
     """(k, mu_b)-binned spectra; arrays of shape (n_bins, n_mu), times V.
     keep_modes adds the per-mode arrays (full N^3 cube, before binning)."""
     bulk = bool(flags & E.FLAG_BULKFLOW_SUBTRACT)
-    mom, mom_used, F = E.fourier_fields(pos, vel, weight, box, n_grid, bulk)
-    q = E.mode_quantities(F, mom_used, box, n_grid, haf, flags)
+    mom, mom_used, F = E.fourier_fields(pos, vel, weight, box, n_grid, bulk, kernel)
+    q = E.mode_quantities(F, mom_used, box, n_grid, haf, flags, kernel)
     W = mom["W"]
     vb = mom["sv"] / W
     ahat = unit_axis(vb if axis is None else axis)
@@ -75,7 +74,7 @@ def estimate_mu(pos, vel, weight=None, *, box, n_grid, haf, n_mu, axis=None,
     if bulk:
         mom_p, Fp = mom_used, F
     else:
-        _, mom_p, Fp = E.fourier_fields(pos, vel, weight, box, n_grid, True)
+        _, mom_p, Fp = E.fourier_fields(pos, vel, weight, box, n_grid, True, kernel)
 
     n = n_grid
     kf = 2.0 * math.pi / box
@@ -83,12 +82,9 @@ def estimate_mu(pos, vel, weight=None, *, box, n_grid, haf, n_mu, axis=None,
     nx, ny, nz = np.meshgrid(nf, nf, nf, indexing="ij")
     n2 = nx * nx + ny * ny + nz * nz
     kvec = kf * np.stack([nx, ny, nz]).astype(np.float64)
-    omega = 2.0 * math.pi * nf / n
+    w1, c1 = E.axis_tables(n, kernel)
     if flags & E.FLAG_NO_DECONVOLVE:
         w1 = np.ones(n)
-    else:
-        w1 = bl3.window_trunc(omega) ** 2
-    c1 = bl3.alias_sum_trunc(omega)
     win2 = w1[:, None, None] * w1[None, :, None] * w1[None, None, :]
     calias = c1[:, None, None] * c1[None, :, None] * c1[None, None, :]
 

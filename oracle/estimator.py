@@ -80,14 +80,25 @@ def cell_and_fraction(pos, box: float, n_grid: int):
     return cell, frac
 
 
-def assign(pos, charges, box: float, n_grid: int):
+KERNELS = ("bl3", "bl3_exact")
+
+
+def assign(pos, charges, box: float, n_grid: int, kernel: str = "bl3"):
     """Assign charges q[c, j] of particles j to 4 periodic grids with BL3.
+
+    kernel "bl3" (default) is the six-tap truncated function described below;
+    "bl3_exact" is the untruncated function (oracle.exact_bl3).
 
     Each particle deposits q * phi(jx - fx) phi(jy - fy) phi(jz - fz) on node
     (cell + (jx, jy, jz)) mod N for every tap j in {-2..3}^3 (Eq. rawFFTed with
     the truncated BL3 window).  Returns float64 array (n_charge, N, N, N)
     indexed [c, x, y, z].
     """
+    if kernel == "bl3_exact":
+        from . import exact_bl3
+        return exact_bl3.assign_exact(pos, charges, box, n_grid)
+    if kernel != "bl3":
+        raise ValueError(f"unknown kernel {kernel!r}")
     charges = np.atleast_2d(np.asarray(charges, dtype=np.float64))
     cell, frac = cell_and_fraction(pos, box, n_grid)
     wts = [bl3.tap_weights(frac[:, a]) for a in range(3)]   # (6, n) each
@@ -195,7 +206,7 @@ def _integer_freqs(n_grid: int):
     return np.rint(np.fft.fftfreq(n_grid) * n_grid).astype(np.int64)
 
 
-def fourier_fields(pos, vel, weight, box, n_grid, bulk_flow=False):
+def fourier_fields(pos, vel, weight, box, n_grid, bulk_flow=False, kernel="bl3"):
     """Moments and full complex FFTs of the four assigned fields.
 
     Returns (mom, mom_used, F) with F[c] = FFT of the grid of charge c in
@@ -214,12 +225,22 @@ def fourier_fields(pos, vel, weight, box, n_grid, bulk_flow=False):
         v_used = vel - v_bulk[None, :]
     mom_used = moments(v_used, w)
     charges = np.stack([w, w * v_used[:, 0], w * v_used[:, 1], w * v_used[:, 2]])
-    grids = assign(pos, charges, box, n_grid)
+    grids = assign(pos, charges, box, n_grid, kernel)
     F = scipy.fft.fftn(grids, axes=(1, 2, 3), workers=-1)
     return mom, mom_used, F
 
 
-def mode_quantities(F, mom_used, box, n_grid, haf, flags=0):
+def axis_tables(n_grid: int, kernel: str = "bl3"):
+    """Per-axis window W(w)^2 and alias sum C(w) at w = 2 pi n / N."""
+    nf = _integer_freqs(n_grid)
+    omega = 2.0 * math.pi * nf / n_grid
+    if kernel == "bl3_exact":
+        # orthonormal phi: the alias sum of phi_hat^2 is 1
+        return bl3.phi_hat(omega) ** 2, np.ones(n_grid)
+    return bl3.window_trunc(omega) ** 2, bl3.alias_sum_trunc(omega)
+
+
+def mode_quantities(F, mom_used, box, n_grid, haf, flags=0, kernel="bl3"):
     """Per-mode estimator values over the full N^3 cube.
 
     Returns a dict of arrays with shape (N, N, N): integer n2, |k|, and the
@@ -236,12 +257,9 @@ def mode_quantities(F, mom_used, box, n_grid, haf, flags=0):
     n2 = nx * nx + ny * ny + nz * nz
     kmag = kf * np.sqrt(n2.astype(np.float64))
 
-    omega = 2.0 * math.pi * nf / n
+    w1, c1 = axis_tables(n, kernel)
     if flags & FLAG_NO_DECONVOLVE:
         w1 = np.ones(n)
-    else:
-        w1 = bl3.window_trunc(omega) ** 2
-    c1 = bl3.alias_sum_trunc(omega)
     win2 = w1[:, None, None] * w1[None, :, None] * w1[None, None, :]
     calias = c1[:, None, None] * c1[None, :, None] * c1[None, None, :]
 
@@ -302,13 +320,13 @@ def bin_modes(q, box, n_grid, k_edges=None, n_bins=32):
 
 
 def estimate(pos, vel, weight=None, *, box, n_grid, haf, k_edges=None,
-             n_bins=32, flags=0, keep_modes=False):
+             n_bins=32, flags=0, keep_modes=False, kernel="bl3"):
     """Binned P_pp, P_theta-theta, Re P_delta-theta and P_dd of one catalog."""
     if n_grid < 8 or n_grid & (n_grid - 1):
         raise ValueError("n_grid must be a power of two >= 8")
     bulk = bool(flags & FLAG_BULKFLOW_SUBTRACT)
-    mom, mom_used, F = fourier_fields(pos, vel, weight, box, n_grid, bulk)
-    q = mode_quantities(F, mom_used, box, n_grid, haf, flags)
+    mom, mom_used, F = fourier_fields(pos, vel, weight, box, n_grid, bulk, kernel)
+    q = mode_quantities(F, mom_used, box, n_grid, haf, flags, kernel)
     out = bin_modes(q, box, n_grid, k_edges, n_bins)
     W = mom["W"]
     extra = {"moments": mom, "moments_used": mom_used}
