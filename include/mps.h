@@ -69,7 +69,14 @@ typedef enum { MPS_F32 = 1, MPS_F64 = 2 } mps_precision;
 enum {
   MPS_BULKFLOW_SUBTRACT = 1u << 0, /* use v - v_b (Sec. 3.1) */
   MPS_NO_SHOTNOISE = 1u << 1,      /* report raw (deconvolved) spectra */
-  MPS_NO_DECONVOLVE = 1u << 2      /* do not divide by W_t(k)^2 */
+  MPS_NO_DECONVOLVE = 1u << 2,     /* do not divide by W_t(k)^2 */
+  /* Assign with the untruncated BL3 function phi = sum_n c_n beta3(x - n)
+   * (Sec. 2.4.1) instead of its six-tap truncation.  Since c_n is a periodic
+   * filter with transform A(w)^(-1/2), the deconvolved spectra equal those of
+   * the cubic B-spline assignment (4 taps) deconvolved by sinc^4(w/2) per
+   * axis, with the alias sum A(w) in the shot terms; that is what is
+   * computed.  mps_assign then returns the cubic B-spline grids. */
+  MPS_KERNEL_BL3_EXACT = 1u << 3
 };
 
 /* One catalog.  The caller owns every buffer; they must stay valid until the

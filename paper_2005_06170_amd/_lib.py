@@ -12,7 +12,8 @@ ERRORS = {-1: "MPS_E_ARG", -2: "MPS_E_NONFINITE", -3: "MPS_E_ZEROWEIGHT",
           -4: "MPS_E_NOMEM", -5: "MPS_E_HIP", -6: "MPS_E_TIMEOUT",
           -7: "MPS_E_BUSY", -8: "MPS_E_TOOBIG"}
 MPS_F32, MPS_F64 = 1, 2
-BULKFLOW_SUBTRACT, NO_SHOTNOISE, NO_DECONVOLVE = 1, 2, 4
+BULKFLOW_SUBTRACT, NO_SHOTNOISE, NO_DECONVOLVE, KERNEL_BL3_EXACT = 1, 2, 4, 8
+KERNELS = {"bl3": 0, "bl3_exact": KERNEL_BL3_EXACT}
 MAX_BINS = 128
 NUM_STAGES = 9
 STAGES = ("moments+count", "scan", "permute", "clear", "scatter",

@@ -40,9 +40,11 @@ def _device_f32(t, name, cols):
     return t
 
 
-def _flags(bulk_flow, no_shotnoise, no_deconvolve) -> int:
+def _flags(bulk_flow, no_shotnoise, no_deconvolve, kernel="bl3") -> int:
+    if kernel not in L.KERNELS:
+        raise ValueError(f"kernel must be one of {sorted(L.KERNELS)}")
     return ((L.BULKFLOW_SUBTRACT if bulk_flow else 0) | (L.NO_SHOTNOISE if no_shotnoise else 0)
-            | (L.NO_DECONVOLVE if no_deconvolve else 0))
+            | (L.NO_DECONVOLVE if no_deconvolve else 0) | L.KERNELS[kernel])
 
 
 def make_catalog(pos, vel, weight=None, *, box, haf=1.0, n_bins=32, k_edges=None, flags=0):
@@ -130,11 +132,13 @@ class Plan:
         L.check(L.lib().mps_plan_reserve(self._h, int(max_particles)), "mps_plan_reserve")
 
     def estimate(self, pos, vel, weight=None, *, box, haf, n_bins=32, k_edges=None,
-                 bulk_flow=False, no_shotnoise=False, no_deconvolve=False, stream=None):
-        """Binned P_pp, P_tt, Re P_dt, P_dd (x V) of one catalog; dict of arrays."""
+                 bulk_flow=False, no_shotnoise=False, no_deconvolve=False, kernel="bl3",
+                 stream=None):
+        """Binned P_pp, P_tt, Re P_dt, P_dd (x V) of one catalog; dict of arrays.
+        kernel: "bl3" (six-tap truncated BL3) or "bl3_exact" (untruncated)."""
         cat, keep = make_catalog(pos, vel, weight, box=box, haf=haf, n_bins=n_bins,
                                  k_edges=k_edges,
-                                 flags=_flags(bulk_flow, no_shotnoise, no_deconvolve))
+                                 flags=_flags(bulk_flow, no_shotnoise, no_deconvolve, kernel))
         res, arrays = make_result(cat.n_bins)
         L.check(L.lib().mps_estimate(self._h, C.byref(cat), C.byref(res), _stream(stream)),
                 "mps_estimate")
@@ -143,7 +147,7 @@ class Plan:
 
     def estimate_mu(self, pos, vel, weight=None, *, box, haf, n_mu, axis=None, n_bins=32,
                     k_edges=None, bulk_flow=False, no_shotnoise=False, no_deconvolve=False,
-                    stream=None):
+                    kernel="bl3", stream=None):
         """(k, mu_b)-binned spectra (Sec. 3); arrays of shape (n_bins, n_mu).
 
         mu_b is the cosine to `axis` (3 numbers) or, by default, to the bulk
@@ -151,7 +155,7 @@ class Plan:
         """
         cat, keep = make_catalog(pos, vel, weight, box=box, haf=haf, n_bins=n_bins,
                                  k_edges=k_edges,
-                                 flags=_flags(bulk_flow, no_shotnoise, no_deconvolve))
+                                 flags=_flags(bulk_flow, no_shotnoise, no_deconvolve, kernel))
         nb = cat.n_bins
         ncell = nb * int(n_mu)
         arrays = {k: np.full(ncell, np.nan) for k in L.MU_KEYS}
@@ -178,12 +182,13 @@ class Plan:
         out["n_eff"] = float(res.n_eff)
         return out
 
-    def assign(self, pos, vel, weight=None, *, box, bulk_flow=False, stream=None):
-        """The four assigned real grids, torch tensor (4, N, N, N) [field, x, y, z]."""
+    def assign(self, pos, vel, weight=None, *, box, bulk_flow=False, kernel="bl3", stream=None):
+        """The four assigned real grids, torch tensor (4, N, N, N) [field, x, y, z]
+        (for kernel="bl3_exact", the cubic B-spline grids)."""
         n = self.n_grid
         out = torch.empty((4, n, n, n), dtype=self.real_dtype, device=pos.device)
         cat, keep = make_catalog(pos, vel, weight, box=box, haf=1.0, n_bins=1,
-                                 flags=_flags(bulk_flow, False, False))
+                                 flags=_flags(bulk_flow, False, False, kernel))
         L.check(L.lib().mps_assign(self._h, C.byref(cat), C.c_void_p(out.data_ptr()),
                                    _stream(stream)), "mps_assign")
         del keep

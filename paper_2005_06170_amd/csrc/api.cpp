@@ -57,6 +57,8 @@ void release(Plan* p) {
   dfree(p->d_header);
   dfree(p->d_win2);
   dfree(p->d_alias);
+  dfree(p->d_win2_pcs);
+  dfree(p->d_alias_pcs);
   dfree(p->d_twiddle);
   dfree(p->d_lut);
   dfree(p->d_bin_partials);
@@ -78,7 +80,7 @@ int validate_catalog(const Plan* p, const mps_catalog* c) {
   if (!(c->box > 0.0) || !std::isfinite(c->box)) return MPS_E_ARG;
   if (!(c->haf > 0.0) || !std::isfinite(c->haf)) return MPS_E_ARG;
   if (c->n_bins < 1 || c->n_bins > kMaxBins) return MPS_E_ARG;
-  if (c->flags & ~7u) return MPS_E_ARG;
+  if (c->flags & ~15u) return MPS_E_ARG;
   (void)p;
   return MPS_OK;
 }
@@ -154,6 +156,17 @@ int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s) {
 }
 
 namespace {
+
+// a / |a| with |a| = sqrt(a0 a0 + a1 a1 + a2 a2), each operation rounded
+// separately (no fused multiply-adds), as the mu bins are documented; false
+// for a zero or non-finite vector.
+bool unit_axis(const double* a, double* out) {
+#pragma clang fp contract(off)
+  const double nrm = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
+  for (int i = 0; i < 3; ++i) out[i] = a[i] / nrm;
+  return true;
+}
 
 int check_header(const ResultHeader* h) {
   if (h->flags & 1u) return MPS_E_NONFINITE;
@@ -232,6 +245,8 @@ int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec) {
   ok = ok && dalloc(&p->d_header, sizeof(ResultHeader)) == hipSuccess;
   ok = ok && dalloc(&p->d_win2, sizeof(double) * (half + 1)) == hipSuccess;
   ok = ok && dalloc(&p->d_alias, sizeof(double) * (half + 1)) == hipSuccess;
+  ok = ok && dalloc(&p->d_win2_pcs, sizeof(double) * (half + 1)) == hipSuccess;
+  ok = ok && dalloc(&p->d_alias_pcs, sizeof(double) * (half + 1)) == hipSuccess;
   ok = ok && dalloc(&p->d_twiddle, 2 * p->real_size * n_grid) == hipSuccess;
   ok = ok && dalloc(&p->d_lut, sizeof(int32_t) * half * half) == hipSuccess;
   ok = ok && dalloc(&p->d_bin_partials, sizeof(double) * p->bin_blocks * kMaxBins * kNumQ) == hipSuccess;
@@ -244,7 +259,9 @@ int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec) {
     return MPS_E_NOMEM;
   }
   p->taps = bl3_tap_polynomials();
-  p->tap_bound = bl3_tap_bounds(p->taps);
+  p->tap_bound = tap_bounds(p->taps, kTaps);
+  p->taps_pcs = pcs_tap_polynomials();
+  p->tap_bound_pcs = tap_bounds(p->taps_pcs, 4);
   std::vector<double> win2, alias;
   bl3_axis_tables(n_grid, &win2, &alias);
   const std::vector<double> tw = twiddles(n_grid);
@@ -252,6 +269,12 @@ int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec) {
   for (double& w : win2) w = 1.0 / w;
   bool up = hipMemcpy(p->d_win2, win2.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) == hipSuccess;
   up = up && hipMemcpy(p->d_alias, alias.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) == hipSuccess;
+  std::vector<double> iwin2_pcs, alias_pcs;
+  pcs_axis_tables(n_grid, &iwin2_pcs, &alias_pcs);
+  up = up && hipMemcpy(p->d_win2_pcs, iwin2_pcs.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) ==
+                 hipSuccess;
+  up = up && hipMemcpy(p->d_alias_pcs, alias_pcs.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) ==
+                 hipSuccess;
   if (prec == MPS_F32) {
     std::vector<float> twf(tw.begin(), tw.end());
     up = up && hipMemcpy(p->d_twiddle, twf.data(), sizeof(float) * twf.size(), hipMemcpyHostToDevice) == hipSuccess;
@@ -313,15 +336,8 @@ int mps_estimate_mu(mps_plan* plan, const mps_catalog* cat, int n_mu, const doub
   int st = validate_catalog(p, cat);
   if (st != MPS_OK) return st;
   if (n_mu < 1 || n_mu > MPS_MAX_MU_BINS || cat->n_bins * n_mu > kMaxMuCells) return MPS_E_ARG;
-  // the unit axis, rounded operation by operation as documented (no fused
-  // multiply-adds), so that every mode's mu bin is reproducible
-#pragma clang fp contract(off)
   double ahat[3] = {0.0, 0.0, 0.0};
-  if (axis) {
-    const double nrm = std::sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
-    if (!(nrm > 0.0) || !std::isfinite(nrm)) return MPS_E_ARG;
-    for (int a = 0; a < 3; ++a) ahat[a] = axis[a] / nrm;
-  }
+  if (axis && !unit_axis(axis, ahat)) return MPS_E_ARG;
   if (hipSetDevice(p->device) != hipSuccess) return MPS_E_HIP;
   if (!p->d_mu_partials) {
     const size_t cells = static_cast<size_t>(kMaxMuCells) * kNumQMu;
@@ -359,12 +375,7 @@ int mps_estimate_mu(mps_plan* plan, const mps_catalog* cat, int n_mu, const doub
 
   const ResultHeader* h = static_cast<const ResultHeader*>(p->h_stage_mu);
   if ((st = check_header(h)) != MPS_OK) return st;
-  if (!axis) {
-    const double* vb = h->d.vb;
-    const double nrm = std::sqrt(vb[0] * vb[0] + vb[1] * vb[1] + vb[2] * vb[2]);
-    if (!(nrm > 0.0)) return MPS_E_ARG;  // no bulk flow to define mu_b
-    for (int a = 0; a < 3; ++a) ahat[a] = vb[a] / nrm;
-  }
+  if (!axis && !unit_axis(h->d.vb, ahat)) return MPS_E_ARG;  // no bulk flow to define mu_b
   const double* cells = reinterpret_cast<const double*>(static_cast<const char*>(p->h_stage_mu) + sizeof(ResultHeader));
   for (int i = 0; i < ncell; ++i) {
     const double* q = cells + static_cast<size_t>(i) * kNumQMu;

@@ -68,8 +68,13 @@ struct Plan;
 // ----------------------------------------------------------------- tables
 // Host-side FP64 construction of the truncated cubic Battle-Lemarie kernel.
 TapPoly bl3_tap_polynomials();
-// Bounds of |w_j| on [0, 1] (ends and stationary points), with a small margin.
-TapBound bl3_tap_bounds(const TapPoly& tp);
+// Bounds of |w_j| on [0, 1] (ends and stationary points) for the first
+// n_taps taps, with a small margin.
+TapBound tap_bounds(const TapPoly& tp, int n_taps);
+// Tap polynomials of the centred cubic B-spline, taps j = -1..2 (4 of the 6).
+TapPoly pcs_tap_polynomials();
+// 1 / (sinc(w/2)^4)^2 and A(w) for w = 2 pi n / N, n = 0..N/2.
+void pcs_axis_tables(int n_grid, std::vector<double>* inv_win2, std::vector<double>* alias);
 // W_t(2 pi n / N)^2 and C_t(2 pi n / N) for n = 0..N/2.
 void bl3_axis_tables(int n_grid, std::vector<double>* win2, std::vector<double>* alias);
 // e^{-2 pi i m / N}, m = 0..N-1, interleaved (re, im).
@@ -99,6 +104,8 @@ struct Plan {
   ResultHeader* d_header = nullptr;
   double* d_win2 = nullptr;          // N/2 + 1: 1 / W_t(2 pi n / N)^2
   double* d_alias = nullptr;         // N/2 + 1
+  double* d_win2_pcs = nullptr;      // N/2 + 1: 1 / sinc^8(pi n / N)
+  double* d_alias_pcs = nullptr;     // N/2 + 1: A(2 pi n / N)
   void* d_twiddle = nullptr;         // N complex of the plan's precision
   int32_t* d_lut = nullptr;          // (N/2)^2
   double* d_bin_partials = nullptr;  // bin_blocks x kMaxBins x kNumQ
@@ -120,8 +127,10 @@ struct Plan {
   std::vector<double> lut_edges;     // edges the LUT was built for (empty: default)
   std::vector<double> edges_used;    // n_bins + 1 edges actually used
 
-  TapPoly taps;
+  TapPoly taps;                      // truncated BL3, 6 taps
   TapBound tap_bound;
+  TapPoly taps_pcs;                  // cubic B-spline, 4 taps (untruncated BL3)
+  TapBound tap_bound_pcs;
 
   // stage timing
   bool timing = false;

@@ -379,11 +379,18 @@ __device__ __forceinline__ DepositQ<T> charges(const float4& a, const float4& v,
   return d;
 }
 
+// Kernels with NTAP taps per axis: the truncated BL3 function (6 taps,
+// j = -2..3) or the cubic B-spline of the untruncated BL3 path (4 taps,
+// j = -1..2).  The LDS block is the tile plus a halo of kHaloLo cells below
+// and NTAP - 1 - kHaloLo above.
+template <int NTAP>
+constexpr int kHaloLo = NTAP / 2 - 1;
+
 // Tap weights and the particle's cell relative to the tile origin.
-template <typename T, int TS>
+template <typename T, int TS, int NTAP>
 __device__ __forceinline__ unsigned particle_taps(const float4& a, const KeyParams& kp, int ox, int oy, int oz,
                                                   const TapPoly& tp, T* wx, T* wy, T* wz) {
-  constexpr int E = TS + 5;
+  constexpr int E = TS + NTAP - 1;
   double fx, fy, fz;
   bool ok;
   int cx = locate(a.x, kp.scale, kp.n, &fx, &ok) - ox;
@@ -395,7 +402,7 @@ __device__ __forceinline__ unsigned particle_taps(const float4& a, const KeyPara
   cy = min(max(cy, 0), TS - 1);
   cz = min(max(cz, 0), TS - 1);
 #pragma unroll
-  for (int j = 0; j < kTaps; ++j) {
+  for (int j = 0; j < NTAP; ++j) {
     wx[j] = static_cast<T>(tap_weight(tp, j, fx));
     wy[j] = static_cast<T>(tap_weight(tp, j, fy));
     wz[j] = static_cast<T>(tap_weight(tp, j, fz));
@@ -433,9 +440,9 @@ __device__ __forceinline__ void unpack_pair(unsigned long long s, int* lo, int* 
 
 // LDS word index of a particle's tap origin (cell relative to the tile
 // origin, halo offset included) without the tap weights.
-template <int TS>
+template <int TS, int NTAP>
 __device__ __forceinline__ unsigned tap_origin(const float4& a, const KeyParams& kp, int ox, int oy, int oz) {
-  constexpr int E = TS + 5;
+  constexpr int E = TS + NTAP - 1;
   double f;
   bool ok;
   int cx = locate(a.x, kp.scale, kp.n, &f, &ok) - ox;
@@ -514,22 +521,23 @@ __device__ __forceinline__ int64_t next_tile(const TileQueues& tq, int64_t n_til
 
 // One line of the separable bound convolution: out[g] = sum_j k_j in[g - j]
 // over taps j = -2..3, with in = 0 outside the E-long line.
-template <int E>
+template <int E, int NTAP>
 __device__ __forceinline__ void bound_line(const float (&in)[E], const TapBound& kb, float (&out)[E]) {
+  constexpr int H = kHaloLo<NTAP>;
 #pragma unroll
   for (int g = 0; g < E; ++g) {
     float o = 0.f;
 #pragma unroll
-    for (int j = -2; j <= 3; ++j)
-      if (g - j >= 0 && g - j < E) o = fmaf(kb.k[j + 2], in[g - j], o);
+    for (int j = -H; j < NTAP - H; ++j)
+      if (g - j >= 0 && g - j < E) o = fmaf(kb.k[j + H], in[g - j], o);
     out[g] = o;
   }
 }
 
 // FP32 grids.  A persistent grid of one workgroup per CU walks the occupied
-// T^3 tiles.  LDS holds the four fields over the tile plus a halo of 2 cells
-// below and 3 above along each axis (taps -2..3) as 32-bit fixed point, two
-// fields per 64-bit word: gfx950's LDS adds 64-bit integers at ~9.4
+// T^3 tiles.  LDS holds the four fields over the tile plus a halo (2 cells
+// below and 3 above along each axis for taps -2..3; 1 and 2 for the cubic
+// B-spline's -1..2) as 32-bit fixed point, two fields per 64-bit word: gfx950's LDS adds 64-bit integers at ~9.4
 // lanes/clk/CU and 32-bit ones at ~14, but FP32 at ~0.3.
 //
 // Sums of fixed-point deposits are exact modulo 2^32 in any order, so only
@@ -542,16 +550,17 @@ __device__ __forceinline__ void bound_line(const float (&in)[E], const TapBound&
 // the worst-case sum of the per-deposit rounding errors (half a unit per
 // particle).  A single pass over LDS gives both the bound and the zeroed
 // accumulator.
-template <int TS, int NT>
+template <int TS, int NT, int NTAP>
 __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, float* __restrict__ grid,
     KeyParams kp, int64_t n_tiles, TileQueues tq, TapPoly tp, TapBound kb, const Derived* dsrc, int bulk) {
-  constexpr int E = TS + 5;
+  constexpr int H = kHaloLo<NTAP>;
+  constexpr int E = TS + NTAP - 1;
   constexpr int VOL = E * E * E;
   constexpr int kPer = 6;
   constexpr int kSuper = kPer * NT;
   constexpr int kWaves = NT / 64;
-  constexpr int kCellOff = (2 * E + 2) * E + 2;  // tap origin -> the particle's own cell
+  constexpr int kCellOff = (H * E + H) * E + H;  // tap origin -> the particle's own cell
   __shared__ __align__(16) int acc[kNumFields * VOL];
   __shared__ BankSort<NT, kPer> bs;
   __shared__ float red[kWaves][kNumFields];
@@ -615,7 +624,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       if (t + r * NT < m0) {
         const int64_t p = static_cast<int64_t>(p0) + t + r * NT;
         const float4 a = sorted[2 * p];
-        const unsigned base = tap_origin<TS>(a, kp, ox, oy, oz);
+        const unsigned base = tap_origin<TS, NTAP>(a, kp, ox, oy, oz);
         const unsigned b = base & 31u;
         key0[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
         add_cell_sums(a, sorted[2 * p + 1], base + kCellOff);
@@ -623,31 +632,31 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     }
     for (uint32_t p = p0 + static_cast<uint32_t>(m0) + t; p < p1; p += NT) {
       const float4 a = sorted[2 * static_cast<int64_t>(p)];
-      add_cell_sums(a, sorted[2 * static_cast<int64_t>(p) + 1], tap_origin<TS>(a, kp, ox, oy, oz) + kCellOff);
+      add_cell_sums(a, sorted[2 * static_cast<int64_t>(p) + 1], tap_origin<TS, NTAP>(a, kp, ox, oy, oz) + kCellOff);
     }
     __syncthreads();
     // bound convolution along z (lines of the tile's interior x, y), then y
     // (interior x), as floats in place
     for (int rr = t; rr < kNumFields * TS * TS; rr += NT) {
       const int f = rr / (TS * TS);
-      const int x = 2 + (rr / TS) % TS, y = 2 + rr % TS;
+      const int x = H + (rr / TS) % TS, y = H + rr % TS;
       int* line = acc + f * VOL + (x * E + y) * E;
       float in[E], out[E];
 #pragma unroll
       for (int g = 0; g < E; ++g) in[g] = static_cast<float>(static_cast<unsigned>(line[g]));
-      bound_line<E>(in, kb, out);
+      bound_line<E, NTAP>(in, kb, out);
 #pragma unroll
       for (int g = 0; g < E; ++g) line[g] = __float_as_int(out[g]);
     }
     __syncthreads();
     for (int rr = t; rr < kNumFields * TS * E; rr += NT) {
       const int f = rr / (TS * E);
-      const int x = 2 + (rr / E) % TS, z = rr % E;
+      const int x = H + (rr / E) % TS, z = rr % E;
       int* line = acc + f * VOL + x * E * E + z;
       float in[E], out[E];
 #pragma unroll
       for (int g = 0; g < E; ++g) in[g] = __int_as_float(line[g * E]);
-      bound_line<E>(in, kb, out);
+      bound_line<E, NTAP>(in, kb, out);
 #pragma unroll
       for (int g = 0; g < E; ++g) line[g * E] = __float_as_int(out[g]);
     }
@@ -663,7 +672,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         in[g] = __int_as_float(line[g * E * E]);
         line[g * E * E] = 0;
       }
-      bound_line<E>(in, kb, out);
+      bound_line<E, NTAP>(in, kb, out);
       float m = 0.f;
 #pragma unroll
       for (int g = 0; g < E; ++g) m = fmaxf(m, out[g]);
@@ -712,23 +721,23 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         const uint32_t p = c0 + bs.idx[q];
         const float4 a = sorted[2 * static_cast<int64_t>(p)];
         const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
-        float wx[kTaps], wy[kTaps], wz[kTaps];
-        const unsigned base = particle_taps<float, TS>(a, kp, ox, oy, oz, tp, wx, wy, wz);
+        float wx[NTAP], wy[NTAP], wz[NTAP];
+        const unsigned base = particle_taps<float, TS, NTAP>(a, kp, ox, oy, oz, tp, wx, wy, wz);
         const DepositQ<float> d = charges<float>(a, v, bulk, vb0, vb1, vb2);
         float qs[kNumFields];
 #pragma unroll
         for (int f = 0; f < kNumFields; ++f) qs[f] = d.q[f] * sc[f];
         unsigned long long* accp[2] = {acc2 + base, acc2 + VOL + base};
 #pragma unroll
-        for (int jx = 0; jx < kTaps; ++jx) {
+        for (int jx = 0; jx < NTAP; ++jx) {
 #pragma unroll
-          for (int jy = 0; jy < kTaps; ++jy) {
+          for (int jy = 0; jy < NTAP; ++jy) {
             const float wxy = wx[jx] * wy[jy];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
               const float wlo = wxy * qs[2 * k], whi = wxy * qs[2 * k + 1];
 #pragma unroll
-              for (int jz = 0; jz < kTaps; ++jz)
+              for (int jz = 0; jz < NTAP; ++jz)
                 atomicAdd(accp[k] + (jx * E + jy) * E + jz,
                           pack_pair(round_to_int(wlo * wz[jz]), round_to_int(whi * wz[jz])));
             }
@@ -748,7 +757,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         key[r] = 0;
         if (t + r * NT < m) {
           const unsigned b =
-              tap_origin<TS>(sorted[2 * static_cast<int64_t>(c0 + t + r * NT)], kp, ox, oy, oz) & 31u;
+              tap_origin<TS, NTAP>(sorted[2 * static_cast<int64_t>(c0 + t + r * NT)], kp, ox, oy, oz) & 31u;
           key[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
         }
       }
@@ -762,9 +771,9 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     for (int f = 0; f < kNumFields; ++f) inv[f] = inv_s[f];
     for (int i = t; i < VOL; i += NT) {
       const int ez = i % E, ey = (i / E) % E, ex = i / (E * E);
-      const int gx = (ox + ex - 2) & (n - 1);
-      const int gy = (oy + ey - 2) & (n - 1);
-      const int gz = (oz + ez - 2) & (n - 1);
+      const int gx = (ox + ex - H) & (n - 1);
+      const int gy = (oy + ey - H) & (n - 1);
+      const int gz = (oz + ez - H) & (n - 1);
       const int64_t gi = (static_cast<int64_t>(gx) * n + gy) * n + gz;
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
@@ -783,11 +792,12 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
 // FP64 grids: LDS accumulation with ds_add_f64 (~7 lanes/clk/CU on gfx950),
 // same tiles and bank-sorted lane order as the FP32 kernel (a double spans
 // two banks, so the key is the element index mod 32).
-template <int TS, int NT>
+template <int TS, int NT, int NTAP>
 __global__ __launch_bounds__(NT) void scatter_f64_kernel(
     const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, double* __restrict__ grid,
     KeyParams kp, int64_t n_tiles, int64_t xcd_chunk, TapPoly tp, const Derived* dsrc, int bulk) {
-  constexpr int E = TS + 5;
+  constexpr int H = kHaloLo<NTAP>;
+  constexpr int E = TS + NTAP - 1;
   constexpr int VOL = E * E * E;
   constexpr int kPer = 4;
   constexpr int kSuper = kPer * NT;
@@ -821,7 +831,7 @@ __global__ __launch_bounds__(NT) void scatter_f64_kernel(
     for (int r = 0; r < kPer; ++r) {
       const int i = t + r * NT;
       if (i < m) {
-        bank[r] = tap_origin<TS>(sorted[2 * static_cast<int64_t>(c0 + i)], kp, ox, oy, oz) & 31u;
+        bank[r] = tap_origin<TS, NTAP>(sorted[2 * static_cast<int64_t>(c0 + i)], kp, ox, oy, oz) & 31u;
         slot[r] = static_cast<unsigned>(atomicAdd(&bs.cnt[bank[r]], 1));
       }
     }
@@ -842,24 +852,24 @@ __global__ __launch_bounds__(NT) void scatter_f64_kernel(
       const uint32_t p = c0 + bs.idx[q];
       const float4 a = sorted[2 * static_cast<int64_t>(p)];
       const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
-      double wx[kTaps], wy[kTaps], wz[kTaps];
-      const unsigned base = particle_taps<double, TS>(a, kp, ox, oy, oz, tp, wx, wy, wz);
+      double wx[NTAP], wy[NTAP], wz[NTAP];
+      const unsigned base = particle_taps<double, TS, NTAP>(a, kp, ox, oy, oz, tp, wx, wy, wz);
       const DepositQ<double> d = charges<double>(a, v, bulk, vb0, vb1, vb2);
-      double qz[kNumFields][kTaps];
+      double qz[kNumFields][NTAP];
 #pragma unroll
       for (int f = 0; f < kNumFields; ++f)
 #pragma unroll
-        for (int j = 0; j < kTaps; ++j) qz[f][j] = d.q[f] * wz[j];
+        for (int j = 0; j < NTAP; ++j) qz[f][j] = d.q[f] * wz[j];
       double* accf[kNumFields] = {acc + base, acc + VOL + base, acc + 2 * VOL + base, acc + 3 * VOL + base};
 #pragma unroll
-      for (int jx = 0; jx < kTaps; ++jx) {
+      for (int jx = 0; jx < NTAP; ++jx) {
 #pragma unroll
-        for (int jy = 0; jy < kTaps; ++jy) {
+        for (int jy = 0; jy < NTAP; ++jy) {
           const double wxy = wx[jx] * wy[jy];
 #pragma unroll
           for (int f = 0; f < kNumFields; ++f)
 #pragma unroll
-            for (int jz = 0; jz < kTaps; ++jz) atomicAdd(accf[f] + (jx * E + jy) * E + jz, wxy * qz[f][jz]);
+            for (int jz = 0; jz < NTAP; ++jz) atomicAdd(accf[f] + (jx * E + jy) * E + jz, wxy * qz[f][jz]);
         }
       }
     }
@@ -869,9 +879,9 @@ __global__ __launch_bounds__(NT) void scatter_f64_kernel(
   const int64_t n3 = static_cast<int64_t>(n) * n * n;
   for (int i = t; i < VOL; i += NT) {
     const int ez = i % E, ey = (i / E) % E, ex = i / (E * E);
-    const int gx = (ox + ex - 2) & (n - 1);
-    const int gy = (oy + ey - 2) & (n - 1);
-    const int gz = (oz + ez - 2) & (n - 1);
+    const int gx = (ox + ex - H) & (n - 1);
+    const int gy = (oy + ey - H) & (n - 1);
+    const int gz = (oz + ez - H) & (n - 1);
     const int64_t gi = (static_cast<int64_t>(gx) * n + gy) * n + gz;
 #pragma unroll
     for (int f = 0; f < kNumFields; ++f) {
@@ -951,37 +961,41 @@ hipError_t launch_clear_grid(Plan* p, hipStream_t s) {
   return hipGetLastError();
 }
 
-// bulk: 1 = deposit w (v - v_b) (only the assign diagnostic asks for it; the
-// estimator removes the bulk flow in Fourier space, p' = p - v_b delta).
-hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int bulk) {
+template <int NTAP>
+hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int bulk, const TapPoly& tp,
+                               const TapBound& tb) {
   const KeyParams kp = key_params(p, c);
   const int64_t xcd_chunk = (p->n_tiles % 8 == 0) ? p->n_tiles / 8 : 0;
   const Derived* dsrc = &p->d_header->d;
-  if (p->prec == MPS_F32 && p->tile == 16) {
+  if (p->prec == MPS_F32) {
     TileQueues tq;
     tq.counter = p->tile_queue;
     tq.nq = xcd_chunk > 0 ? 8 : 1;
     tq.per_queue = xcd_chunk > 0 ? xcd_chunk : p->n_tiles;
     clear_kernel<uint32_t><<<1, 64, 0, s>>>(p->tile_queue, 8);
-    // one workgroup per CU (the LDS holds one), never more than the tiles
-    const int64_t blocks = p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus;
-    scatter_fixed_kernel<16, 1024><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
-        p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, p->taps, p->tap_bound, dsrc, bulk);
-  } else if (p->prec == MPS_F32) {
-    TileQueues tq;
-    tq.counter = p->tile_queue;
-    tq.nq = xcd_chunk > 0 ? 8 : 1;
-    tq.per_queue = xcd_chunk > 0 ? xcd_chunk : p->n_tiles;
-    clear_kernel<uint32_t><<<1, 64, 0, s>>>(p->tile_queue, 8);
-    const int64_t cap = 4 * static_cast<int64_t>(p->num_cus);
-    const int64_t blocks = p->n_tiles < cap ? p->n_tiles : cap;
-    scatter_fixed_kernel<8, 512><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
-        p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, p->taps, p->tap_bound, dsrc, bulk);
+    if (p->tile == 16) {
+      // one workgroup per CU (the LDS holds one), never more than the tiles
+      const int64_t blocks = p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus;
+      scatter_fixed_kernel<16, 1024, NTAP><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+          p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk);
+    } else {
+      const int64_t cap = 4 * static_cast<int64_t>(p->num_cus);
+      const int64_t blocks = p->n_tiles < cap ? p->n_tiles : cap;
+      scatter_fixed_kernel<8, 512, NTAP><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
+          p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk);
+    }
   } else {
-    scatter_f64_kernel<8, 512><<<static_cast<unsigned>(p->n_tiles), 512, 0, s>>>(
-        p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, xcd_chunk, p->taps, dsrc, bulk);
+    scatter_f64_kernel<8, 512, NTAP><<<static_cast<unsigned>(p->n_tiles), 512, 0, s>>>(
+        p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, xcd_chunk, tp, dsrc, bulk);
   }
   return hipGetLastError();
+}
+
+// bulk: 1 = deposit w (v - v_b) (only the assign diagnostic asks for it; the
+// estimator removes the bulk flow in Fourier space, p' = p - v_b delta).
+hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int bulk) {
+  if (c->flags & MPS_KERNEL_BL3_EXACT) return launch_scatter_taps<4>(p, c, s, bulk, p->taps_pcs, p->tap_bound_pcs);
+  return launch_scatter_taps<6>(p, c, s, bulk, p->taps, p->tap_bound);
 }
 
 hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s) {

@@ -117,9 +117,10 @@ TapPoly bl3_tap_polynomials() {
   return tp;
 }
 
-TapBound bl3_tap_bounds(const TapPoly& tp) {
+TapBound tap_bounds(const TapPoly& tp, int n_taps) {
   TapBound b;
-  for (int j = 0; j < kTaps; ++j) {
+  for (int j = 0; j < kTaps; ++j) b.k[j] = 0.f;
+  for (int j = 0; j < n_taps; ++j) {
     const double* c = tp.c[j];
     // |w_j| on [0, 1] peaks at an end or where w_j' = c1 + 2 c2 f + 3 c3 f^2 vanishes
     double cand[4] = {0.0, 1.0, -1.0, -1.0};
@@ -143,6 +144,34 @@ TapBound bl3_tap_bounds(const TapPoly& tp) {
     b.k[j] = static_cast<float>(m * 1.0001);
   }
   return b;
+}
+
+TapPoly pcs_tap_polynomials() {
+  // beta3(j - f) on f in [0, 1) for j = -1, 0, 1, 2: (1 - f)^3 / 6,
+  // 2/3 - f^2 + f^3 / 2, 1/6 + f/2 + f^2/2 - f^3/2, f^3 / 6
+  static const double c[4][4] = {{1.0 / 6.0, -0.5, 0.5, -1.0 / 6.0},
+                                 {2.0 / 3.0, 0.0, -1.0, 0.5},
+                                 {1.0 / 6.0, 0.5, 0.5, -0.5},
+                                 {0.0, 0.0, 0.0, 1.0 / 6.0}};
+  TapPoly tp;
+  for (int j = 0; j < kTaps; ++j)
+    for (int q = 0; q < 4; ++q) tp.c[j][q] = j < 4 ? c[j][q] : 0.0;
+  return tp;
+}
+
+void pcs_axis_tables(int n_grid, std::vector<double>* inv_win2, std::vector<double>* alias) {
+  const int half = n_grid / 2;
+  inv_win2->assign(half + 1, 1.0);
+  alias->assign(half + 1, 1.0);
+  for (int n = 0; n <= half; ++n) {
+    const double w = 2.0 * M_PI * n / n_grid;
+    const double h = 0.5 * w;
+    const double sinc = n == 0 ? 1.0 : std::sin(h) / h;
+    const double s4 = sinc * sinc * sinc * sinc;
+    (*inv_win2)[n] = 1.0 / (s4 * s4);
+    // sum_J |beta3_hat(w + 2 pi J)|^2: the degree-7 B-spline at the integers
+    (*alias)[n] = (2416.0 + 2382.0 * std::cos(w) + 240.0 * std::cos(2.0 * w) + 2.0 * std::cos(3.0 * w)) / 5040.0;
+  }
 }
 
 void bl3_axis_tables(int n_grid, std::vector<double>* win2, std::vector<double>* alias) {
