@@ -65,12 +65,20 @@ def algorithmic_bytes(n_grid, n_part, real):
     }
 
 
-def time_path(mps, torch, pos, vel, prec, steps, warmup):
+def time_path(mps, torch, pos, vel, prec, steps, warmup, kernel="bl3", n_mu=0):
+    """Time `steps` estimates (n_mu > 0: the (k, mu_b) estimate with that many
+    mu bins along the z axis)."""
     plan = mps.Plan(N_GRID, prec)
     plan.reserve(pos.shape[0])
-    kw = dict(box=BOX, haf=HAF, n_bins=32)
+    kw = dict(box=BOX, haf=HAF, n_bins=32, kernel=kernel)
+
+    def run():
+        if n_mu:
+            return plan.estimate_mu(pos, vel, n_mu=n_mu, axis=(0.0, 0.0, 1.0), **kw)
+        return plan.estimate(pos, vel, **kw)
+
     for _ in range(warmup):
-        plan.estimate(pos, vel, **kw)
+        run()
     plan.set_timing(True)
     stages = []
     lat = []
@@ -78,7 +86,7 @@ def time_path(mps, torch, pos, vel, prec, steps, warmup):
     t0 = time.perf_counter()
     for _ in range(steps):
         t1 = time.perf_counter()
-        out = plan.estimate(pos, vel, **kw)
+        out = run()
         lat.append(time.perf_counter() - t1)
         stages.append(plan.stage_times())
     torch.cuda.synchronize()
@@ -196,6 +204,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip timing the untruncated-kernel and (k, mu_b) variants")
     ap.add_argument("--shuffle", action="store_true",
                     help="permute particle order randomly (no spatial coherence)")
     ap.add_argument("--serving", action="store_true",
@@ -232,18 +242,38 @@ def main():
     n_part = pos.shape[0]
 
     _log("timing the FP32 path")
-    wall, lat, stages, _ = time_path(mps, torch, pos, vel, "f32", args.steps, args.warmup)
+    wall, lat, stages, out32 = time_path(mps, torch, pos, vel, "f32", args.steps, args.warmup)
     ms_step = 1e3 * wall / args.steps
     _log(f"f32: {ms_step:.2f} ms/step; stages {stages}")
 
     fp64 = None
+    precision = None
     if not args.no_fp64:
         _log("timing the FP64 path")
         steps64 = max(3, args.steps // 4)
-        wall64, lat64, stages64, _ = time_path(mps, torch, pos, vel, "f64", steps64, 1)
+        wall64, lat64, stages64, out64 = time_path(mps, torch, pos, vel, "f64", steps64, 1)
         fp64 = {"catalogs_per_s": steps64 / wall64, "ms_per_step": 1e3 * wall64 / steps64,
                 "stage_ms": stages64}
         _log(f"f64: {1e3 * wall64 / steps64:.2f} ms/step")
+        # precision study: per-bin error of the FP32 grids against the FP64 grids,
+        # |dP| / (|P| + SN) (the FP64 path matches the oracle to ~1e-13)
+        precision = {}
+        for key, sn in (("p_pp", out64["sn_pp"]), ("p_tt", out64["sn_tt"]), ("p_dd", out64["sn_dd"]),
+                        ("p_dt", np.sqrt(out64["sn_dd"] * out64["sn_tt"]))):
+            ok = np.isfinite(out64[key])
+            e = np.abs(out32[key][ok] - out64[key][ok]) / (np.abs(out64[key][ok]) + np.abs(sn[ok]))
+            precision[key] = float(e.max())
+        _log(f"FP32 vs FP64 max guarded per-bin error: {precision}")
+
+    variants = None
+    if not args.no_variants:
+        variants = {}
+        steps_v = max(3, args.steps // 4)
+        for name, kw in (("bl3_exact_f32", {"kernel": "bl3_exact"}), ("mu16_f32", {"n_mu": 16})):
+            _log(f"timing variant {name}")
+            wall_v, _, stages_v, _ = time_path(mps, torch, pos, vel, "f32", steps_v, 1, **kw)
+            variants[name] = {"catalogs_per_s": steps_v / wall_v, "ms_per_step": 1e3 * wall_v / steps_v,
+                              "stage_ms": stages_v}
 
     abytes = algorithmic_bytes(N_GRID, n_part, 4)
     per_stage = {}
@@ -298,6 +328,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},
         "fp64": fp64,
+        "precision_f32_vs_f64": precision,
+        "variants": variants,
         "stages": per_stage,
         "roofline": roofline,
         "cpu_baseline": cpu,
