@@ -10,6 +10,8 @@
 // the block to HBM with global atomic adds.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace mps {
@@ -112,11 +114,23 @@ __device__ __forceinline__ uint32_t tile_key(float x, float y, float z, const Ke
 // wave still sees consecutive particles) and issues all their loads first.
 constexpr int kUnroll = 4;
 
-template <bool kHasW>
+// Tile histograms: with at most kLdsTiles tiles each workgroup counts in
+// LDS and adds its non-zero counts to the global histogram once at the end,
+// so that catalogs in random order over few tiles do not serialise on a few
+// global counters; larger grids count with wave-aggregated global atomics.
+constexpr int kLdsTiles = 16384;
+
+template <bool kHasW, bool kLds>
 __global__ __launch_bounds__(kCountThreads) void count_kernel(
     const float* __restrict__ pos, const float* __restrict__ vel, const float* __restrict__ wgt,
-    int64_t np, KeyParams kp, uint32_t* __restrict__ tile_count, double* __restrict__ partials,
-    ResultHeader* hdr) {
+    int64_t np, KeyParams kp, int64_t n_tiles, uint32_t* __restrict__ tile_count,
+    double* __restrict__ partials, ResultHeader* hdr) {
+  extern __shared__ uint32_t hist[];  // n_tiles counters when kLds
+  if (kLds) {
+    for (int64_t i = threadIdx.x; i < n_tiles; i += kCountThreads) hist[i] = 0u;
+    __syncthreads();
+  }
+  uint32_t* counts = kLds ? hist : tile_count;
   double acc[kMomentSums];
 #pragma unroll
   for (int q = 0; q < kMomentSums; ++q) acc[q] = 0.0;
@@ -171,8 +185,13 @@ __global__ __launch_bounds__(kCountThreads) void count_kernel(
         mx[2] = fmax(mx[2], fabs(w * dvy));
         mx[3] = fmax(mx[3], fabs(w * dvz));
       }
-      wave_run_atomic(key, valid, tile_count);
+      wave_run_atomic(key, valid, counts);
     }
+  }
+  if (kLds) {
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n_tiles; i += kCountThreads)
+      if (hist[i]) atomicAdd(tile_count + i, hist[i]);
   }
   __shared__ double red[kCountThreads / 64][kMomentSums + kMomentMax];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -294,13 +313,41 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
 }
 
 // Counting-sort scatter of the particle records into tile order.  Record:
-// (x, y, z, w), (v_x, v_y, v_z, 0).
-template <bool kHasW>
+// (x, y, z, w), (v_x, v_y, v_z, 0).  With at most kLdsTiles tiles a
+// workgroup first counts its own particles per tile in LDS, reserves one
+// contiguous range per tile with a single global atomic, and then hands out
+// slots from LDS; otherwise every wave claims slots with global atomics.
+template <bool kHasW, bool kLds>
 __global__ __launch_bounds__(kCountThreads) void permute_kernel(
     const float* __restrict__ pos, const float* __restrict__ vel, const float* __restrict__ wgt,
-    int64_t np, KeyParams kp, uint32_t* __restrict__ cursor, float4* __restrict__ sorted) {
+    int64_t np, KeyParams kp, int64_t n_tiles, uint32_t* __restrict__ cursor, float4* __restrict__ sorted) {
+  extern __shared__ uint32_t hist[];  // n_tiles counters when kLds
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kCountThreads * kUnroll;
-  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kCountThreads * kUnroll; base < np; base += stride) {
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * kCountThreads * kUnroll;
+  if (kLds) {
+    for (int64_t i = threadIdx.x; i < n_tiles; i += kCountThreads) hist[i] = 0u;
+    __syncthreads();
+    for (int64_t base = first; base < np; base += stride) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t i = base + u * kCountThreads + threadIdx.x;
+        const bool valid = i < np;
+        uint32_t key = 0xffffffffu;
+        if (valid) {
+          bool ok;
+          key = tile_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], kp, &ok);
+        }
+        wave_run_atomic(key, valid, hist);
+      }
+    }
+    __syncthreads();
+    // reserve this workgroup's ranges; hist[t] becomes the next free slot
+    for (int64_t t = threadIdx.x; t < n_tiles; t += kCountThreads)
+      if (hist[t]) hist[t] = atomicAdd(cursor + t, hist[t]);
+    __syncthreads();
+  }
+  uint32_t* slots = kLds ? hist : cursor;
+  for (int64_t base = first; base < np; base += stride) {
     float4 a[kUnroll], v[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -329,7 +376,7 @@ __global__ __launch_bounds__(kCountThreads) void permute_kernel(
         bool ok;
         key = tile_key(a[u].x, a[u].y, a[u].z, kp, &ok);
       }
-      run[u] = wave_run_claim(key, valid, cursor);
+      run[u] = wave_run_claim(key, valid, slots);
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -431,6 +478,22 @@ __device__ __forceinline__ int round_to_int(float x) {
 __device__ __forceinline__ unsigned long long pack_pair(int lo, int hi) {
   const unsigned h = static_cast<unsigned>(hi + (lo >> 31));
   return (static_cast<unsigned long long>(h) << 32) | static_cast<unsigned>(lo);
+}
+
+// The pair (round(wlo wz), round(whi wz)) packed as above in five VALU
+// operations: lo < 0 exactly when x = wlo wz < -1/2, and the indicator
+// clamp(-2^40 (x + 1/2)) to [0, 1] is exactly 0 or 1 for every FP32 x (the
+// FP32 values below -1/2 lie at least 2^-25 below it), so the sign correction
+// folds into the high product as round(whi wz - [lo < 0]).  That rounds the
+// exact product once; it may differ from rounding the FP32 product by one
+// unit, or by one FP32 spacing where that exceeds a unit, and the 64-bit sum
+// remains exact.
+__device__ __forceinline__ unsigned long long deposit_pair(float wlo, float whi, float wz) {
+  const float x = wlo * wz;
+  const int lo = round_to_int(x);
+  const float neg = __builtin_amdgcn_fmed3f(fmaf(x, -0x1p40f, -0x1p39f), 0.f, 1.f);
+  const int hi = round_to_int(fmaf(whi, wz, -neg));
+  return (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) | static_cast<unsigned>(lo);
 }
 
 __device__ __forceinline__ void unpack_pair(unsigned long long s, int* lo, int* hi) {
@@ -594,6 +657,10 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   while (tile >= 0) {
     const uint32_t p0 = offset[tile], p1 = offset[tile + 1];
     const uint32_t cnt = p1 - p0;
+    if (cnt == 0) {  // nothing to deposit or flush (uniform across the workgroup)
+      tile = next_tile<NT>(tq, n_tiles, &s_tile);
+      continue;
+    }
     const int tz = static_cast<int>(tile % nt);
     const int ty = static_cast<int>((tile / nt) % nt);
     const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
@@ -738,8 +805,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
               const float wlo = wxy * qs[2 * k], whi = wxy * qs[2 * k + 1];
 #pragma unroll
               for (int jz = 0; jz < NTAP; ++jz)
-                atomicAdd(accp[k] + (jx * E + jy) * E + jz,
-                          pack_pair(round_to_int(wlo * wz[jz]), round_to_int(whi * wz[jz])));
+                atomicAdd(accp[k] + (jx * E + jy) * E + jz, deposit_pair(wlo, whi, wz[jz]));
             }
           }
         }
@@ -918,12 +984,20 @@ hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
   clear_kernel<uint32_t><<<1, 256, 0, s>>>(reinterpret_cast<uint32_t*>(p->d_header),
                                            static_cast<int64_t>(sizeof(ResultHeader) / sizeof(uint32_t)));
   const int nb = kMomentBlocks;  // fixed grid: the moment sums keep one order
-  if (c->weight)
-    count_kernel<true><<<nb, kCountThreads, 0, s>>>(c->pos, c->vel, c->weight, c->n_particles, kp,
-                                                   p->tile_count, p->moment_partials, p->d_header);
-  else
-    count_kernel<false><<<nb, kCountThreads, 0, s>>>(c->pos, c->vel, nullptr, c->n_particles, kp,
-                                                    p->tile_count, p->moment_partials, p->d_header);
+  const bool lds = p->n_tiles <= kLdsTiles;
+  auto go = [&](auto has_w, auto use_lds) {
+    const size_t dyn = decltype(use_lds)::value ? sizeof(uint32_t) * static_cast<size_t>(p->n_tiles) : 0;
+    count_kernel<decltype(has_w)::value, decltype(use_lds)::value><<<nb, kCountThreads, dyn, s>>>(
+        c->pos, c->vel, c->weight, c->n_particles, kp, p->n_tiles, p->tile_count, p->moment_partials,
+        p->d_header);
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  if (c->weight) {
+    if (lds) go(T_{}, T_{}); else go(T_{}, F_{});
+  } else {
+    if (lds) go(F_{}, T_{}); else go(F_{}, F_{});
+  }
   return hipGetLastError();
 }
 
@@ -941,12 +1015,19 @@ hipError_t launch_scan(Plan* p, hipStream_t s) {
 hipError_t launch_permute(Plan* p, const mps_catalog* c, hipStream_t s) {
   const KeyParams kp = key_params(p, c);
   const int nb = count_blocks(c->n_particles);
-  if (c->weight)
-    permute_kernel<true><<<nb, kCountThreads, 0, s>>>(c->pos, c->vel, c->weight, c->n_particles, kp,
-                                                     p->tile_cursor, p->sorted);
-  else
-    permute_kernel<false><<<nb, kCountThreads, 0, s>>>(c->pos, c->vel, nullptr, c->n_particles, kp,
-                                                      p->tile_cursor, p->sorted);
+  const bool lds = p->n_tiles <= kLdsTiles;
+  auto go = [&](auto has_w, auto use_lds) {
+    const size_t dyn = decltype(use_lds)::value ? sizeof(uint32_t) * static_cast<size_t>(p->n_tiles) : 0;
+    permute_kernel<decltype(has_w)::value, decltype(use_lds)::value><<<nb, kCountThreads, dyn, s>>>(
+        c->pos, c->vel, c->weight, c->n_particles, kp, p->n_tiles, p->tile_cursor, p->sorted);
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  if (c->weight) {
+    if (lds) go(T_{}, T_{}); else go(T_{}, F_{});
+  } else {
+    if (lds) go(F_{}, T_{}); else go(F_{}, F_{});
+  }
   return hipGetLastError();
 }
 

@@ -64,11 +64,12 @@ def _blocks(grid0, rng):
 
 
 def _near(cell, nodes, n):
-    """Particles whose cell is within reach (taps -2..3) of any of the nodes."""
-    lo = nodes.min(axis=0)
+    """Particles whose cell is within reach (taps -2..3) of any of the nodes
+    of a block that starts at nodes[0] and is contiguous modulo n."""
+    lo = nodes[0]
     keep = np.ones(cell.shape[0], dtype=bool)
     for a in range(3):
-        # nodes of a block are contiguous modulo n: reach is [lo - 3, hi + 2]
+        # reach is [lo - 3, hi + 2]
         span = (nodes[:, a] - lo[a]) % n
         d = (cell[:, a] - (lo[a] - 3)) % n
         keep &= d <= span.max() + 5
@@ -123,8 +124,11 @@ def test_fullsize_fft_on_sampled_modes(mps, zel512_dev, prec):
         for m in modes:
             want = _dft_mode(g, m)
             got = complex(spec[f, m[0] % N, m[1] % N, m[2]].cpu().numpy())
-            worst = max(worst, abs(got - want) / norm)
-        print(prec, "field", f, "max |dF| / rms |F|:", worst, flush=True)
+            # rounding errors scale with the mode itself where it is large
+            # (the long-wavelength modes of the clustered fields) and with
+            # the rms elsewhere
+            worst = max(worst, abs(got - want) / (norm + abs(want)))
+        print(prec, "field", f, "max |dF| / (rms |F| + |F|):", worst, flush=True)
         assert worst < (1e-12 if prec == "f64" else 2e-5), (f, worst)
     del grid, spec
     plan.close()
@@ -180,23 +184,34 @@ def test_fullsize_translation_by_whole_cells(mps, zel512, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_plane_wave_control_512(mps, prec):
+@pytest.mark.parametrize("kernel", ["bl3_exact", "bl3"])
+def test_plane_wave_control_512(mps, prec, kernel):
     """200^3-particle plane wave (k0 = 2 pi 4 / L, A = 1 Mpc/h) on the 512^3
-    grid: a lattice incommensurate with the grid, so no comb tooth aliases onto
-    |n| = 4.  One shell [3.5, 4.5] k_f holds the 6 modes with n^2 = 16, two of
-    which carry the wave, so the shell mean is V (2/6) P_wave."""
+    grid.  The shell [sqrt(15.5), sqrt(16.5)] k_f holds the 6 modes with
+    n^2 = 16, two of which carry the wave, so the shell mean is V (2/6) P_wave.
+
+    With the untruncated kernel every spectrum matches the closed form: its
+    window vanishes at every alias of k0 (a CPU evaluation of the transform at
+    k0 gives |delta| and |p_x| within 2e-6 and 1e-8 of it).  The six-tap
+    truncation leaves window tails ~1/J^2 at the aliases k0 + 2 k_N J, where
+    the lattice's comb carries Bessel sidebands J_h(k_x A) of order 0.1: the
+    density at k0 picks up a few per cent (3.9e-2 in |delta| by the same CPU
+    evaluation) while the momentum, which has no comb, stays within 2e-4.  For
+    that kernel only P_pp and P_tt are compared with the closed form."""
     m_wave, amp = 4, 1.0
     pos, vel = catalogs.plane_wave(200, BOX, amp, m_wave, HAF)
     kf = 2 * math.pi / BOX
-    edges = np.array([3.5 * kf, 4.5 * kf])
+    edges = np.array([math.sqrt(15.5) * kf, math.sqrt(16.5) * kf])   # n^2 = 16 only
     r = mps.Plan(N, prec).estimate(torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda(),
-                                   box=BOX, haf=HAF, k_edges=edges, no_shotnoise=True)
+                                   box=BOX, haf=HAF, k_edges=edges, no_shotnoise=True, kernel=kernel)
     assert int(r["n_modes"][0]) == 6
     z = m_wave * kf * amp
     frac = BOX ** 3 * 2.0 / 6.0
-    want = {"p_dd": jv(1, z) ** 2, "p_pp": (HAF * amp) ** 2 * jvp(1, z) ** 2,
-            "p_tt": z * z * jvp(1, z) ** 2, "p_dt": z * jv(1, z) * jvp(1, z)}
+    want = {"p_pp": (HAF * amp) ** 2 * jvp(1, z) ** 2, "p_tt": z * z * jvp(1, z) ** 2}
+    if kernel == "bl3_exact":
+        want.update({"p_dd": jv(1, z) ** 2, "p_dt": z * jv(1, z) * jvp(1, z)})
     errs = {k: abs(float(r[k][0]) / (frac * v) - 1) for k, v in want.items()}
-    print(prec, "plane wave at 512^3: relative error", errs, flush=True)
+    print(prec, kernel, "plane wave at 512^3: relative error", errs, flush=True)
     assert r["p_dt"][0] > 0
-    assert max(errs.values()) < 1e-3, errs
+    tol = 1e-3 if kernel == "bl3" else (3e-5 if prec == "f64" else 1e-4)
+    assert max(errs.values()) < tol, errs
