@@ -97,6 +97,26 @@ def time_path(mps, torch, pos, vel, prec, steps, warmup, kernel="bl3", n_mu=0):
     return wall, np.array(lat), avg, out
 
 
+def time_subcubes(mps, torch, pos, vel, prec, steps, warmup):
+    """The sub-sample workload: the catalog cut into 4^3 cubes of 250 Mpc/h,
+    each estimated on a 128^3 grid (the spacing of the 512^3 grid)."""
+    plan = mps.Plan(N_GRID // 4, prec)
+
+    def run():
+        return plan.estimate_subcubes(pos, vel, box=BOX, haf=HAF, n_div=4)
+
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.close()
+    return wall
+
+
 def cpu_baseline():
     """Oracle on 1/64 of the workload: a 128^3-particle Zel'dovich catalog of the
     same construction on a 128^3 grid (64x fewer particles and cells)."""
@@ -205,7 +225,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip timing the untruncated-kernel and (k, mu_b) variants")
+                    help="skip timing the untruncated-kernel, (k, mu_b) and sub-sample variants")
     ap.add_argument("--shuffle", action="store_true",
                     help="permute particle order randomly (no spatial coherence)")
     ap.add_argument("--serving", action="store_true",
@@ -274,6 +294,11 @@ def main():
             wall_v, _, stages_v, _ = time_path(mps, torch, pos, vel, "f32", steps_v, 1, **kw)
             variants[name] = {"catalogs_per_s": steps_v / wall_v, "ms_per_step": 1e3 * wall_v / steps_v,
                               "stage_ms": stages_v}
+        _log("timing variant subcubes_4x4x4_128_f32")
+        wall_v = time_subcubes(mps, torch, pos, vel, "f32", steps_v, 1)
+        variants["subcubes_4x4x4_128_f32"] = {"catalogs_per_s": steps_v / wall_v,
+                                              "ms_per_step": 1e3 * wall_v / steps_v,
+                                              "sub_catalogs_per_s": 64 * steps_v / wall_v}
 
     abytes = algorithmic_bytes(N_GRID, n_part, 4)
     per_stage = {}

@@ -146,6 +146,8 @@ typedef struct {
 
 #define MPS_MAX_MU_BINS 64
 #define MPS_MAX_MU_CELLS 512   /* n_bins * n_mu */
+#define MPS_MAX_DIV 8          /* sub-cubes per axis in mps_estimate_subcubes */
+#define MPS_MAX_SUBCUBES 512   /* MPS_MAX_DIV^3 */
 
 typedef struct mps_plan mps_plan;
 typedef struct mps_server mps_server;
@@ -188,6 +190,37 @@ int mps_estimate_batch(mps_plan* const* plans, const mps_catalog* cats,
  * over the grid. */
 int mps_estimate_mu(mps_plan* plan, const mps_catalog* cat, int n_mu,
                     const double* axis, mps_result_mu* out, hipStream_t stream);
+
+/* Spectra of sub-samples (Sec. 2.4.1: the periodic box cut evenly into
+ * n_div^3 non-overlapping cubes of side L / n_div; Secs. 3.3 and 4.1 average
+ * them and take their scatter as error bars).
+ *
+ * The catalog `cat` (box L) is split on the device: per axis
+ * u = x (n_div / L) in FP64, g = floor(u), cube index
+ * m = g - n_div floor(g / n_div) clamped to [0, n_div - 1], and the particle's
+ * position within its cube x' = x - g (L / n_div) rounded to float32 (FP64,
+ * no fused operations).  Sub-cube s = (m_x n_div + m_y) n_div + m_z is then
+ * estimated exactly as mps_estimate estimates a catalog of those particles
+ * (velocities and weights unchanged) in a periodic box of side L / n_div on
+ * the plan's N^3 grid: k_edges, if given, apply to every sub-cube, the
+ * default bins are linear on [0, k_N) of the sub-box, and
+ * MPS_BULKFLOW_SUBTRACT removes each sub-cube's own bulk flow.
+ *
+ * n_div: 1 .. MPS_MAX_DIV.  outs: host array of n_div^3 results (array
+ * members caller-allocated as for mps_estimate, or NULL); status: host array
+ * of n_div^3 ints, MPS_OK or the sub-cube's error (MPS_E_ZEROWEIGHT for a
+ * cube without particles, whose outs arrays are left untouched).  mean, sdev:
+ * NULL or results that receive, per bin, the mean and the sample standard
+ * deviation (divisor m - 1; NaN for m < 2) over the m sub-cubes with status
+ * MPS_OK, likewise for v_bulk, sigma_v2 and n_eff; their n_modes is the mode
+ * count of one sub-cube (the same for all).  Returns MPS_E_NONFINITE if any
+ * position is not finite, MPS_E_ARG, MPS_E_NOMEM or MPS_E_HIP for the whole
+ * call, else MPS_OK.  The sub-catalogs live in plan workspace (28 bytes per
+ * particle with weights, 24 without); the sub-cube estimates run one after
+ * another on `stream` and the call returns after all results are copied. */
+int mps_estimate_subcubes(mps_plan* plan, const mps_catalog* cat, int n_div,
+                          mps_result* outs, int* status, mps_result* mean,
+                          mps_result* sdev, hipStream_t stream);
 
 /* Diagnostics of the hot path's first stages, using the same kernels as
  * mps_estimate.  mps_assign writes the four assigned real grids

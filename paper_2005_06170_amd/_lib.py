@@ -40,6 +40,7 @@ MU_KEYS = ("k_mean", "mu_mean", "p_pp", "p_tt", "p_dd", "p_dt_re", "p_dt_im", "p
            "p_dpb_im", "sn_pp", "sn_tt", "sn_dd", "sn_dt_im", "sn_dpb")
 MAX_MU_BINS = 64
 MAX_MU_CELLS = 512
+MAX_DIV = 8
 
 
 class ResultMu(C.Structure):
@@ -76,6 +77,8 @@ def lib():
         "mps_estimate": (i32, [vp, C.POINTER(Catalog), C.POINTER(Result), vp]),
         "mps_estimate_batch": (i32, [C.POINTER(vp), C.POINTER(Catalog), C.POINTER(Result), i32, vp]),
         "mps_estimate_mu": (i32, [vp, C.POINTER(Catalog), i32, C.POINTER(dbl), C.POINTER(ResultMu), vp]),
+        "mps_estimate_subcubes": (i32, [vp, C.POINTER(Catalog), i32, C.POINTER(Result), C.POINTER(i32),
+                                        C.POINTER(Result), C.POINTER(Result), vp]),
         "mps_assign": (i32, [vp, C.POINTER(Catalog), vp, vp]),
         "mps_fft": (i32, [vp, vp, vp]),
         "mps_plan_set_timing": (i32, [vp, i32]),
@@ -116,7 +119,8 @@ def exported_symbols():
     """Names declared in include/mps.h that the loaded library exports."""
     L = lib()
     names = ["mps_plan_create", "mps_plan_destroy", "mps_plan_reserve", "mps_footprint",
-             "mps_estimate", "mps_estimate_batch", "mps_estimate_mu", "mps_assign", "mps_fft",
+             "mps_estimate", "mps_estimate_batch", "mps_estimate_mu", "mps_estimate_subcubes",
+             "mps_assign", "mps_fft",
              "mps_plan_set_timing", "mps_plan_stage_times", "mps_server_create",
              "mps_submit", "mps_wait", "mps_server_destroy", "mps_strerror"]
     return {n: hasattr(L, n) for n in names}

@@ -182,6 +182,42 @@ class Plan:
         out["n_eff"] = float(res.n_eff)
         return out
 
+    def estimate_subcubes(self, pos, vel, weight=None, *, box, haf, n_div=4, n_bins=32,
+                          k_edges=None, bulk_flow=False, no_shotnoise=False, no_deconvolve=False,
+                          kernel="bl3", stream=None):
+        """Spectra of the n_div^3 sub-samples of a periodic catalog of side
+        `box` (Sec. 2.4.1), each a periodic catalog of side box / n_div on
+        this plan's grid, plus their per-bin mean and sample standard
+        deviation.  Returns {"sub": list of per-cube dicts (None for an empty
+        cube), "status": int array, "mean": dict, "sdev": dict, "sub_box"}."""
+        n_div = int(n_div)
+        if not 1 <= n_div <= L.MAX_DIV:
+            raise ValueError(f"n_div must be in [1, {L.MAX_DIV}]")
+        cat, keep = make_catalog(pos, vel, weight, box=box, haf=haf, n_bins=n_bins,
+                                 k_edges=k_edges,
+                                 flags=_flags(bulk_flow, no_shotnoise, no_deconvolve, kernel))
+        nc = n_div ** 3
+        nb = cat.n_bins
+        outs = (L.Result * nc)()
+        arrays = []
+        for s in range(nc):
+            res, arr = make_result(nb)
+            outs[s] = res
+            arrays.append(arr)
+        status = np.zeros(nc, dtype=np.int32)
+        mean, mean_arr = make_result(nb)
+        sdev, sdev_arr = make_result(nb)
+        L.check(L.lib().mps_estimate_subcubes(
+            self._h, C.byref(cat), n_div, outs, status.ctypes.data_as(C.POINTER(C.c_int)),
+            C.byref(mean), C.byref(sdev), _stream(stream)), "mps_estimate_subcubes")
+        del keep
+        sub_box = float(box) / n_div
+        subs = [unpack_result(outs[s], arrays[s], sub_box, self.n_grid, k_edges, nb)
+                if status[s] == L.MPS_OK else None for s in range(nc)]
+        return {"sub": subs, "status": status, "sub_box": sub_box,
+                "mean": unpack_result(mean, mean_arr, sub_box, self.n_grid, k_edges, nb),
+                "sdev": unpack_result(sdev, sdev_arr, sub_box, self.n_grid, k_edges, nb)}
+
     def assign(self, pos, vel, weight=None, *, box, bulk_flow=False, kernel="bl3", stream=None):
         """The four assigned real grids, torch tensor (4, N, N, N) [field, x, y, z]
         (for kernel="bl3_exact", the cubic B-spline grids)."""

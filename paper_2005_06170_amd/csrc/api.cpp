@@ -65,6 +65,14 @@ void release(Plan* p) {
   dfree(p->d_bins);
   dfree(p->d_mu_partials);
   dfree(p->d_mu_bins);
+  dfree(p->split_pos);
+  dfree(p->split_vel);
+  dfree(p->split_w);
+  dfree(p->split_count);
+  dfree(p->split_offset);
+  dfree(p->split_cursor);
+  if (p->h_split) (void)hipHostFree(p->h_split);
+  if (p->h_stage_sub) (void)hipHostFree(p->h_stage_sub);
   if (p->h_stage_mu) (void)hipHostFree(p->h_stage_mu);
   if (p->h_stage) (void)hipHostFree(p->h_stage);
   for (auto& e : p->ev)
@@ -137,7 +145,8 @@ int enqueue_particles(Plan* p, const mps_catalog* c, hipStream_t s, int bulk_gri
   return MPS_OK;
 }
 
-int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s) {
+int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s, void* stage) {
+  if (!stage) stage = p->h_stage;
   int st = enqueue_particles(p, c, s, 0);
   if (st != MPS_OK) return st;
   MPS_TRY(launch_fft_z(p, p->grid, s));
@@ -149,8 +158,8 @@ int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s) {
   MPS_TRY(launch_finalize(p, c, s));
   mark(p, 9, s);
   const size_t bytes = sizeof(ResultHeader) + sizeof(double) * kNumQ * c->n_bins;
-  MPS_TRY(hipMemcpyAsync(p->h_stage, p->d_header, sizeof(ResultHeader), hipMemcpyDeviceToHost, s));
-  MPS_TRY(hipMemcpyAsync(static_cast<char*>(p->h_stage) + sizeof(ResultHeader), p->d_bins,
+  MPS_TRY(hipMemcpyAsync(stage, p->d_header, sizeof(ResultHeader), hipMemcpyDeviceToHost, s));
+  MPS_TRY(hipMemcpyAsync(static_cast<char*>(stage) + sizeof(ResultHeader), p->d_bins,
                          bytes - sizeof(ResultHeader), hipMemcpyDeviceToHost, s));
   return MPS_OK;
 }
@@ -178,11 +187,12 @@ int check_header(const ResultHeader* h) {
 
 }  // namespace
 
-int unpack(Plan* p, const mps_catalog* c, mps_result* out) {
-  const ResultHeader* h = static_cast<const ResultHeader*>(p->h_stage);
+int unpack(Plan* p, const mps_catalog* c, mps_result* out, const void* stage) {
+  if (!stage) stage = p->h_stage;
+  const ResultHeader* h = static_cast<const ResultHeader*>(stage);
   const int st = check_header(h);
   if (st != MPS_OK) return st;
-  const double* bins = reinterpret_cast<const double*>(static_cast<const char*>(p->h_stage) + sizeof(ResultHeader));
+  const double* bins = reinterpret_cast<const double*>(static_cast<const char*>(stage) + sizeof(ResultHeader));
   for (int b = 0; b < c->n_bins; ++b) {
     const double* s = bins + b * kNumQ;
     if (out->n_modes) out->n_modes[b] = static_cast<int64_t>(std::llround(s[QCount]));
@@ -428,6 +438,166 @@ int mps_estimate_batch(mps_plan* const* plans, const mps_catalog* cats, mps_resu
     if (st != MPS_OK && first == MPS_OK) first = st;
   }
   return first;
+}
+
+}  // extern "C"
+
+namespace mps {
+namespace {
+
+int ensure_split(Plan* p, int64_t np) {
+  if (!p->split_count) {
+    bool ok = dalloc(&p->split_count, sizeof(uint32_t) * (kMaxCubes + 1)) == hipSuccess;
+    ok = ok && dalloc(&p->split_offset, sizeof(uint32_t) * (kMaxCubes + 1)) == hipSuccess;
+    ok = ok && dalloc(&p->split_cursor, sizeof(uint32_t) * kMaxCubes) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&p->h_split), sizeof(uint32_t) * (kMaxCubes + 1),
+                             hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc(&p->h_stage_sub, p->stage_bytes * kMaxCubes, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+      dfree(p->split_count);
+      dfree(p->split_offset);
+      dfree(p->split_cursor);
+      if (p->h_split) (void)hipHostFree(p->h_split);
+      if (p->h_stage_sub) (void)hipHostFree(p->h_stage_sub);
+      p->split_count = p->split_offset = p->split_cursor = p->h_split = nullptr;
+      p->h_stage_sub = nullptr;
+      return MPS_E_NOMEM;
+    }
+  }
+  if (np <= p->split_cap) return MPS_OK;
+  dfree(p->split_pos);
+  dfree(p->split_vel);
+  dfree(p->split_w);
+  p->split_pos = p->split_vel = p->split_w = nullptr;
+  p->split_cap = 0;
+  const size_t n = static_cast<size_t>(np);
+  bool ok = dalloc(&p->split_pos, sizeof(float) * 3 * n) == hipSuccess;
+  ok = ok && dalloc(&p->split_vel, sizeof(float) * 3 * n) == hipSuccess;
+  ok = ok && dalloc(&p->split_w, sizeof(float) * n) == hipSuccess;
+  if (!ok) {
+    dfree(p->split_pos);
+    dfree(p->split_vel);
+    dfree(p->split_w);
+    p->split_pos = p->split_vel = p->split_w = nullptr;
+    return MPS_E_NOMEM;
+  }
+  p->split_cap = np;
+  return MPS_OK;
+}
+
+// Mean and sample standard deviation (divisor m - 1) of one value over the
+// m staged sub-cube results; v(i) is the value of the i-th.
+template <typename F>
+void spread(int m, F v, double* mean, double* sdev) {
+  double s = 0.0;
+  for (int i = 0; i < m; ++i) s += v(i);
+  const double mu = m > 0 ? s / m : NAN;
+  double q = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double d = v(i) - mu;
+    q += d * d;
+  }
+  if (mean) *mean = mu;
+  if (sdev) *sdev = m > 1 ? std::sqrt(q / (m - 1)) : NAN;
+}
+
+void subcube_stats(const std::vector<const char*>& ok_stages, int n_bins, mps_result* mean, mps_result* sdev) {
+  const int m = static_cast<int>(ok_stages.size());
+  auto bins = [&](int i) {
+    return reinterpret_cast<const double*>(ok_stages[i] + sizeof(ResultHeader));
+  };
+  auto head = [&](int i) { return reinterpret_cast<const ResultHeader*>(ok_stages[i]); };
+  struct Field {
+    int q;
+    double* mps_result::*member;
+  };
+  const Field fields[] = {{QKsum, &mps_result::k_mean}, {QPdd, &mps_result::p_dd}, {QPpp, &mps_result::p_pp},
+                          {QPtt, &mps_result::p_tt},    {QPdt, &mps_result::p_dt}, {QSdd, &mps_result::sn_dd},
+                          {QSpp, &mps_result::sn_pp},   {QStt, &mps_result::sn_tt}};
+  for (const Field& f : fields) {
+    double* om = mean ? mean->*(f.member) : nullptr;
+    double* os = sdev ? sdev->*(f.member) : nullptr;
+    for (int b = 0; b < n_bins; ++b)
+      spread(m, [&](int i) { return bins(i)[b * kNumQ + f.q]; }, om ? om + b : nullptr, os ? os + b : nullptr);
+  }
+  for (mps_result* r : {mean, sdev})
+    if (r && r->n_modes)
+      for (int b = 0; b < n_bins; ++b)
+        r->n_modes[b] = m > 0 ? static_cast<int64_t>(std::llround(bins(0)[b * kNumQ + QCount])) : 0;
+  double dm = 0.0, ds = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    spread(m, [&](int i) { return head(i)->d.vb[a]; }, &dm, &ds);
+    if (mean) mean->v_bulk[a] = dm;
+    if (sdev) sdev->v_bulk[a] = ds;
+  }
+  spread(m, [&](int i) { return head(i)->d.sigma_v2; }, &dm, &ds);
+  if (mean) mean->sigma_v2 = dm;
+  if (sdev) sdev->sigma_v2 = ds;
+  spread(m, [&](int i) { return head(i)->d.W * head(i)->d.W / head(i)->d.W2; }, &dm, &ds);
+  if (mean) mean->n_eff = dm;
+  if (sdev) sdev->n_eff = ds;
+}
+
+}  // namespace
+}  // namespace mps
+
+extern "C" {
+
+int mps_estimate_subcubes(mps_plan* plan, const mps_catalog* cat, int n_div, mps_result* outs, int* status,
+                          mps_result* mean, mps_result* sdev, hipStream_t stream) {
+  if (!plan || !outs || !status) return MPS_E_ARG;
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  int st = validate_catalog(p, cat);
+  if (st != MPS_OK) return st;
+  if (n_div < 1 || n_div > MPS_MAX_DIV) return MPS_E_ARG;
+  const int n_cubes = n_div * n_div * n_div;
+  mps_catalog sub = *cat;
+  sub.box = cat->box / n_div;
+  if (!(sub.box > 0.0)) return MPS_E_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return MPS_E_HIP;
+  if ((st = ensure_bins(p, &sub)) != MPS_OK) return st;
+  if ((st = ensure_split(p, cat->n_particles)) != MPS_OK) return st;
+
+  SplitParams sp;
+  sp.scale = static_cast<double>(n_div) / cat->box;
+  sp.sub_box = sub.box;
+  sp.n_div = n_div;
+  sp.n_cubes = n_cubes;
+  MPS_TRY(launch_split_count(cat, sp, p->split_count, stream));
+  MPS_TRY(hipMemcpyAsync(p->h_split, p->split_count, sizeof(uint32_t) * (n_cubes + 1), hipMemcpyDeviceToHost,
+                         stream));
+  MPS_TRY(launch_split_permute(cat, sp, p->split_count, p->split_offset, p->split_cursor, p->split_pos,
+                               p->split_vel, cat->weight ? p->split_w : nullptr, stream));
+  if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
+  if (p->h_split[n_cubes]) return MPS_E_NONFINITE;
+  std::vector<uint32_t> count(p->h_split, p->h_split + n_cubes);
+  int64_t largest = 0;
+  for (uint32_t c : count) largest = c > largest ? c : largest;
+  if ((st = ensure_particles(p, largest)) != MPS_OK) return st;
+
+  std::vector<mps_catalog> cats(n_cubes, sub);
+  int64_t off = 0;
+  char* stage = static_cast<char*>(p->h_stage_sub);
+  for (int s = 0; s < n_cubes; ++s) {
+    cats[s].n_particles = count[s];
+    cats[s].pos = p->split_pos + 3 * off;
+    cats[s].vel = p->split_vel + 3 * off;
+    cats[s].weight = cat->weight ? p->split_w + off : nullptr;
+    off += count[s];
+    status[s] = MPS_E_ZEROWEIGHT;
+    if (count[s] == 0) continue;
+    if ((st = enqueue_estimate(p, &cats[s], stream, stage + p->stage_bytes * s)) != MPS_OK) return st;
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
+  std::vector<const char*> ok_stages;
+  for (int s = 0; s < n_cubes; ++s) {
+    if (count[s] == 0) continue;
+    const char* slot = stage + p->stage_bytes * s;
+    status[s] = unpack(p, &cats[s], &outs[s], slot);
+    if (status[s] == MPS_OK) ok_stages.push_back(slot);
+  }
+  if (mean || sdev) subcube_stats(ok_stages, sub.n_bins, mean, sdev);
+  return MPS_OK;
 }
 
 int mps_assign(mps_plan* plan, const mps_catalog* cat, void* grids, hipStream_t stream) {

@@ -28,6 +28,15 @@ enum MuQ {
   MSdd, MSpp, MStt, MSdtIm, MSdpb, kNumQMu
 };
 constexpr int kMaxMuCells = MPS_MAX_MU_CELLS;
+constexpr int kMaxCubes = MPS_MAX_SUBCUBES;  // n_div^3 for n_div <= MPS_MAX_DIV
+
+// Split of a catalog into n_div^3 sub-cubes (subcubes.hip).
+struct SplitParams {
+  double scale;    // n_div / L
+  double sub_box;  // L / n_div
+  int n_div;
+  int n_cubes;     // n_div^3
+};
 
 // Polynomial weights of the six taps: w_j(f) = sum_p coef[j][p] f^p with
 // f = u - floor(u) in [0, 1).  FP64.
@@ -117,6 +126,17 @@ struct Plan {
   double* d_mu_bins = nullptr;       // kMaxMuCells x kNumQMu
   void* h_stage_mu = nullptr;        // pinned: header + kMaxMuCells x kNumQMu
 
+  // sub-cube split (allocated on first use)
+  float* split_pos = nullptr;        // split_cap x 3
+  float* split_vel = nullptr;        // split_cap x 3
+  float* split_w = nullptr;          // split_cap
+  int64_t split_cap = 0;
+  uint32_t* split_count = nullptr;   // kMaxCubes counts + 1 flag
+  uint32_t* split_offset = nullptr;  // kMaxCubes + 1
+  uint32_t* split_cursor = nullptr;  // kMaxCubes
+  uint32_t* h_split = nullptr;       // pinned copy of split_count
+  void* h_stage_sub = nullptr;       // pinned: kMaxCubes result slots of stage_bytes
+
   // host staging (pinned): header + bins
   void* h_stage = nullptr;
   size_t stage_bytes = 0;
@@ -144,8 +164,11 @@ constexpr int kMomentBlocks = 1024;
 int validate_catalog(const Plan* p, const mps_catalog* c);
 int ensure_bins(Plan* p, const mps_catalog* c);
 int ensure_particles(Plan* p, int64_t np);
-int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s);  // async, incl. D2H
-int unpack(Plan* p, const mps_catalog* c, mps_result* out);          // after the stream synced
+// Async, including the copy of the results to `stage` (the plan's own
+// staging buffer when NULL).
+int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s, void* stage = nullptr);
+// After the stream synced; reads `stage` (the plan's own when NULL).
+int unpack(Plan* p, const mps_catalog* c, mps_result* out, const void* stage = nullptr);
 
 // Launchers (particles.hip).  All enqueue on `stream`.
 hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s);
@@ -165,5 +188,11 @@ hipError_t launch_finalize(Plan* p, const mps_catalog* c, hipStream_t s);
 // NULL for the bulk-flow direction (computed on the device).
 hipError_t launch_mu_bin(Plan* p, const mps_catalog* c, int n_mu, const double* axis, hipStream_t s);
 hipError_t launch_finalize_mu(Plan* p, const mps_catalog* c, int n_mu, hipStream_t s);
+
+// Launchers (subcubes.hip).  count: n_cubes counts, then a non-finite flag.
+hipError_t launch_split_count(const mps_catalog* c, const SplitParams& sp, uint32_t* count, hipStream_t s);
+hipError_t launch_split_permute(const mps_catalog* c, const SplitParams& sp, const uint32_t* count,
+                                uint32_t* offset, uint32_t* cursor, float* out_pos, float* out_vel, float* out_w,
+                                hipStream_t s);
 
 }  // namespace mps

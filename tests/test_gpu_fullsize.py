@@ -22,7 +22,7 @@ import torch
 from scipy.special import jv, jvp
 
 import oracle
-from gpu_common import guarded_rel
+from gpu_common import compare_spectra, guarded_rel
 from synth import catalogs
 
 pytestmark = pytest.mark.gpu
@@ -181,6 +181,43 @@ def test_fullsize_translation_by_whole_cells(mps, zel512, prec):
     # u = x N / L is rounded in FP64 either way: a particle within ~1e-13 of
     # a cell edge may change cell, a change of order 1e-10 in a spectrum
     assert max(errs.values()) < (1e-8 if prec == "f64" else 3e-4), errs
+
+
+def test_fullsize_subcubes(mps, zel512, zel512_dev):
+    """The 64 sub-samples of the benchmark catalog: 4^3 cubes of 250 Mpc/h,
+    each on a 128^3 grid (the 512^3 grid's spacing).  Particle counts per
+    cube are exact; one sampled cube matches the oracle; FP32 matches FP64 on
+    every cube and on the mean and spread."""
+    pos, vel = zel512
+    cube, local = oracle.subcubes.split(pos, BOX, 4)
+    counts = np.bincount(cube, minlength=64).astype(np.float64)
+    res = {}
+    for prec in ("f64", "f32"):
+        plan = mps.Plan(128, prec)
+        res[prec] = plan.estimate_subcubes(*zel512_dev, box=BOX, haf=HAF, n_div=4)
+        plan.close()
+        assert np.all(res[prec]["status"] == 0)
+        assert [r["n_eff"] for r in res[prec]["sub"]] == counts.tolist()
+    c = 37
+    sel = cube == c
+    print("oracle on cube", c, "with", int(sel.sum()), "particles", flush=True)
+    want = oracle.estimate(local[sel], vel[sel], box=BOX / 4, n_grid=128, haf=HAF)
+    for prec in ("f64", "f32"):
+        compare_spectra(res[prec]["sub"][c], want, 1e-5 if prec == "f64" else 3e-4, f"{prec} cube {c}")
+    a, b = res["f32"], res["f64"]
+    worst = {}
+    for key, sk in (("p_pp", "sn_pp"), ("p_tt", "sn_tt"), ("p_dd", "sn_dd"), ("p_dt", None)):
+        for s in range(64):
+            sn = b["sub"][s][sk] if sk else np.sqrt(b["sub"][s]["sn_dd"] * b["sub"][s]["sn_tt"])
+            e = float(guarded_rel(a["sub"][s][key], b["sub"][s][key], sn).max())
+            worst[key] = max(worst.get(key, 0.0), e)
+        sn = b["mean"][sk] if sk else np.sqrt(b["mean"]["sn_dd"] * b["mean"]["sn_tt"])
+        worst[key + " mean"] = float(guarded_rel(a["mean"][key], b["mean"][key], sn).max())
+        ok = np.isfinite(b["sdev"][key])
+        worst[key + " sdev"] = float(np.max(np.abs(a["sdev"][key][ok] - b["sdev"][key][ok])
+                                            / (np.abs(b["mean"][key][ok]) + np.abs(sn[ok]))))
+    print("sub-cubes FP32 vs FP64 max guarded error:", worst, flush=True)
+    assert max(worst.values()) <= 3e-4, worst
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
