@@ -10,4 +10,4 @@ from .estimator import (  # noqa: F401
     edges_bin_index, estimate, fourier_fields, mode_quantities, moments)
 from . import bl3  # noqa: F401
 from .anisotropic import estimate_mu, mu_bin, unit_axis  # noqa: F401
-from . import subcubes  # noqa: F401
+from . import bspline, subcubes  # noqa: F401

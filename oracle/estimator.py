@@ -80,14 +80,16 @@ def cell_and_fraction(pos, box: float, n_grid: int):
     return cell, frac
 
 
-KERNELS = ("bl3", "bl3_exact")
+KERNELS = ("bl3", "bl3_exact", "ngp", "cic", "tsc", "pcs", "pqs", "bspline6",
+           "bspline1", "bspline2", "bspline3", "bspline4", "bspline5")
 
 
 def assign(pos, charges, box: float, n_grid: int, kernel: str = "bl3"):
     """Assign charges q[c, j] of particles j to 4 periodic grids with BL3.
 
     kernel "bl3" (default) is the six-tap truncated function described below;
-    "bl3_exact" is the untruncated function (oracle.exact_bl3).
+    "bl3_exact" is the untruncated function (oracle.exact_bl3); the B-spline
+    kernels ("ngp" .. "bspline6") are in oracle.bspline.
 
     Each particle deposits q * phi(jx - fx) phi(jy - fy) phi(jz - fz) on node
     (cell + (jx, jy, jz)) mod N for every tap j in {-2..3}^3 (Eq. rawFFTed with
@@ -97,6 +99,9 @@ def assign(pos, charges, box: float, n_grid: int, kernel: str = "bl3"):
     if kernel == "bl3_exact":
         from . import exact_bl3
         return exact_bl3.assign_exact(pos, charges, box, n_grid)
+    from . import bspline
+    if bspline.order_of(kernel):
+        return bspline.assign(pos, charges, box, n_grid, bspline.order_of(kernel))
     if kernel != "bl3":
         raise ValueError(f"unknown kernel {kernel!r}")
     charges = np.atleast_2d(np.asarray(charges, dtype=np.float64))
@@ -237,6 +242,9 @@ def axis_tables(n_grid: int, kernel: str = "bl3"):
     if kernel == "bl3_exact":
         # orthonormal phi: the alias sum of phi_hat^2 is 1
         return bl3.phi_hat(omega) ** 2, np.ones(n_grid)
+    from . import bspline
+    if bspline.order_of(kernel):
+        return bspline.axis_tables(n_grid, bspline.order_of(kernel))
     return bl3.window_trunc(omega) ** 2, bl3.alias_sum_trunc(omega)
 
 
