@@ -79,6 +79,20 @@ enum {
   MPS_KERNEL_BL3_EXACT = 1u << 3
 };
 
+/* Assignment with the centred B-spline of order p (degree p - 1) instead of
+ * BL3: the comparison kernels of Sec. 2.4.1 (a fifth-order B-spline) and
+ * Sec. 2.4.3 (nearest grid point).  p = 1 NGP, 2 CIC, 3 TSC, 4 PCS, 5 PQS,
+ * 6 the quintic.  Node g receives beta_{p-1}(g - u) (u the particle's grid
+ * coordinate; the box beta_0 is 1 on (-1/2, 1/2], so with p = 1 a particle
+ * joins node floor(u + 1/2), the sum rounded in FP64).  The spectra are
+ * deconvolved by the window sinc^p(w/2) per axis, and the shot terms scale
+ * with the alias sum sum_m beta_{2p-1}(m) cos(m w).  Put
+ * MPS_KERNEL_BSPLINE(p) in the flags; it cannot be combined with
+ * MPS_KERNEL_BL3_EXACT (which equals MPS_KERNEL_BSPLINE(4) in its
+ * spectra). */
+#define MPS_KERNEL_ORDER_SHIFT 4
+#define MPS_KERNEL_BSPLINE(p) ((uint32_t)(p) << MPS_KERNEL_ORDER_SHIFT)
+
 /* One catalog.  The caller owns every buffer; they must stay valid until the
  * call that uses them returns (or, for mps_submit, until mps_wait reports the
  * ticket done).  The library never frees or retains them. */

@@ -55,10 +55,10 @@ void release(Plan* p) {
   dfree(p->tile_queue);
   dfree(p->moment_partials);
   dfree(p->d_header);
-  dfree(p->d_win2);
-  dfree(p->d_alias);
-  dfree(p->d_win2_pcs);
-  dfree(p->d_alias_pcs);
+  for (int k = 0; k < kNumKernels; ++k) {
+    dfree(p->d_iwin2[k]);
+    dfree(p->d_alias[k]);
+  }
   dfree(p->d_twiddle);
   dfree(p->d_lut);
   dfree(p->d_bin_partials);
@@ -88,7 +88,9 @@ int validate_catalog(const Plan* p, const mps_catalog* c) {
   if (!(c->box > 0.0) || !std::isfinite(c->box)) return MPS_E_ARG;
   if (!(c->haf > 0.0) || !std::isfinite(c->haf)) return MPS_E_ARG;
   if (c->n_bins < 1 || c->n_bins > kMaxBins) return MPS_E_ARG;
-  if (c->flags & ~15u) return MPS_E_ARG;
+  if (c->flags & ~(15u | (7u << MPS_KERNEL_ORDER_SHIFT))) return MPS_E_ARG;
+  const uint32_t order = (c->flags >> MPS_KERNEL_ORDER_SHIFT) & 7u;
+  if (order > 6 || (order != 0 && (c->flags & MPS_KERNEL_BL3_EXACT))) return MPS_E_ARG;
   (void)p;
   return MPS_OK;
 }
@@ -253,10 +255,10 @@ int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec) {
   ok = ok && dalloc(&p->tile_queue, sizeof(uint32_t) * 8) == hipSuccess;
   ok = ok && dalloc(&p->moment_partials, sizeof(double) * kMomentBlocks * (kMomentSums + kMomentMax)) == hipSuccess;
   ok = ok && dalloc(&p->d_header, sizeof(ResultHeader)) == hipSuccess;
-  ok = ok && dalloc(&p->d_win2, sizeof(double) * (half + 1)) == hipSuccess;
-  ok = ok && dalloc(&p->d_alias, sizeof(double) * (half + 1)) == hipSuccess;
-  ok = ok && dalloc(&p->d_win2_pcs, sizeof(double) * (half + 1)) == hipSuccess;
-  ok = ok && dalloc(&p->d_alias_pcs, sizeof(double) * (half + 1)) == hipSuccess;
+  for (int k = 0; k < kNumKernels; ++k) {
+    ok = ok && dalloc(&p->d_iwin2[k], sizeof(double) * (half + 1)) == hipSuccess;
+    ok = ok && dalloc(&p->d_alias[k], sizeof(double) * (half + 1)) == hipSuccess;
+  }
   ok = ok && dalloc(&p->d_twiddle, 2 * p->real_size * n_grid) == hipSuccess;
   ok = ok && dalloc(&p->d_lut, sizeof(int32_t) * half * half) == hipSuccess;
   ok = ok && dalloc(&p->d_bin_partials, sizeof(double) * p->bin_blocks * kMaxBins * kNumQ) == hipSuccess;
@@ -268,23 +270,25 @@ int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec) {
     release(p);
     return MPS_E_NOMEM;
   }
-  p->taps = bl3_tap_polynomials();
-  p->tap_bound = tap_bounds(p->taps, kTaps);
-  p->taps_pcs = pcs_tap_polynomials();
-  p->tap_bound_pcs = tap_bounds(p->taps_pcs, 4);
-  std::vector<double> win2, alias;
-  bl3_axis_tables(n_grid, &win2, &alias);
   const std::vector<double> tw = twiddles(n_grid);
-  // the x pass multiplies by W_t^-2 per axis
-  for (double& w : win2) w = 1.0 / w;
-  bool up = hipMemcpy(p->d_win2, win2.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) == hipSuccess;
-  up = up && hipMemcpy(p->d_alias, alias.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) == hipSuccess;
-  std::vector<double> iwin2_pcs, alias_pcs;
-  pcs_axis_tables(n_grid, &iwin2_pcs, &alias_pcs);
-  up = up && hipMemcpy(p->d_win2_pcs, iwin2_pcs.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) ==
-                 hipSuccess;
-  up = up && hipMemcpy(p->d_alias_pcs, alias_pcs.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) ==
-                 hipSuccess;
+  bool up = true;
+  for (int k = 0; k < kNumKernels; ++k) {
+    std::vector<double> iwin2, alias;
+    if (k == 0) {
+      p->taps[k] = bl3_tap_polynomials();
+      bl3_axis_tables(n_grid, &iwin2, &alias);
+      // the x pass multiplies by W_t^-2 per axis
+      for (double& w : iwin2) w = 1.0 / w;
+    } else {
+      p->taps[k] = bspline_tap_polynomials(k);
+      bspline_axis_tables(n_grid, k, &iwin2, &alias);
+    }
+    p->tap_bound[k] = tap_bounds(p->taps[k], kernel_taps(k));
+    up = up && hipMemcpy(p->d_iwin2[k], iwin2.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) ==
+                   hipSuccess;
+    up = up && hipMemcpy(p->d_alias[k], alias.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) ==
+                   hipSuccess;
+  }
   if (prec == MPS_F32) {
     std::vector<float> twf(tw.begin(), tw.end());
     up = up && hipMemcpy(p->d_twiddle, twf.data(), sizeof(float) * twf.size(), hipMemcpyHostToDevice) == hipSuccess;

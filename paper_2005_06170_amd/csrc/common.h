@@ -38,11 +38,27 @@ struct SplitParams {
   int n_cubes;     // n_div^3
 };
 
-// Polynomial weights of the six taps: w_j(f) = sum_p coef[j][p] f^p with
-// f = u - floor(u) in [0, 1).  FP64.
+// Polynomial weights of up to six taps: w_j(f) = sum_p coef[j][p] f^p with
+// f = u - floor(u) in [0, 1) (u shifted by half a cell for the odd-order
+// B-splines), degree <= 5.  FP64.
+constexpr int kPolyCoef = 6;
 struct TapPoly {
-  double c[kTaps][4];
+  double c[kTaps][kPolyCoef];
 };
+
+// Assignment kernels: 0 the truncated BL3 function (6 taps, cubic pieces);
+// p = 1..6 the centred B-spline of order p (p taps, degree p - 1; order 4
+// also serves the untruncated BL3 function, whose deconvolved spectra are
+// those of the cubic B-spline).
+constexpr int kNumKernels = 7;
+inline int kernel_id(uint32_t flags) {
+  if (flags & MPS_KERNEL_BL3_EXACT) return 4;
+  return static_cast<int>((flags >> MPS_KERNEL_ORDER_SHIFT) & 7u);
+}
+inline int kernel_taps(int id) { return id == 0 ? kTaps : id; }
+inline int kernel_degree(int id) { return id == 0 ? 3 : id - 1; }
+// half a cell for odd orders: taps are centred on the nearest node
+inline double kernel_shift(int id) { return (id & 1) ? 0.5 : 0.0; }
 
 // Upper bounds of |w_j(f)| over f in [0, 1) for the six taps.
 struct TapBound {
@@ -77,13 +93,13 @@ struct Plan;
 // ----------------------------------------------------------------- tables
 // Host-side FP64 construction of the truncated cubic Battle-Lemarie kernel.
 TapPoly bl3_tap_polynomials();
-// Bounds of |w_j| on [0, 1] (ends and stationary points) for the first
-// n_taps taps, with a small margin.
+// Bounds of |w_j| on [0, 1] for the first n_taps taps, with a small margin.
 TapBound tap_bounds(const TapPoly& tp, int n_taps);
-// Tap polynomials of the centred cubic B-spline, taps j = -1..2 (4 of the 6).
-TapPoly pcs_tap_polynomials();
-// 1 / (sinc(w/2)^4)^2 and A(w) for w = 2 pi n / N, n = 0..N/2.
-void pcs_axis_tables(int n_grid, std::vector<double>* inv_win2, std::vector<double>* alias);
+// Tap polynomials of the centred B-spline of order p = 1..6.
+TapPoly bspline_tap_polynomials(int order);
+// 1 / sinc^(2p)(w/2) and the alias sum sum_m beta_{2p-1}(m) cos(m w) for
+// w = 2 pi n / N, n = 0..N/2.
+void bspline_axis_tables(int n_grid, int order, std::vector<double>* inv_win2, std::vector<double>* alias);
 // W_t(2 pi n / N)^2 and C_t(2 pi n / N) for n = 0..N/2.
 void bl3_axis_tables(int n_grid, std::vector<double>* win2, std::vector<double>* alias);
 // e^{-2 pi i m / N}, m = 0..N-1, interleaved (re, im).
@@ -111,10 +127,8 @@ struct Plan {
   int num_cus = 256;
   double* moment_partials = nullptr; // kMomentBlocks x (kMomentSums + kMomentMax)
   ResultHeader* d_header = nullptr;
-  double* d_win2 = nullptr;          // N/2 + 1: 1 / W_t(2 pi n / N)^2
-  double* d_alias = nullptr;         // N/2 + 1
-  double* d_win2_pcs = nullptr;      // N/2 + 1: 1 / sinc^8(pi n / N)
-  double* d_alias_pcs = nullptr;     // N/2 + 1: A(2 pi n / N)
+  double* d_iwin2[kNumKernels] = {};  // per kernel, N/2 + 1: 1 / W(2 pi n / N)^2
+  double* d_alias[kNumKernels] = {};  // per kernel, N/2 + 1: sum_J W^2(w + 2 pi J)
   void* d_twiddle = nullptr;         // N complex of the plan's precision
   int32_t* d_lut = nullptr;          // (N/2)^2
   double* d_bin_partials = nullptr;  // bin_blocks x kMaxBins x kNumQ
@@ -147,10 +161,8 @@ struct Plan {
   std::vector<double> lut_edges;     // edges the LUT was built for (empty: default)
   std::vector<double> edges_used;    // n_bins + 1 edges actually used
 
-  TapPoly taps;                      // truncated BL3, 6 taps
-  TapBound tap_bound;
-  TapPoly taps_pcs;                  // cubic B-spline, 4 taps (untruncated BL3)
-  TapBound tap_bound_pcs;
+  TapPoly taps[kNumKernels];         // per kernel (see kernel_id)
+  TapBound tap_bound[kNumKernels];
 
   // stage timing
   bool timing = false;

@@ -722,10 +722,10 @@ hipError_t run_x_bin(Plan* p, const mps_catalog* c, hipStream_t s) {
   bp.no_shot = (c->flags & MPS_NO_SHOTNOISE) ? 1 : 0;
   bp.no_deconv = (c->flags & MPS_NO_DECONVOLVE) ? 1 : 0;
   bp.bulk = (c->flags & MPS_BULKFLOW_SUBTRACT) ? 1 : 0;
-  const bool exact = (c->flags & MPS_KERNEL_BL3_EXACT) != 0;
+  const int kid = kernel_id(c->flags);
   fft_x_bin_kernel<T, N, B, 512><<<static_cast<unsigned>(p->bin_blocks), 512, 0, s>>>(
-      static_cast<const T*>(p->grid), static_cast<const cpx<T>*>(p->d_twiddle), p->d_header,
-      exact ? p->d_win2_pcs : p->d_win2, exact ? p->d_alias_pcs : p->d_alias, p->d_lut, bp, p->d_bin_partials);
+      static_cast<const T*>(p->grid), static_cast<const cpx<T>*>(p->d_twiddle), p->d_header, p->d_iwin2[kid],
+      p->d_alias[kid], p->d_lut, bp, p->d_bin_partials);
   return hipGetLastError();
 }
 
@@ -742,10 +742,10 @@ hipError_t run_mu_bin(Plan* p, const mps_catalog* c, int n_mu, const double* axi
   mp.no_shot = (c->flags & MPS_NO_SHOTNOISE) ? 1 : 0;
   mp.no_deconv = (c->flags & MPS_NO_DECONVOLVE) ? 1 : 0;
   mp.bulk = (c->flags & MPS_BULKFLOW_SUBTRACT) ? 1 : 0;
-  const bool exact = (c->flags & MPS_KERNEL_BL3_EXACT) != 0;
+  const int kid = kernel_id(c->flags);
   mu_bin_kernel<T, N, 512><<<static_cast<unsigned>(p->num_cus), 512, 0, s>>>(
-      static_cast<const T*>(p->grid), p->d_header, exact ? p->d_win2_pcs : p->d_win2,
-      exact ? p->d_alias_pcs : p->d_alias, p->d_lut, mp, p->d_mu_partials);
+      static_cast<const T*>(p->grid), p->d_header, p->d_iwin2[kid], p->d_alias[kid], p->d_lut, mp,
+      p->d_mu_partials);
   return hipGetLastError();
 }
 

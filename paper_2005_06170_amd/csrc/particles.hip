@@ -19,13 +19,15 @@ namespace {
 
 constexpr int kCountThreads = 256;
 
-// Grid coordinate of one float32 coordinate: u = x * (N / L) in FP64, cell
-// floor(u) mod N, fraction f = u - floor(u).  The same expression, without
-// fused operations, decides the tile in the sort and the taps in the
-// scatter.
-__device__ __forceinline__ int locate(float x, double scale, int n, double* frac, bool* ok) {
+// Grid coordinate of one float32 coordinate: u = x * (N / L) + shift in FP64
+// (shift = 1/2 for the odd-order B-splines, whose taps are centred on the
+// nearest node; 0 otherwise), cell floor(u) mod N, fraction f = u - floor(u).
+// The same expression, without fused operations, decides the tile in the
+// sort and the taps in the scatter.
+__device__ __forceinline__ int locate(float x, double scale, double shift, int n, double* frac, bool* ok) {
 #pragma clang fp contract(off)
   double u = static_cast<double>(x) * scale;
+  u = u + shift;
   const bool fin = isfinite(u);
   if (!fin) u = 0.0;
   const double uf = floor(u);
@@ -94,6 +96,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 struct KeyParams {
   double scale;  // N / L
+  double shift;  // added to u = x N / L (see locate)
   int n;         // grid size
   int tshift;    // log2(tile)
   int nt;        // tiles per axis
@@ -102,9 +105,9 @@ struct KeyParams {
 __device__ __forceinline__ uint32_t tile_key(float x, float y, float z, const KeyParams& kp, bool* ok) {
   double f;
   bool a, b, c;
-  const int cx = locate(x, kp.scale, kp.n, &f, &a);
-  const int cy = locate(y, kp.scale, kp.n, &f, &b);
-  const int cz = locate(z, kp.scale, kp.n, &f, &c);
+  const int cx = locate(x, kp.scale, kp.shift, kp.n, &f, &a);
+  const int cy = locate(y, kp.scale, kp.shift, kp.n, &f, &b);
+  const int cz = locate(z, kp.scale, kp.shift, kp.n, &f, &c);
   *ok = a && b && c;
   return static_cast<uint32_t>(((cx >> kp.tshift) * kp.nt + (cy >> kp.tshift)) * kp.nt + (cz >> kp.tshift));
 }
@@ -396,8 +399,12 @@ __global__ __launch_bounds__(256) void clear_kernel(T* __restrict__ g, int64_t n
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) g[i] = T(0);
 }
 
+template <int DEG>
 __device__ __forceinline__ double tap_weight(const TapPoly& tp, int j, double f) {
-  return ((tp.c[j][3] * f + tp.c[j][2]) * f + tp.c[j][1]) * f + tp.c[j][0];
+  double v = tp.c[j][DEG];
+#pragma unroll
+  for (int q = DEG - 1; q >= 0; --q) v = v * f + tp.c[j][q];
+  return v;
 }
 
 template <typename T>
@@ -426,23 +433,24 @@ __device__ __forceinline__ DepositQ<T> charges(const float4& a, const float4& v,
   return d;
 }
 
-// Kernels with NTAP taps per axis: the truncated BL3 function (6 taps,
-// j = -2..3) or the cubic B-spline of the untruncated BL3 path (4 taps,
-// j = -1..2).  The LDS block is the tile plus a halo of kHaloLo cells below
-// and NTAP - 1 - kHaloLo above.
+// Kernels with NTAP taps per axis whose weights are polynomials of degree
+// DEG in the fraction: the truncated BL3 function (6 taps, j = -2..3, cubic)
+// or the B-spline of order NTAP (taps j = -(NTAP-1)/2 .. NTAP/2, degree
+// NTAP - 1; for odd orders relative to the nearest node).  The LDS block is
+// the tile plus a halo of kHaloLo cells below and NTAP - 1 - kHaloLo above.
 template <int NTAP>
-constexpr int kHaloLo = NTAP / 2 - 1;
+constexpr int kHaloLo = (NTAP - 1) / 2;
 
 // Tap weights and the particle's cell relative to the tile origin.
-template <typename T, int TS, int NTAP>
+template <typename T, int TS, int NTAP, int DEG>
 __device__ __forceinline__ unsigned particle_taps(const float4& a, const KeyParams& kp, int ox, int oy, int oz,
                                                   const TapPoly& tp, T* wx, T* wy, T* wz) {
   constexpr int E = TS + NTAP - 1;
   double fx, fy, fz;
   bool ok;
-  int cx = locate(a.x, kp.scale, kp.n, &fx, &ok) - ox;
-  int cy = locate(a.y, kp.scale, kp.n, &fy, &ok) - oy;
-  int cz = locate(a.z, kp.scale, kp.n, &fz, &ok) - oz;
+  int cx = locate(a.x, kp.scale, kp.shift, kp.n, &fx, &ok) - ox;
+  int cy = locate(a.y, kp.scale, kp.shift, kp.n, &fy, &ok) - oy;
+  int cz = locate(a.z, kp.scale, kp.shift, kp.n, &fz, &ok) - oz;
   // the sort placed the particle in this tile with the same locate(); the
   // clamp only keeps LDS indices in range
   cx = min(max(cx, 0), TS - 1);
@@ -450,9 +458,9 @@ __device__ __forceinline__ unsigned particle_taps(const float4& a, const KeyPara
   cz = min(max(cz, 0), TS - 1);
 #pragma unroll
   for (int j = 0; j < NTAP; ++j) {
-    wx[j] = static_cast<T>(tap_weight(tp, j, fx));
-    wy[j] = static_cast<T>(tap_weight(tp, j, fy));
-    wz[j] = static_cast<T>(tap_weight(tp, j, fz));
+    wx[j] = static_cast<T>(tap_weight<DEG>(tp, j, fx));
+    wy[j] = static_cast<T>(tap_weight<DEG>(tp, j, fy));
+    wz[j] = static_cast<T>(tap_weight<DEG>(tp, j, fz));
   }
   return static_cast<unsigned>((cx * E + cy) * E + cz);
 }
@@ -508,9 +516,9 @@ __device__ __forceinline__ unsigned tap_origin(const float4& a, const KeyParams&
   constexpr int E = TS + NTAP - 1;
   double f;
   bool ok;
-  int cx = locate(a.x, kp.scale, kp.n, &f, &ok) - ox;
-  int cy = locate(a.y, kp.scale, kp.n, &f, &ok) - oy;
-  int cz = locate(a.z, kp.scale, kp.n, &f, &ok) - oz;
+  int cx = locate(a.x, kp.scale, kp.shift, kp.n, &f, &ok) - ox;
+  int cy = locate(a.y, kp.scale, kp.shift, kp.n, &f, &ok) - oy;
+  int cz = locate(a.z, kp.scale, kp.shift, kp.n, &f, &ok) - oz;
   cx = min(max(cx, 0), TS - 1);
   cy = min(max(cy, 0), TS - 1);
   cz = min(max(cz, 0), TS - 1);
@@ -613,7 +621,7 @@ __device__ __forceinline__ void bound_line(const float (&in)[E], const TapBound&
 // the worst-case sum of the per-deposit rounding errors (half a unit per
 // particle).  A single pass over LDS gives both the bound and the zeroed
 // accumulator.
-template <int TS, int NT, int NTAP>
+template <int TS, int NT, int NTAP, int DEG>
 __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, float* __restrict__ grid,
     KeyParams kp, int64_t n_tiles, TileQueues tq, TapPoly tp, TapBound kb, const Derived* dsrc, int bulk) {
@@ -789,7 +797,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         const float4 a = sorted[2 * static_cast<int64_t>(p)];
         const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
         float wx[NTAP], wy[NTAP], wz[NTAP];
-        const unsigned base = particle_taps<float, TS, NTAP>(a, kp, ox, oy, oz, tp, wx, wy, wz);
+        const unsigned base = particle_taps<float, TS, NTAP, DEG>(a, kp, ox, oy, oz, tp, wx, wy, wz);
         const DepositQ<float> d = charges<float>(a, v, bulk, vb0, vb1, vb2);
         float qs[kNumFields];
 #pragma unroll
@@ -858,7 +866,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
 // FP64 grids: LDS accumulation with ds_add_f64 (~7 lanes/clk/CU on gfx950),
 // same tiles and bank-sorted lane order as the FP32 kernel (a double spans
 // two banks, so the key is the element index mod 32).
-template <int TS, int NT, int NTAP>
+template <int TS, int NT, int NTAP, int DEG>
 __global__ __launch_bounds__(NT) void scatter_f64_kernel(
     const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, double* __restrict__ grid,
     KeyParams kp, int64_t n_tiles, int64_t xcd_chunk, TapPoly tp, const Derived* dsrc, int bulk) {
@@ -919,7 +927,7 @@ __global__ __launch_bounds__(NT) void scatter_f64_kernel(
       const float4 a = sorted[2 * static_cast<int64_t>(p)];
       const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
       double wx[NTAP], wy[NTAP], wz[NTAP];
-      const unsigned base = particle_taps<double, TS, NTAP>(a, kp, ox, oy, oz, tp, wx, wy, wz);
+      const unsigned base = particle_taps<double, TS, NTAP, DEG>(a, kp, ox, oy, oz, tp, wx, wy, wz);
       const DepositQ<double> d = charges<double>(a, v, bulk, vb0, vb1, vb2);
       double qz[kNumFields][NTAP];
 #pragma unroll
@@ -960,6 +968,7 @@ __global__ __launch_bounds__(NT) void scatter_f64_kernel(
 KeyParams key_params(const Plan* p, const mps_catalog* c) {
   KeyParams kp;
   kp.scale = static_cast<double>(p->n) / c->box;
+  kp.shift = kernel_shift(kernel_id(c->flags));
   kp.n = p->n;
   int ts = 0;
   while ((1 << ts) < p->tile) ++ts;
@@ -1042,7 +1051,7 @@ hipError_t launch_clear_grid(Plan* p, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int NTAP>
+template <int NTAP, int DEG>
 hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int bulk, const TapPoly& tp,
                                const TapBound& tb) {
   const KeyParams kp = key_params(p, c);
@@ -1057,16 +1066,16 @@ hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int
     if (p->tile == 16) {
       // one workgroup per CU (the LDS holds one), never more than the tiles
       const int64_t blocks = p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus;
-      scatter_fixed_kernel<16, 1024, NTAP><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+      scatter_fixed_kernel<16, 1024, NTAP, DEG><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
           p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk);
     } else {
       const int64_t cap = 4 * static_cast<int64_t>(p->num_cus);
       const int64_t blocks = p->n_tiles < cap ? p->n_tiles : cap;
-      scatter_fixed_kernel<8, 512, NTAP><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
+      scatter_fixed_kernel<8, 512, NTAP, DEG><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
           p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk);
     }
   } else {
-    scatter_f64_kernel<8, 512, NTAP><<<static_cast<unsigned>(p->n_tiles), 512, 0, s>>>(
+    scatter_f64_kernel<8, 512, NTAP, DEG><<<static_cast<unsigned>(p->n_tiles), 512, 0, s>>>(
         p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, xcd_chunk, tp, dsrc, bulk);
   }
   return hipGetLastError();
@@ -1075,8 +1084,18 @@ hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int
 // bulk: 1 = deposit w (v - v_b) (only the assign diagnostic asks for it; the
 // estimator removes the bulk flow in Fourier space, p' = p - v_b delta).
 hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int bulk) {
-  if (c->flags & MPS_KERNEL_BL3_EXACT) return launch_scatter_taps<4>(p, c, s, bulk, p->taps_pcs, p->tap_bound_pcs);
-  return launch_scatter_taps<6>(p, c, s, bulk, p->taps, p->tap_bound);
+  const int k = kernel_id(c->flags);
+  const TapPoly& tp = p->taps[k];
+  const TapBound& tb = p->tap_bound[k];
+  switch (k) {
+    case 1: return launch_scatter_taps<1, 0>(p, c, s, bulk, tp, tb);
+    case 2: return launch_scatter_taps<2, 1>(p, c, s, bulk, tp, tb);
+    case 3: return launch_scatter_taps<3, 2>(p, c, s, bulk, tp, tb);
+    case 4: return launch_scatter_taps<4, 3>(p, c, s, bulk, tp, tb);
+    case 5: return launch_scatter_taps<5, 4>(p, c, s, bulk, tp, tb);
+    case 6: return launch_scatter_taps<6, 5>(p, c, s, bulk, tp, tb);
+    default: return launch_scatter_taps<6, 3>(p, c, s, bulk, tp, tb);
+  }
 }
 
 hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s) {

@@ -103,7 +103,7 @@ Pieces bl3_pieces() {
 
 TapPoly bl3_tap_polynomials() {
   const Pieces pc = bl3_pieces();
-  TapPoly tp;
+  TapPoly tp{};
   // tap j covers d = j - f in (j-1, j]: interval m = j-1 with t = 1 - f.
   // Substitute t = 1 - f: sum_p a_p (1 - f)^p.
   static const double binom[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
@@ -122,23 +122,39 @@ TapBound tap_bounds(const TapPoly& tp, int n_taps) {
   for (int j = 0; j < kTaps; ++j) b.k[j] = 0.f;
   for (int j = 0; j < n_taps; ++j) {
     const double* c = tp.c[j];
-    // |w_j| on [0, 1] peaks at an end or where w_j' = c1 + 2 c2 f + 3 c3 f^2 vanishes
-    double cand[4] = {0.0, 1.0, -1.0, -1.0};
-    const double qa = 3.0 * c[3], qb = 2.0 * c[2], qc = c[1];
-    if (qa != 0.0) {
-      const double disc = qb * qb - 4.0 * qa * qc;
-      if (disc >= 0.0) {
-        const double r = std::sqrt(disc);
-        cand[2] = (-qb + r) / (2.0 * qa);
-        cand[3] = (-qb - r) / (2.0 * qa);
-      }
-    } else if (qb != 0.0) {
-      cand[2] = -qc / qb;
-    }
     double m = 0.0;
-    for (double f : cand) {
-      if (f < 0.0 || f > 1.0) continue;
-      m = std::max(m, std::fabs(((c[3] * f + c[2]) * f + c[1]) * f + c[0]));
+    if (c[4] == 0.0 && c[5] == 0.0) {
+      // a cubic: |w_j| on [0, 1] peaks at an end or where
+      // w_j' = c1 + 2 c2 f + 3 c3 f^2 vanishes
+      double cand[4] = {0.0, 1.0, -1.0, -1.0};
+      const double qa = 3.0 * c[3], qb = 2.0 * c[2], qc = c[1];
+      if (qa != 0.0) {
+        const double disc = qb * qb - 4.0 * qa * qc;
+        if (disc >= 0.0) {
+          const double r = std::sqrt(disc);
+          cand[2] = (-qb + r) / (2.0 * qa);
+          cand[3] = (-qb - r) / (2.0 * qa);
+        }
+      } else if (qb != 0.0) {
+        cand[2] = -qc / qb;
+      }
+      for (double f : cand) {
+        if (f < 0.0 || f > 1.0) continue;
+        m = std::max(m, std::fabs(((c[3] * f + c[2]) * f + c[1]) * f + c[0]));
+      }
+    } else {
+      // higher degree: samples every 1/4096 plus the largest possible change
+      // between samples, sum_k k |c_k| / 8192
+      constexpr int kSamples = 4096;
+      for (int i = 0; i <= kSamples; ++i) {
+        const double f = static_cast<double>(i) / kSamples;
+        double v = 0.0;
+        for (int q = kPolyCoef - 1; q >= 0; --q) v = v * f + c[q];
+        m = std::max(m, std::fabs(v));
+      }
+      double slope = 0.0;
+      for (int q = 1; q < kPolyCoef; ++q) slope += q * std::fabs(c[q]);
+      m += slope * 0.5 / kSamples;
     }
     // margin for the FP32 evaluation of the taps on the device
     b.k[j] = static_cast<float>(m * 1.0001);
@@ -146,31 +162,73 @@ TapBound tap_bounds(const TapPoly& tp, int n_taps) {
   return b;
 }
 
-TapPoly pcs_tap_polynomials() {
-  // beta3(j - f) on f in [0, 1) for j = -1, 0, 1, 2: (1 - f)^3 / 6,
-  // 2/3 - f^2 + f^3 / 2, 1/6 + f/2 + f^2/2 - f^3/2, f^3 / 6
-  static const double c[4][4] = {{1.0 / 6.0, -0.5, 0.5, -1.0 / 6.0},
-                                 {2.0 / 3.0, 0.0, -1.0, 0.5},
-                                 {1.0 / 6.0, 0.5, 0.5, -0.5},
-                                 {0.0, 0.0, 0.0, 1.0 / 6.0}};
-  TapPoly tp;
-  for (int j = 0; j < kTaps; ++j)
-    for (int q = 0; q < 4; ++q) tp.c[j][q] = j < 4 ? c[j][q] : 0.0;
+namespace {
+
+// Centred B-spline of degree n by the Cox-de Boor recursion
+//   beta_n(x) = ((x + (n+1)/2) beta_{n-1}(x + 1/2) + ((n+1)/2 - x) beta_{n-1}(x - 1/2)) / n,
+// beta_0 = 1 on (-1/2, 1/2].
+long double bspline(int n, long double x) {
+  if (n == 0) return (x > -0.5L && x <= 0.5L) ? 1.0L : 0.0L;
+  const long double h = 0.5L * (n + 1);
+  return ((x + h) * bspline(n - 1, x + 0.5L) + (h - x) * bspline(n - 1, x - 0.5L)) / n;
+}
+
+}  // namespace
+
+TapPoly bspline_tap_polynomials(int order) {
+  // tap t = 0..p-1 is node c + j, j = t - (p-1)/2; with the particle at
+  // c + f - s (s = 1/2 for odd p) its weight is beta_{p-1}(j - f + s), one
+  // polynomial of degree p - 1 in f on (0, 1): fitted through p interior
+  // points in long double
+  TapPoly tp{};
+  const int d = order - 1;
+  const int lo = -((order - 1) / 2);
+  const long double s = (order & 1) ? 0.5L : 0.0L;
+  for (int t = 0; t < order; ++t) {
+    long double a[kPolyCoef][kPolyCoef + 1] = {};
+    for (int k = 0; k <= d; ++k) {
+      const long double f = (k + 0.5L) / (d + 1);
+      long double pw = 1.0L;
+      for (int q = 0; q <= d; ++q) {
+        a[k][q] = pw;
+        pw *= f;
+      }
+      a[k][d + 1] = bspline(d, (lo + t) - f + s);
+    }
+    // Gauss-Jordan elimination with partial pivoting
+    for (int col = 0; col <= d; ++col) {
+      int piv = col;
+      for (int r = col + 1; r <= d; ++r)
+        if (std::fabs(static_cast<double>(a[r][col])) > std::fabs(static_cast<double>(a[piv][col]))) piv = r;
+      for (int q = 0; q <= d + 1; ++q) std::swap(a[col][q], a[piv][q]);
+      for (int r = 0; r <= d; ++r) {
+        if (r == col) continue;
+        const long double g = a[r][col] / a[col][col];
+        for (int q = col; q <= d + 1; ++q) a[r][q] -= g * a[col][q];
+      }
+    }
+    for (int q = 0; q <= d; ++q) tp.c[t][q] = static_cast<double>(a[q][d + 1] / a[q][q]);
+  }
   return tp;
 }
 
-void pcs_axis_tables(int n_grid, std::vector<double>* inv_win2, std::vector<double>* alias) {
+void bspline_axis_tables(int n_grid, int order, std::vector<double>* inv_win2, std::vector<double>* alias) {
   const int half = n_grid / 2;
   inv_win2->assign(half + 1, 1.0);
   alias->assign(half + 1, 1.0);
+  // sum_J sinc^(2p)((w + 2 pi J)/2) = sum_m beta_{2p-1}(m) cos(m w) (Poisson)
+  std::vector<double> bm(order, 0.0);
+  for (int m = 0; m < order; ++m) bm[m] = static_cast<double>(bspline(2 * order - 1, m));
   for (int n = 0; n <= half; ++n) {
     const double w = 2.0 * M_PI * n / n_grid;
     const double h = 0.5 * w;
     const double sinc = n == 0 ? 1.0 : std::sin(h) / h;
-    const double s4 = sinc * sinc * sinc * sinc;
-    (*inv_win2)[n] = 1.0 / (s4 * s4);
-    // sum_J |beta3_hat(w + 2 pi J)|^2: the degree-7 B-spline at the integers
-    (*alias)[n] = (2416.0 + 2382.0 * std::cos(w) + 240.0 * std::cos(2.0 * w) + 2.0 * std::cos(3.0 * w)) / 5040.0;
+    double s2p = 1.0;
+    for (int k = 0; k < 2 * order; ++k) s2p *= sinc;
+    (*inv_win2)[n] = 1.0 / s2p;
+    double c = bm[0];
+    for (int m = 1; m < order; ++m) c += 2.0 * bm[m] * std::cos(m * w);
+    (*alias)[n] = c;
   }
 }
 
