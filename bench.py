@@ -117,6 +117,37 @@ def time_subcubes(mps, torch, pos, vel, prec, steps, warmup):
     return wall
 
 
+def resolution_study(mps, pos, vel, n_lo=N_GRID // 2):
+    """The aliasing check of Sec. 2.4.3 on the synthetic catalog: estimates on
+    N^3 and (2N)^3 grids in the same k bins (32 linear bins up to the k_N of
+    the N^3 grid), FP32.  Per kernel and spectrum: the lower edge (in units
+    of k_N) of the first bin where |P_N / P_2N - 1| exceeds 1 %, and the
+    largest deviation below 0.5 k_N and 0.7 k_N."""
+    kn = math.pi * n_lo / BOX
+    edges = kn * np.arange(33) / 32
+    out = {}
+    for kernel in ("bl3", "pqs", "ngp"):
+        res = []
+        for n in (n_lo, 2 * n_lo):
+            plan = mps.Plan(n, "f32")
+            res.append(plan.estimate(pos, vel, box=BOX, haf=HAF, k_edges=edges, kernel=kernel))
+            plan.close()
+        lo, hi = res
+        out[kernel] = {}
+        for key in ("p_pp", "p_tt", "p_dt", "p_dd"):
+            with np.errstate(invalid="ignore", divide="ignore"):
+                dev = np.abs(lo[key] / hi[key] - 1.0)
+            kc = lo["k_mean"] / kn
+            ok = np.isfinite(dev)
+            bad = np.nonzero(ok & (dev > 0.01))[0]
+            out[kernel][key] = {
+                "k_over_kN_1pct": float(edges[bad[0]] / kn) if bad.size else None,
+                "max_dev_below_0.5kN": float(np.max(dev[ok & (kc < 0.5)])),
+                "max_dev_below_0.7kN": float(np.max(dev[ok & (kc < 0.7)]))}
+        _log(f"resolution study {kernel}: {out[kernel]}")
+    return {"grids": [n_lo, 2 * n_lo], "precision": "f32", "k_N": kn, "by_kernel": out}
+
+
 def cpu_baseline():
     """Oracle on 1/64 of the workload: a 128^3-particle Zel'dovich catalog of the
     same construction on a 128^3 grid (64x fewer particles and cells)."""
@@ -225,7 +256,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip timing the untruncated-kernel, (k, mu_b) and sub-sample variants")
+                    help="skip the kernel, (k, mu_b) and sub-sample variants and the N vs 2N study")
     ap.add_argument("--shuffle", action="store_true",
                     help="permute particle order randomly (no spatial coherence)")
     ap.add_argument("--serving", action="store_true",
@@ -289,7 +320,8 @@ def main():
     if not args.no_variants:
         variants = {}
         steps_v = max(3, args.steps // 4)
-        for name, kw in (("bl3_exact_f32", {"kernel": "bl3_exact"}), ("mu16_f32", {"n_mu": 16})):
+        for name, kw in (("bl3_exact_f32", {"kernel": "bl3_exact"}), ("pqs_f32", {"kernel": "pqs"}),
+                         ("ngp_f32", {"kernel": "ngp"}), ("mu16_f32", {"n_mu": 16})):
             _log(f"timing variant {name}")
             wall_v, _, stages_v, _ = time_path(mps, torch, pos, vel, "f32", steps_v, 1, **kw)
             variants[name] = {"catalogs_per_s": steps_v / wall_v, "ms_per_step": 1e3 * wall_v / steps_v,
@@ -299,6 +331,11 @@ def main():
         variants["subcubes_4x4x4_128_f32"] = {"catalogs_per_s": steps_v / wall_v,
                                               "ms_per_step": 1e3 * wall_v / steps_v,
                                               "sub_catalogs_per_s": 64 * steps_v / wall_v}
+
+    aliasing = None
+    if not args.no_variants:
+        _log("resolution study (N vs 2N)")
+        aliasing = resolution_study(mps, pos, vel)
 
     abytes = algorithmic_bytes(N_GRID, n_part, 4)
     per_stage = {}
@@ -355,6 +392,7 @@ def main():
         "fp64": fp64,
         "precision_f32_vs_f64": precision,
         "variants": variants,
+        "resolution_study": aliasing,
         "stages": per_stage,
         "roofline": roofline,
         "cpu_baseline": cpu,

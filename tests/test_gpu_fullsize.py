@@ -157,6 +157,19 @@ def test_fullsize_fp32_matches_fp64(mps, zel512_dev):
     assert max(errs.values()) <= 3e-4, errs
 
 
+@pytest.mark.parametrize("kernel", ["pqs", "ngp"])
+def test_fullsize_bspline_fp32_matches_fp64(mps, zel512_dev, kernel):
+    """The comparison kernels at 512^3: FP32 grids against FP64 grids."""
+    outs = {p: mps.Plan(N, p).estimate(*zel512_dev, box=BOX, haf=HAF, kernel=kernel) for p in ("f32", "f64")}
+    a, b = outs["f32"], outs["f64"]
+    errs = {}
+    for key, sn in (("p_pp", b["sn_pp"]), ("p_tt", b["sn_tt"]), ("p_dd", b["sn_dd"]),
+                    ("p_dt", np.sqrt(b["sn_dd"] * b["sn_tt"]))):
+        errs[key] = float(guarded_rel(a[key], b[key], sn).max())
+    print(kernel, "512^3 FP32 vs FP64 max guarded per-bin error:", errs, flush=True)
+    assert max(errs.values()) <= 3e-4, errs
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_fullsize_translation_by_whole_cells(mps, zel512, prec):
     """Moving every particle by whole cells leaves every spectrum unchanged.
