@@ -236,6 +236,49 @@ int mps_estimate_subcubes(mps_plan* plan, const mps_catalog* cat, int n_div,
                           mps_result* outs, int* status, mps_result* mean,
                           mps_result* sdev, hipStream_t stream);
 
+/* One-loop standard perturbation theory predictions (the one-loop section
+ * and its appendices: Eqs. Ppd, PpdD4, pdivpD4, the P13 and P22 formulas,
+ * Eq. intBktree, Eq. Pcov), FP64 on the device.
+ *
+ * Inputs (host): k[n_k] > 0, the wavenumbers to predict at; a table of the
+ * z = 0 linear spectrum P0, table_k[n_table] strictly ascending > 0 and
+ * table_p[n_table] > 0, interpolated linearly in (ln k, ln P) and zero
+ * outside [table_k[0], table_k[n_table - 1]]; d_z = D(z)/D(0); haf = H a f.
+ * n_k in [1, MPS_SPT_MAX_K], n_table in [2, MPS_SPT_MAX_TABLE].
+ *
+ * Outputs (host arrays of n_k, each may be NULL), with K_xy the P13 kernels
+ * (their logarithm read with the factor 3/r^3), y = 1 + r^2 - 2 r x:
+ *   p13, p13_dt, p13_tt: c P0(k) k^3/(4 pi^2) int dr P0(kr) K_xy(r),
+ *     c = 1/504, 1/504, 1/168;
+ *   p22, p22_dt, p22_tt: k^3/(98 4 pi^2) int dr P0(kr) int dx P0(k sqrt(y))
+ *     N_x N_y / y^2, N_delta = 3r + 7x - 10 r x^2, N_theta = 7x - r - 6 r x^2;
+ *   i1, i2, i3: the three terms of the tree-level bispectrum integral
+ *     B_dtt,0 = i1 + i2 + i3 (Eq. intBktree);
+ *   pcov1, pcov2: P_cov^I and P_cov^II (Eq. Pcov);
+ *   p_lin = D^2 P0; p_dd = D^2 P0 + D^4 (2 p13 + p22);
+ *   p_theta_p = D^2 P0 + D^4 (6 p13 + 4 p22) and
+ *   p_dtheta_p = D^2 P0 + D^4 (4 p13 + 2 p22) (Eq. pdivpD4);
+ *   p_mom = (Haf/k)^2 [D^2 P0 + D^4 (2 p13_tt + p22_tt + pcov1 + pcov2
+ *     + 2 k^2 (i1 + i2 + i3))] (Eq. PpdD4).
+ * The integrals use fixed Gauss-Legendre panels between the points where
+ * the integrands are not smooth.  MPS_E_ARG for bad sizes, non-positive or
+ * non-finite k, table values or haf, or a table that is not ascending;
+ * MPS_E_NOMEM, MPS_E_HIP.  Work is enqueued on `stream`; the call returns
+ * after the results are copied. */
+#define MPS_SPT_MAX_K 65536
+#define MPS_SPT_MAX_TABLE 2048
+#define MPS_SPT_NUM_OUT 16
+typedef struct {
+  double *p13, *p22, *p13_dt, *p22_dt, *p13_tt, *p22_tt;
+  double *i1, *i2, *i3;
+  double *pcov1, *pcov2;
+  double *p_lin, *p_dd, *p_theta_p, *p_dtheta_p, *p_mom;
+} mps_spt_result;
+
+int mps_spt_one_loop(const double* k, int n_k, const double* table_k,
+                     const double* table_p, int n_table, double d_z,
+                     double haf, mps_spt_result* out, hipStream_t stream);
+
 /* Diagnostics of the hot path's first stages, using the same kernels as
  * mps_estimate.  mps_assign writes the four assigned real grids
  * (rho, rho v_x, rho v_y, rho v_z; layout [field][x][y][z], z fastest, the

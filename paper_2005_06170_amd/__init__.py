@@ -6,5 +6,5 @@ optional bulk-flow removal, and |k|-shell binning of P_pp, P_theta-theta and
 P_delta-theta, all in HIP kernels for gfx950.  torch supplies device memory and
 streams only.
 """
-from .api import Plan, Server, estimate, estimate_batch  # noqa: F401
+from .api import Plan, Server, estimate, estimate_batch, spt_one_loop  # noqa: F401
 from ._lib import MpsError  # noqa: F401

@@ -55,6 +55,16 @@ class ResultMu(C.Structure):
                    ("v_bulk", C.c_double * 3), ("sigma_v2", C.c_double), ("n_eff", C.c_double)])
 
 
+SPT_KEYS = ("p13", "p22", "p13_dt", "p22_dt", "p13_tt", "p22_tt", "i1", "i2", "i3", "pcov1", "pcov2",
+            "p_lin", "p_dd", "p_theta_p", "p_dtheta_p", "p_mom")
+SPT_MAX_K = 65536
+SPT_MAX_TABLE = 2048
+
+
+class SptResult(C.Structure):
+    _fields_ = [(k, C.POINTER(C.c_double)) for k in SPT_KEYS]
+
+
 class MpsError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
@@ -85,6 +95,8 @@ def lib():
         "mps_estimate_mu": (i32, [vp, C.POINTER(Catalog), i32, C.POINTER(dbl), C.POINTER(ResultMu), vp]),
         "mps_estimate_subcubes": (i32, [vp, C.POINTER(Catalog), i32, C.POINTER(Result), C.POINTER(i32),
                                         C.POINTER(Result), C.POINTER(Result), vp]),
+        "mps_spt_one_loop": (i32, [C.POINTER(dbl), i32, C.POINTER(dbl), C.POINTER(dbl), i32, dbl, dbl,
+                                   C.POINTER(SptResult), vp]),
         "mps_assign": (i32, [vp, C.POINTER(Catalog), vp, vp]),
         "mps_fft": (i32, [vp, vp, vp]),
         "mps_plan_set_timing": (i32, [vp, i32]),
@@ -126,7 +138,7 @@ def exported_symbols():
     L = lib()
     names = ["mps_plan_create", "mps_plan_destroy", "mps_plan_reserve", "mps_footprint",
              "mps_estimate", "mps_estimate_batch", "mps_estimate_mu", "mps_estimate_subcubes",
-             "mps_assign", "mps_fft",
+             "mps_spt_one_loop", "mps_assign", "mps_fft",
              "mps_plan_set_timing", "mps_plan_stage_times", "mps_server_create",
              "mps_submit", "mps_wait", "mps_server_destroy", "mps_strerror"]
     return {n: hasattr(L, n) for n in names}

@@ -250,6 +250,26 @@ class Plan:
         return dict(zip(L.STAGES, list(ms)))
 
 
+def spt_one_loop(k, table_k, table_p, *, d_z=1.0, haf=50.0, stream=None):
+    """One-loop SPT predictions at wavenumbers k from a tabulated z = 0 linear
+    spectrum (log-log interpolated, zero outside the table); dict of arrays
+    (keys as mps_spt_result: p13, p22, ..., p_mom)."""
+    kk = np.ascontiguousarray(k, dtype=np.float64).ravel()
+    tk = np.ascontiguousarray(table_k, dtype=np.float64).ravel()
+    tp = np.ascontiguousarray(table_p, dtype=np.float64).ravel()
+    if tk.shape != tp.shape:
+        raise ValueError("table_k and table_p differ in length")
+    out = {key: np.full(kk.shape[0], np.nan) for key in L.SPT_KEYS}
+    res = L.SptResult()
+    for key in L.SPT_KEYS:
+        setattr(res, key, out[key].ctypes.data_as(C.POINTER(C.c_double)))
+    dp = C.POINTER(C.c_double)
+    L.check(L.lib().mps_spt_one_loop(kk.ctypes.data_as(dp), kk.shape[0], tk.ctypes.data_as(dp),
+                                     tp.ctypes.data_as(dp), tk.shape[0], float(d_z), float(haf),
+                                     C.byref(res), _stream(stream)), "mps_spt_one_loop")
+    return out
+
+
 def footprint(n_grid: int, precision, n_particles: int) -> int:
     return int(L.lib().mps_footprint(int(n_grid), _prec(precision), int(n_particles)))
 
