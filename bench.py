@@ -117,6 +117,21 @@ def time_subcubes(mps, torch, pos, vel, prec, steps, warmup):
     return wall
 
 
+def time_spt(mps, n_k=1024, n_table=256, reps=5):
+    """One-loop SPT predictions at n_k wavenumbers in [0.005, 1] h/Mpc from an
+    n_table-node table of the catalogs' power law (wall clock per call,
+    including the host breakpoints and the copies)."""
+    tk = np.geomspace(1e-3, 4.0, n_table)
+    tp = 2e3 * tk ** -1.5 * np.exp(-tk / 0.5)
+    ks = np.geomspace(0.005, 1.0, n_k)
+    mps.spt_one_loop(ks, tk, tp)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mps.spt_one_loop(ks, tk, tp)
+    dt = (time.perf_counter() - t0) / reps
+    return {"n_k": n_k, "n_table": n_table, "ms_per_call": 1e3 * dt, "predictions_per_s": n_k / dt}
+
+
 def resolution_study(mps, pos, vel, n_lo=N_GRID // 2):
     """The aliasing check of Sec. 2.4.3 on the synthetic catalog: estimates on
     N^3 and (2N)^3 grids in the same k bins (32 linear bins up to the k_N of
@@ -331,6 +346,8 @@ def main():
         variants["subcubes_4x4x4_128_f32"] = {"catalogs_per_s": steps_v / wall_v,
                                               "ms_per_step": 1e3 * wall_v / steps_v,
                                               "sub_catalogs_per_s": 64 * steps_v / wall_v}
+        _log("timing the one-loop SPT predictions")
+        variants["spt_one_loop_f64"] = time_spt(mps)
 
     aliasing = None
     if not args.no_variants:
