@@ -214,7 +214,16 @@ def serving(args):
     gaps = rng.exponential(1.0 / args.rate, n_req)
     picks = [(int(rng.integers(len(pool))), grids[int(rng.integers(len(grids)))]) for _ in range(n_req)]
     out = {}
-    for prec in (["f32", "f64"] if not args.no_fp64 else ["f32"]):
+    runs = [("f32", "f32")] + ([] if args.no_fp64 else [("f64", "f64")])
+    if args.host_catalogs:
+        runs.append(("f32_host", "f32"))
+    for label, prec in runs:
+        if label == "f32_host":
+            # the same pool from page-locked host memory: each request's
+            # catalog crosses PCIe on its worker's stream (MPS_CATALOG_HOST)
+            _log("moving the pool to pinned host memory")
+            pool = [(p.cpu().pin_memory(), v.cpu().pin_memory()) for p, v in pool]
+            torch.cuda.empty_cache()
         srv = mps.Server(hbm_budget_bytes=int(args.budget_gb * 2 ** 30), max_inflight=args.inflight,
                          small_particles=4_000_000)
         # warm the plan pool with one request per grid size
@@ -233,7 +242,7 @@ def serving(args):
                 done_t[j] = time.perf_counter()
                 lat[j] = done_t[j] - t_sub[j]
                 if j % 100 == 0:
-                    _log(f"{prec}: {j}/{n_req} done")
+                    _log(f"{label}: {j}/{n_req} done")
 
         th = threading.Thread(target=collect)
         th.start()
@@ -251,15 +260,19 @@ def serving(args):
         elapsed = max(done_t) - t0
         srv.close()
         lat_ms = np.array(lat) * 1e3
-        out[prec] = {"catalogs_per_s": n_req / elapsed, "p50_ms": float(np.percentile(lat_ms, 50)),
-                     "p99_ms": float(np.percentile(lat_ms, 99)), "requests": n_req,
-                     "offered_rate": args.rate, "elapsed_s": elapsed}
-        _log(f"{prec}: {out[prec]}")
+        out[label] = {"catalogs_per_s": n_req / elapsed, "p50_ms": float(np.percentile(lat_ms, 50)),
+                      "p99_ms": float(np.percentile(lat_ms, 99)), "requests": n_req,
+                      "offered_rate": args.rate, "elapsed_s": elapsed}
+        if label == "f32_host":
+            gb = sum(24.0 * pool[ci][0].shape[0] for ci, _ in picks) / 1e9
+            out[label]["h2d_GB"] = gb
+            out[label]["h2d_GB_per_s"] = gb / elapsed
+        _log(f"{label}: {out[label]}")
     line = {"metric": "serving: catalogs/s and p50/p99 latency, Poisson arrivals", "value": out["f32"]["catalogs_per_s"],
             "unit": "catalogs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "poisson_stream_grids_128-1024_particles_1e6-5e8", "rate": args.rate,
                        "duration_s": args.duration, "inflight": args.inflight, "budget_gb": args.budget_gb},
-            "f32": out["f32"], "fp64": out.get("f64")}
+            "f32": out["f32"], "fp64": out.get("f64"), "f32_host_catalogs": out.get("f32_host")}
     print(json.dumps(line))
 
 
@@ -280,6 +293,8 @@ def main():
     ap.add_argument("--duration", type=float, default=30.0)
     ap.add_argument("--inflight", type=int, default=3)
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--host-catalogs", action="store_true",
+                    help="serving: also run the stream with the pool in pinned host memory")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, copy 1 GiB device-to-device once (calibrates HBM counters)")
     args = ap.parse_args()

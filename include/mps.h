@@ -93,6 +93,14 @@ enum {
 #define MPS_KERNEL_ORDER_SHIFT 4
 #define MPS_KERNEL_BSPLINE(p) ((uint32_t)(p) << MPS_KERNEL_ORDER_SHIFT)
 
+/* The catalog's pos, vel and weight are host pointers: the plan copies them
+ * to device workspace (28 bytes per particle, kept for reuse) on the call's
+ * stream before the first kernel.  Page-locked (pinned) host memory lets the
+ * copy run asynchronously and overlap other streams' work; pageable memory
+ * works but copies synchronously.  Accepted by every estimate entry point
+ * and by mps_submit. */
+#define MPS_CATALOG_HOST (1u << 7)
+
 /* One catalog.  The caller owns every buffer; they must stay valid until the
  * call that uses them returns (or, for mps_submit, until mps_wait reports the
  * ticket done).  The library never frees or retains them. */

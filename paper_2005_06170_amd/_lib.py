@@ -14,6 +14,7 @@ ERRORS = {-1: "MPS_E_ARG", -2: "MPS_E_NONFINITE", -3: "MPS_E_ZEROWEIGHT",
 MPS_F32, MPS_F64 = 1, 2
 BULKFLOW_SUBTRACT, NO_SHOTNOISE, NO_DECONVOLVE, KERNEL_BL3_EXACT = 1, 2, 4, 8
 KERNEL_ORDER_SHIFT = 4
+CATALOG_HOST = 1 << 7
 KERNELS = {"bl3": 0, "bl3_exact": KERNEL_BL3_EXACT}
 # centred B-splines of order p (MPS_KERNEL_BSPLINE(p))
 for _name, _p in (("ngp", 1), ("cic", 2), ("tsc", 3), ("pcs", 4), ("pqs", 5), ("bspline6", 6)):

@@ -28,9 +28,10 @@ def _stream(stream) -> C.c_void_p:
     return C.c_void_p(stream.cuda_stream)
 
 
-def _device_f32(t, name, cols):
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+def _device_f32(t, name, cols, host_ok=False):
+    if not isinstance(t, torch.Tensor) or not (t.is_cuda or (host_ok and t.device.type == "cpu")):
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor"
+                        + (" or a CPU tensor (pinned memory recommended)" if host_ok else ""))
     if t.dtype != torch.float32:
         raise TypeError(f"{name} must be float32")
     if not t.is_contiguous():
@@ -48,9 +49,17 @@ def _flags(bulk_flow, no_shotnoise, no_deconvolve, kernel="bl3") -> int:
 
 
 def make_catalog(pos, vel, weight=None, *, box, haf=1.0, n_bins=32, k_edges=None, flags=0):
-    """Build an mps_catalog; returns (struct, objects that must stay alive)."""
-    _device_f32(pos, "pos", 3)
-    _device_f32(vel, "vel", 3)
+    """Build an mps_catalog; returns (struct, objects that must stay alive).
+    CPU tensors (all three on the host) are passed as a host-resident catalog
+    (MPS_CATALOG_HOST): the library copies them to the device."""
+    host = isinstance(pos, torch.Tensor) and pos.device.type == "cpu"
+    _device_f32(pos, "pos", 3, host_ok=True)
+    _device_f32(vel, "vel", 3, host_ok=True)
+    for t, name in ((vel, "vel"), (weight, "weight")):
+        if t is not None and (t.device.type == "cpu") != host:
+            raise ValueError(f"pos and {name} must both be on the host or both on the device")
+    if host:
+        flags |= L.CATALOG_HOST
     if vel.shape[0] != pos.shape[0]:
         raise ValueError("pos and vel differ in length")
     keep = [pos, vel]
@@ -60,7 +69,7 @@ def make_catalog(pos, vel, weight=None, *, box, haf=1.0, n_bins=32, k_edges=None
     cat.vel = vel.data_ptr()
     cat.weight = None
     if weight is not None:
-        _device_f32(weight, "weight", 0)
+        _device_f32(weight, "weight", 0, host_ok=True)
         if weight.dim() != 1 or weight.shape[0] != pos.shape[0]:
             raise ValueError("weight must have shape (n,)")
         cat.weight = weight.data_ptr()
@@ -222,7 +231,8 @@ class Plan:
         """The four assigned real grids, torch tensor (4, N, N, N) [field, x, y, z]
         (for kernel="bl3_exact", the cubic B-spline grids)."""
         n = self.n_grid
-        out = torch.empty((4, n, n, n), dtype=self.real_dtype, device=pos.device)
+        dev = torch.device("cuda") if pos.device.type == "cpu" else pos.device
+        out = torch.empty((4, n, n, n), dtype=self.real_dtype, device=dev)
         cat, keep = make_catalog(pos, vel, weight, box=box, haf=1.0, n_bins=1,
                                  flags=_flags(bulk_flow, False, False, kernel))
         L.check(L.lib().mps_assign(self._h, C.byref(cat), C.c_void_p(out.data_ptr()),

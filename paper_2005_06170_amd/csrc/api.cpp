@@ -65,6 +65,7 @@ void release(Plan* p) {
   dfree(p->d_bins);
   dfree(p->d_mu_partials);
   dfree(p->d_mu_bins);
+  dfree(p->host_stage);
   dfree(p->split_pos);
   dfree(p->split_vel);
   dfree(p->split_w);
@@ -88,7 +89,7 @@ int validate_catalog(const Plan* p, const mps_catalog* c) {
   if (!(c->box > 0.0) || !std::isfinite(c->box)) return MPS_E_ARG;
   if (!(c->haf > 0.0) || !std::isfinite(c->haf)) return MPS_E_ARG;
   if (c->n_bins < 1 || c->n_bins > kMaxBins) return MPS_E_ARG;
-  if (c->flags & ~(15u | (7u << MPS_KERNEL_ORDER_SHIFT))) return MPS_E_ARG;
+  if (c->flags & ~(15u | (7u << MPS_KERNEL_ORDER_SHIFT) | MPS_CATALOG_HOST)) return MPS_E_ARG;
   const uint32_t order = (c->flags >> MPS_KERNEL_ORDER_SHIFT) & 7u;
   if (order > 6 || (order != 0 && (c->flags & MPS_KERNEL_BL3_EXACT))) return MPS_E_ARG;
   (void)p;
@@ -121,6 +122,16 @@ int ensure_particles(Plan* p, int64_t np) {
   return MPS_OK;
 }
 
+int ensure_host_stage(Plan* p, int64_t np) {
+  if (np <= p->host_cap) return MPS_OK;
+  dfree(p->host_stage);
+  p->host_stage = nullptr;
+  p->host_cap = 0;
+  if (dalloc(&p->host_stage, kHostStageBytes * static_cast<size_t>(np)) != hipSuccess) return MPS_E_NOMEM;
+  p->host_cap = np;
+  return MPS_OK;
+}
+
 #define MPS_TRY(expr)                               \
   do {                                              \
     if ((expr) != hipSuccess) return MPS_E_HIP;     \
@@ -131,7 +142,25 @@ void mark(Plan* p, int i, hipStream_t s) {
 }
 
 // Stages up to (and including) the scatter; `bulk_grid` deposits v - v_b.
-int enqueue_particles(Plan* p, const mps_catalog* c, hipStream_t s, int bulk_grid) {
+// A host-resident catalog is first copied to the plan's staging buffer.
+int enqueue_particles(Plan* p, const mps_catalog* c0, hipStream_t s, int bulk_grid) {
+  mps_catalog staged;
+  const mps_catalog* c = c0;
+  if (c0->flags & MPS_CATALOG_HOST) {
+    const int st = ensure_host_stage(p, c0->n_particles);
+    if (st != MPS_OK) return st;
+    const size_t n = static_cast<size_t>(c0->n_particles);
+    staged = *c0;
+    staged.flags &= ~MPS_CATALOG_HOST;
+    staged.pos = p->host_stage;
+    staged.vel = p->host_stage + 3 * n;
+    staged.weight = c0->weight ? p->host_stage + 6 * n : nullptr;
+    MPS_TRY(hipMemcpyAsync(p->host_stage, c0->pos, sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
+    MPS_TRY(hipMemcpyAsync(p->host_stage + 3 * n, c0->vel, sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
+    if (c0->weight)
+      MPS_TRY(hipMemcpyAsync(p->host_stage + 6 * n, c0->weight, sizeof(float) * n, hipMemcpyHostToDevice, s));
+    c = &staged;
+  }
   mark(p, 0, s);
   MPS_TRY(launch_count(p, c, s));
   MPS_TRY(launch_derive(p, c, s));
@@ -326,7 +355,8 @@ size_t mps_footprint(int n_grid, mps_precision prec, int64_t n_particles) {
   b += sizeof(uint32_t) * (3 * tiles + 1);                           // tile tables
   b += sizeof(int32_t) * half * half;                                // bin LUT
   b += sizeof(double) * (static_cast<size_t>(256) + 1) * kMaxBins * kNumQ;
-  b += sizeof(double) * (kMomentBlocks * (kMomentSums + kMomentMax) + 2 * (half + 1)) + 2 * rs * n_grid + sizeof(ResultHeader);
+  b += sizeof(double) * (kMomentBlocks * (kMomentSums + kMomentMax) + 2 * kNumKernels * (half + 1)) +
+       2 * rs * n_grid + sizeof(ResultHeader);
   return b;
 }
 
@@ -557,10 +587,25 @@ int mps_estimate_subcubes(mps_plan* plan, const mps_catalog* cat, int n_div, mps
   const int n_cubes = n_div * n_div * n_div;
   mps_catalog sub = *cat;
   sub.box = cat->box / n_div;
+  sub.flags &= ~MPS_CATALOG_HOST;  // the sub-catalogs live in plan workspace
   if (!(sub.box > 0.0)) return MPS_E_ARG;
   if (hipSetDevice(p->device) != hipSuccess) return MPS_E_HIP;
   if ((st = ensure_bins(p, &sub)) != MPS_OK) return st;
   if ((st = ensure_split(p, cat->n_particles)) != MPS_OK) return st;
+  mps_catalog staged = *cat;
+  if (cat->flags & MPS_CATALOG_HOST) {  // the split reads a device copy
+    if ((st = ensure_host_stage(p, cat->n_particles)) != MPS_OK) return st;
+    const size_t n = static_cast<size_t>(cat->n_particles);
+    staged.flags &= ~MPS_CATALOG_HOST;
+    staged.pos = p->host_stage;
+    staged.vel = p->host_stage + 3 * n;
+    staged.weight = cat->weight ? p->host_stage + 6 * n : nullptr;
+    MPS_TRY(hipMemcpyAsync(p->host_stage, cat->pos, sizeof(float) * 3 * n, hipMemcpyHostToDevice, stream));
+    MPS_TRY(hipMemcpyAsync(p->host_stage + 3 * n, cat->vel, sizeof(float) * 3 * n, hipMemcpyHostToDevice, stream));
+    if (cat->weight)
+      MPS_TRY(hipMemcpyAsync(p->host_stage + 6 * n, cat->weight, sizeof(float) * n, hipMemcpyHostToDevice, stream));
+    cat = &staged;
+  }
 
   SplitParams sp;
   sp.scale = static_cast<double>(n_div) / cat->box;

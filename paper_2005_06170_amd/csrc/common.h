@@ -140,6 +140,10 @@ struct Plan {
   double* d_mu_bins = nullptr;       // kMaxMuCells x kNumQMu
   void* h_stage_mu = nullptr;        // pinned: header + kMaxMuCells x kNumQMu
 
+  // device copy of a host-resident catalog (MPS_CATALOG_HOST)
+  float* host_stage = nullptr;       // host_cap x 7: pos, vel, weight
+  int64_t host_cap = 0;
+
   // sub-cube split (allocated on first use)
   float* split_pos = nullptr;        // split_cap x 3
   float* split_vel = nullptr;        // split_cap x 3
@@ -176,6 +180,12 @@ constexpr int kMomentBlocks = 1024;
 int validate_catalog(const Plan* p, const mps_catalog* c);
 int ensure_bins(Plan* p, const mps_catalog* c);
 int ensure_particles(Plan* p, int64_t np);
+int ensure_host_stage(Plan* p, int64_t np);
+constexpr size_t kHostStageBytes = 7 * sizeof(float);  // per particle
+// Bytes of the device copy a host-resident catalog of np particles needs.
+inline size_t host_stage_bytes(const mps_catalog* c) {
+  return (c->flags & MPS_CATALOG_HOST) ? kHostStageBytes * static_cast<size_t>(c->n_particles) : 0;
+}
 // Async, including the copy of the results to `stage` (the plan's own
 // staging buffer when NULL).
 int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s, void* stage = nullptr);

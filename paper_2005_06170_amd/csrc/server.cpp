@@ -48,6 +48,7 @@ struct PooledPlan {
   int n_grid = 0;
   mps_precision prec = MPS_F32;
   int64_t cap = 0;            // particles reserved
+  int64_t host_cap = 0;       // particles of host-catalog staging reserved
   size_t bytes = 0;
   bool busy = false;
   uint64_t last_use = 0;
@@ -91,14 +92,19 @@ bool make_room(Server* s, size_t need, const PooledPlan* keep) {
   return true;
 }
 
-// An idle pooled plan of this shape with room for np particles: reuse one
-// that is large enough, else grow the largest idle one of the shape, else
-// create one.  Called with mu held; returns nullptr if the budget cannot host
-// it right now (*status stays MPS_OK) or never can / creation failed.
-PooledPlan* acquire_plan(Server* s, int n_grid, mps_precision prec, int64_t np, int* status) {
+size_t plan_bytes(int n_grid, mps_precision prec, int64_t cap, int64_t host_cap) {
+  return mps_footprint(n_grid, prec, cap) + kHostStageBytes * static_cast<size_t>(host_cap);
+}
+
+// An idle pooled plan of this shape with room for np particles (and, for a
+// host-resident catalog, np particles of staging): reuse one that is large
+// enough, else grow the largest idle one of the shape, else create one.
+// Called with mu held; returns nullptr if the budget cannot host it right
+// now (*status stays MPS_OK) or never can / creation failed.
+PooledPlan* acquire_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host, int* status) {
   *status = MPS_OK;
-  const size_t need = mps_footprint(n_grid, prec, np);
-  if (need > s->budget) {
+  const int64_t hp = host ? np : 0;
+  if (plan_bytes(n_grid, prec, np, hp) > s->budget) {
     *status = MPS_E_TOOBIG;
     return nullptr;
   }
@@ -106,7 +112,7 @@ PooledPlan* acquire_plan(Server* s, int n_grid, mps_precision prec, int64_t np, 
   PooledPlan* grow = nullptr;
   for (auto& pp : s->pool) {
     if (pp.busy || pp.n_grid != n_grid || pp.prec != prec) continue;
-    if (pp.cap >= np) {
+    if (pp.cap >= np && pp.host_cap >= hp) {
       if (!fit || pp.cap < fit->cap) fit = &pp;
     } else if (!grow || pp.cap > grow->cap) {
       grow = &pp;
@@ -118,23 +124,29 @@ PooledPlan* acquire_plan(Server* s, int n_grid, mps_precision prec, int64_t np, 
     return fit;
   }
   if (grow) {
+    const int64_t cap = std::max(grow->cap, np), hcap = std::max(grow->host_cap, hp);
+    const size_t need = plan_bytes(n_grid, prec, cap, hcap);
     if (!make_room(s, need - grow->bytes, grow)) return nullptr;
-    const int st = mps_plan_reserve(grow->plan, np);
+    int st = mps_plan_reserve(grow->plan, cap);
+    if (st == MPS_OK && hcap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(grow->plan), hcap);
     if (st != MPS_OK) {
       *status = st;
       return nullptr;
     }
     s->used += need - grow->bytes;
     grow->bytes = need;
-    grow->cap = np;
+    grow->cap = cap;
+    grow->host_cap = hcap;
     grow->busy = true;
     grow->last_use = ++s->clock;
     return grow;
   }
+  const size_t need = plan_bytes(n_grid, prec, np, hp);
   if (!make_room(s, need, nullptr)) return nullptr;
   mps_plan* plan = nullptr;
   int st = mps_plan_create(&plan, n_grid, prec);
   if (st == MPS_OK) st = mps_plan_reserve(plan, np);
+  if (st == MPS_OK && hp > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(plan), hp);
   if (st != MPS_OK) {
     if (plan) mps_plan_destroy(plan);
     *status = st;
@@ -145,6 +157,7 @@ PooledPlan* acquire_plan(Server* s, int n_grid, mps_precision prec, int64_t np, 
   pp.n_grid = n_grid;
   pp.prec = prec;
   pp.cap = np;
+  pp.host_cap = hp;
   pp.bytes = need;
   pp.busy = true;
   pp.last_use = ++s->clock;
@@ -177,7 +190,8 @@ void worker_main(Server* s) {
       for (auto it = s->queue.begin(); it != s->queue.end();) {
         const auto r = *it;
         int st = MPS_OK;
-        PooledPlan* pp = acquire_plan(s, r->n_grid, r->prec, r->cat.n_particles, &st);
+        PooledPlan* pp = acquire_plan(s, r->n_grid, r->prec, r->cat.n_particles,
+                                      (r->cat.flags & MPS_CATALOG_HOST) != 0, &st);
         if (!pp && st != MPS_OK) {  // can never run (too big, or creation failed)
           it = s->queue.erase(it);
           finish(s, r, st);
@@ -199,7 +213,8 @@ void worker_main(Server* s) {
               continue;
             }
             int st2 = MPS_OK;
-            PooledPlan* p2 = acquire_plan(s, q->n_grid, q->prec, q->cat.n_particles, &st2);
+            PooledPlan* p2 = acquire_plan(s, q->n_grid, q->prec, q->cat.n_particles,
+                                          (q->cat.flags & MPS_CATALOG_HOST) != 0, &st2);
             if (!p2) break;
             batch.push_back(q);
             plans.push_back(p2);
@@ -291,7 +306,7 @@ int mps_submit(mps_server* srv, const mps_catalog* cat, int n_grid, mps_precisio
   r->n_grid = n_grid;
   r->prec = prec;
   r->out = out;
-  r->bytes = mps_footprint(n_grid, prec, cat->n_particles);
+  r->bytes = mps_footprint(n_grid, prec, cat->n_particles) + host_stage_bytes(cat);
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return MPS_E_ARG;
