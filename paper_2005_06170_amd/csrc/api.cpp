@@ -76,6 +76,11 @@ void release(Plan* p) {
   if (p->h_stage_sub) (void)hipHostFree(p->h_stage_sub);
   if (p->h_stage_mu) (void)hipHostFree(p->h_stage_mu);
   if (p->h_stage) (void)hipHostFree(p->h_stage);
+  for (int i = 0; i < Plan::kSubLanes; ++i) {
+    if (i > 0 && p->sub_plan[i - 1]) release(p->sub_plan[i - 1]);
+    if (p->sub_stream[i]) (void)hipStreamDestroy(p->sub_stream[i]);
+    if (p->sub_done[i]) (void)hipEventDestroy(p->sub_done[i]);
+  }
   for (auto& e : p->ev)
     if (e) (void)hipEventDestroy(e);
   delete p;
@@ -519,6 +524,28 @@ int ensure_split(Plan* p, int64_t np) {
   return MPS_OK;
 }
 
+// Helper plans and streams for running sub-sample estimates concurrently.
+int ensure_sub_lanes(Plan* p) {
+  // created in order and kept: resumes where an earlier failure stopped
+  for (int i = 0; i < Plan::kSubLanes; ++i) {
+    if (i > 0 && !p->sub_plan[i - 1]) {
+      mps_plan* h = nullptr;
+      const int st = mps_plan_create(&h, p->n, p->prec);
+      if (st != MPS_OK) return st;
+      p->sub_plan[i - 1] = reinterpret_cast<Plan*>(h);
+    }
+    if (!p->sub_stream[i] && hipStreamCreateWithFlags(&p->sub_stream[i], hipStreamNonBlocking) != hipSuccess) {
+      p->sub_stream[i] = nullptr;
+      return MPS_E_HIP;
+    }
+    if (!p->sub_done[i] && hipEventCreateWithFlags(&p->sub_done[i], hipEventDisableTiming) != hipSuccess) {
+      p->sub_done[i] = nullptr;
+      return MPS_E_HIP;
+    }
+  }
+  return MPS_OK;
+}
+
 // Mean and sample standard deviation (divisor m - 1) of one value over the
 // m staged sub-cube results; v(i) is the value of the i-th.
 template <typename F>
@@ -624,6 +651,16 @@ int mps_estimate_subcubes(mps_plan* plan, const mps_catalog* cat, int n_div, mps
   for (uint32_t c : count) largest = c > largest ? c : largest;
   if ((st = ensure_particles(p, largest)) != MPS_OK) return st;
 
+  // the split is complete (synchronised above); the cubes' estimates run
+  // round robin on kSubLanes plans, each with its own stream, so that the
+  // small grids' kernels overlap
+  if ((st = ensure_sub_lanes(p)) != MPS_OK) return st;
+  Plan* lane[Plan::kSubLanes];
+  for (int i = 0; i < Plan::kSubLanes; ++i) {
+    lane[i] = i == 0 ? p : p->sub_plan[i - 1];
+    if ((st = ensure_bins(lane[i], &sub)) != MPS_OK) return st;
+    if ((st = ensure_particles(lane[i], largest)) != MPS_OK) return st;
+  }
   std::vector<mps_catalog> cats(n_cubes, sub);
   int64_t off = 0;
   char* stage = static_cast<char*>(p->h_stage_sub);
@@ -635,14 +672,20 @@ int mps_estimate_subcubes(mps_plan* plan, const mps_catalog* cat, int n_div, mps
     off += count[s];
     status[s] = MPS_E_ZEROWEIGHT;
     if (count[s] == 0) continue;
-    if ((st = enqueue_estimate(p, &cats[s], stream, stage + p->stage_bytes * s)) != MPS_OK) return st;
+    const int l = s % Plan::kSubLanes;
+    if ((st = enqueue_estimate(lane[l], &cats[s], p->sub_stream[l], stage + p->stage_bytes * s)) != MPS_OK)
+      return st;
+  }
+  for (int i = 0; i < Plan::kSubLanes; ++i) {
+    MPS_TRY(hipEventRecord(p->sub_done[i], p->sub_stream[i]));
+    MPS_TRY(hipStreamWaitEvent(stream, p->sub_done[i], 0));
   }
   if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
   std::vector<const char*> ok_stages;
   for (int s = 0; s < n_cubes; ++s) {
     if (count[s] == 0) continue;
     const char* slot = stage + p->stage_bytes * s;
-    status[s] = unpack(p, &cats[s], &outs[s], slot);
+    status[s] = unpack(lane[s % Plan::kSubLanes], &cats[s], &outs[s], slot);
     if (status[s] == MPS_OK) ok_stages.push_back(slot);
   }
   if (mean || sdev) subcube_stats(ok_stages, sub.n_bins, mean, sdev);

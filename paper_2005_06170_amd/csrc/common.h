@@ -154,6 +154,12 @@ struct Plan {
   uint32_t* split_cursor = nullptr;  // kMaxCubes
   uint32_t* h_split = nullptr;       // pinned copy of split_count
   void* h_stage_sub = nullptr;       // pinned: kMaxCubes result slots of stage_bytes
+  // concurrent sub-sample estimates: helper plans of the same shape, each
+  // on its own stream (created on first use)
+  static constexpr int kSubLanes = 4;
+  Plan* sub_plan[kSubLanes - 1] = {};
+  hipStream_t sub_stream[kSubLanes] = {};
+  hipEvent_t sub_done[kSubLanes] = {};
 
   // host staging (pinned): header + bins
   void* h_stage = nullptr;
