@@ -238,8 +238,11 @@ int mps_estimate_mu(mps_plan* plan, const mps_catalog* cat, int n_mu,
  * count of one sub-cube (the same for all).  Returns MPS_E_NONFINITE if any
  * position is not finite, MPS_E_ARG, MPS_E_NOMEM or MPS_E_HIP for the whole
  * call, else MPS_OK.  The sub-catalogs live in plan workspace (28 bytes per
- * particle with weights, 24 without); the sub-cube estimates run one after
- * another on `stream` and the call returns after all results are copied. */
+ * particle with weights, 24 without).  The split runs on `stream` after its
+ * earlier work; the cubes' estimates then run round robin on this plan and
+ * three helper plans of the same shape (created on first use and owned by
+ * this plan), each on its own stream, and the call returns after all
+ * results are copied. */
 int mps_estimate_subcubes(mps_plan* plan, const mps_catalog* cat, int n_div,
                           mps_result* outs, int* status, mps_result* mean,
                           mps_result* sdev, hipStream_t stream);
