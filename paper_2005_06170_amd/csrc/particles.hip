@@ -113,8 +113,8 @@ __device__ __forceinline__ uint32_t tile_key(float x, float y, float z, const Ke
 }
 
 // Moments (FP64) and tile histogram in one pass over the catalog.  Each
-// thread takes kUnroll particles per step (one per wave-wide slab, so that a
-// wave still sees consecutive particles) and issues all their loads first.
+// thread takes kUnroll consecutive particles per step and issues all their
+// loads first.
 constexpr int kUnroll = 4;
 
 // Tile histograms: with at most kLdsTiles tiles each workgroup counts in
@@ -123,11 +123,49 @@ constexpr int kUnroll = 4;
 // global counters; larger grids count with wave-aggregated global atomics.
 constexpr int kLdsTiles = 16384;
 
+// Catalog records of particles i0 .. i0+kUnroll-1 (one lane's group): with
+// 16-byte aligned arrays and a whole group, three 16-byte loads per array
+// (12 floats = 4 particles' xyz) instead of twelve 4-byte ones.  Missing
+// particles read as (0, 0, 0), velocity 0, weight 1.
+template <bool kHasW>
+__device__ __forceinline__ void load_group(const float* __restrict__ pos, const float* __restrict__ vel,
+                                           const float* __restrict__ wgt, int64_t np, int64_t i0, bool vec,
+                                           float4 (&a)[kUnroll], float4 (&v)[kUnroll]) {
+  static_assert(kUnroll == 4, "one group is four particles");
+  if (vec && i0 + kUnroll <= np) {
+    const float4* p4 = reinterpret_cast<const float4*>(pos + 3 * i0);
+    const float4* v4 = reinterpret_cast<const float4*>(vel + 3 * i0);
+    const float4 p0 = p4[0], p1 = p4[1], p2 = p4[2];
+    const float4 q0 = v4[0], q1 = v4[1], q2 = v4[2];
+    float4 w = make_float4(1.f, 1.f, 1.f, 1.f);
+    if (kHasW) w = *reinterpret_cast<const float4*>(wgt + i0);
+    a[0] = make_float4(p0.x, p0.y, p0.z, w.x);
+    a[1] = make_float4(p0.w, p1.x, p1.y, w.y);
+    a[2] = make_float4(p1.z, p1.w, p2.x, w.z);
+    a[3] = make_float4(p2.y, p2.z, p2.w, w.w);
+    v[0] = make_float4(q0.x, q0.y, q0.z, 0.f);
+    v[1] = make_float4(q0.w, q1.x, q1.y, 0.f);
+    v[2] = make_float4(q1.z, q1.w, q2.x, 0.f);
+    v[3] = make_float4(q2.y, q2.z, q2.w, 0.f);
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int64_t i = i0 + u;
+    a[u] = make_float4(0.f, 0.f, 0.f, 1.f);
+    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < np) {
+      a[u] = make_float4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], kHasW ? wgt[i] : 1.f);
+      v[u] = make_float4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.f);
+    }
+  }
+}
+
 template <bool kHasW, bool kLds>
 __global__ __launch_bounds__(kCountThreads) void count_kernel(
     const float* __restrict__ pos, const float* __restrict__ vel, const float* __restrict__ wgt,
     int64_t np, KeyParams kp, int64_t n_tiles, uint32_t* __restrict__ tile_count,
-    double* __restrict__ partials, ResultHeader* hdr) {
+    double* __restrict__ partials, ResultHeader* hdr, bool vec) {
   extern __shared__ uint32_t hist[];  // n_tiles counters when kLds
   if (kLds) {
     for (int64_t i = threadIdx.x; i < n_tiles; i += kCountThreads) hist[i] = 0u;
@@ -139,35 +177,23 @@ __global__ __launch_bounds__(kCountThreads) void count_kernel(
   for (int q = 0; q < kMomentSums; ++q) acc[q] = 0.0;
   double mx[kMomentMax] = {0.0, 0.0, 0.0, 0.0};
   bool bad = false;
+  // each lane takes a group of kUnroll consecutive particles per step; for a
+  // given u the wave's lanes hold particles 4 apart, still in input order
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kCountThreads * kUnroll;
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * kCountThreads * kUnroll; base < np; base += stride) {
-    float x[kUnroll], y[kUnroll], z[kUnroll], vx[kUnroll], vy[kUnroll], vz[kUnroll], wf[kUnroll];
+    const int64_t i0 = base + static_cast<int64_t>(threadIdx.x) * kUnroll;
+    float4 a[kUnroll], v[kUnroll];
+    load_group<kHasW>(pos, vel, wgt, np, i0, vec, a, v);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int64_t i = base + u * kCountThreads + threadIdx.x;
-      x[u] = y[u] = z[u] = vx[u] = vy[u] = vz[u] = 0.f;
-      wf[u] = 1.f;
-      if (i < np) {
-        x[u] = pos[3 * i];
-        y[u] = pos[3 * i + 1];
-        z[u] = pos[3 * i + 2];
-        vx[u] = vel[3 * i];
-        vy[u] = vel[3 * i + 1];
-        vz[u] = vel[3 * i + 2];
-        if (kHasW) wf[u] = wgt[i];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int64_t i = base + u * kCountThreads + threadIdx.x;
-      const bool valid = i < np;
+      const bool valid = i0 + u < np;
       uint32_t key = 0xffffffffu;
       if (valid) {
         bool ok;
-        key = tile_key(x[u], y[u], z[u], kp, &ok);
+        key = tile_key(a[u].x, a[u].y, a[u].z, kp, &ok);
         bad |= !ok;
-        const double w = wf[u];
-        const double dvx = vx[u], dvy = vy[u], dvz = vz[u];
+        const double w = a[u].w;
+        const double dvx = v[u].x, dvy = v[u].y, dvz = v[u].z;
         const double w2 = w * w;
         acc[0] += w;
         acc[1] += w2;
@@ -323,7 +349,8 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
 template <bool kHasW, bool kLds>
 __global__ __launch_bounds__(kCountThreads) void permute_kernel(
     const float* __restrict__ pos, const float* __restrict__ vel, const float* __restrict__ wgt,
-    int64_t np, KeyParams kp, int64_t n_tiles, uint32_t* __restrict__ cursor, float4* __restrict__ sorted) {
+    int64_t np, KeyParams kp, int64_t n_tiles, uint32_t* __restrict__ cursor, float4* __restrict__ sorted,
+    bool vec) {
   extern __shared__ uint32_t hist[];  // n_tiles counters when kLds
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kCountThreads * kUnroll;
   const int64_t first = static_cast<int64_t>(blockIdx.x) * kCountThreads * kUnroll;
@@ -331,14 +358,16 @@ __global__ __launch_bounds__(kCountThreads) void permute_kernel(
     for (int64_t i = threadIdx.x; i < n_tiles; i += kCountThreads) hist[i] = 0u;
     __syncthreads();
     for (int64_t base = first; base < np; base += stride) {
+      const int64_t i0 = base + static_cast<int64_t>(threadIdx.x) * kUnroll;
+      float4 a[kUnroll], v[kUnroll];
+      load_group<false>(pos, vel, nullptr, np, i0, vec, a, v);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int64_t i = base + u * kCountThreads + threadIdx.x;
-        const bool valid = i < np;
+        const bool valid = i0 + u < np;
         uint32_t key = 0xffffffffu;
         if (valid) {
           bool ok;
-          key = tile_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], kp, &ok);
+          key = tile_key(a[u].x, a[u].y, a[u].z, kp, &ok);
         }
         wave_run_atomic(key, valid, hist);
       }
@@ -350,6 +379,9 @@ __global__ __launch_bounds__(kCountThreads) void permute_kernel(
     __syncthreads();
   }
   uint32_t* slots = kLds ? hist : cursor;
+  // one particle per lane per slab here (not the count's groups of four):
+  // consecutive lanes then write consecutive slots of a tile, so a wave's
+  // records go out in a few long runs
   for (int64_t base = first; base < np; base += stride) {
     float4 a[kUnroll], v[kUnroll];
 #pragma unroll
@@ -358,13 +390,8 @@ __global__ __launch_bounds__(kCountThreads) void permute_kernel(
       a[u] = make_float4(0.f, 0.f, 0.f, 1.f);
       v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (i < np) {
-        a[u].x = pos[3 * i];
-        a[u].y = pos[3 * i + 1];
-        a[u].z = pos[3 * i + 2];
-        if (kHasW) a[u].w = wgt[i];
-        v[u].x = vel[3 * i];
-        v[u].y = vel[3 * i + 1];
-        v[u].z = vel[3 * i + 2];
+        a[u] = make_float4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], kHasW ? wgt[i] : 1.f);
+        v[u] = make_float4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.f);
       }
     }
     // all slots are claimed before any record is written, so the returning
@@ -977,6 +1004,13 @@ KeyParams key_params(const Plan* p, const mps_catalog* c) {
   return kp;
 }
 
+// 16-byte aligned catalog arrays: the particle loads can be vectorised
+bool vec_aligned(const mps_catalog* c) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(c->pos) | reinterpret_cast<uintptr_t>(c->vel) |
+                      reinterpret_cast<uintptr_t>(c->weight);
+  return (a & 15u) == 0;
+}
+
 int count_blocks(int64_t np) {
   int64_t b = (np + kCountThreads * kUnroll - 1) / (kCountThreads * kUnroll);
   return static_cast<int>(b < kMomentBlocks ? (b < 1 ? 1 : b) : kMomentBlocks);
@@ -998,7 +1032,7 @@ hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
     const size_t dyn = decltype(use_lds)::value ? sizeof(uint32_t) * static_cast<size_t>(p->n_tiles) : 0;
     count_kernel<decltype(has_w)::value, decltype(use_lds)::value><<<nb, kCountThreads, dyn, s>>>(
         c->pos, c->vel, c->weight, c->n_particles, kp, p->n_tiles, p->tile_count, p->moment_partials,
-        p->d_header);
+        p->d_header, vec_aligned(c));
   };
   using T_ = std::true_type;
   using F_ = std::false_type;
@@ -1028,7 +1062,7 @@ hipError_t launch_permute(Plan* p, const mps_catalog* c, hipStream_t s) {
   auto go = [&](auto has_w, auto use_lds) {
     const size_t dyn = decltype(use_lds)::value ? sizeof(uint32_t) * static_cast<size_t>(p->n_tiles) : 0;
     permute_kernel<decltype(has_w)::value, decltype(use_lds)::value><<<nb, kCountThreads, dyn, s>>>(
-        c->pos, c->vel, c->weight, c->n_particles, kp, p->n_tiles, p->tile_cursor, p->sorted);
+        c->pos, c->vel, c->weight, c->n_particles, kp, p->n_tiles, p->tile_cursor, p->sorted, vec_aligned(c));
   };
   using T_ = std::true_type;
   using F_ = std::false_type;
