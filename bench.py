@@ -132,6 +132,51 @@ def time_spt(mps, n_k=1024, n_table=256, reps=5):
     return {"n_k": n_k, "n_table": n_table, "ms_per_call": 1e3 * dt, "predictions_per_s": n_k / dt}
 
 
+def batch_workload(mps, torch, seed_config=4, n_cat=64):
+    """The batched form: 64 catalogs of uneven sizes (particle counts
+    log-uniform in [1e5, 4e6], grids from {64, 128, 256}^3, boxes from
+    {250, 500, 1000} Mpc/h, half uniform with Gaussian velocities, half
+    Zel'dovich power-law lattices with rms displacement 3 Mpc/h x L/1000),
+    FP32 grids.  Times one mps_estimate_batch call over all 64 against 64
+    mps_estimate calls in sequence (plans created beforehand in both)."""
+    from synth import catalogs
+    rng = np.random.default_rng(catalogs.seed_for(seed_config))
+    cats = []
+    for i in range(n_cat):
+        n = int(round(np.exp(rng.uniform(np.log(1e5), np.log(4e6)))))
+        grid = int(rng.choice([64, 128, 256]))
+        box = float(rng.choice([250.0, 500.0, 1000.0]))
+        if i % 2 == 0:
+            pos, vel = catalogs.uniform_gaussian(n, box, 300.0, seed=catalogs.seed_for(seed_config, 100 + i))
+        else:
+            nl = max(2, int(round(n ** (1.0 / 3.0))))
+            pos, vel = catalogs.zeldovich(nl, box, 3.0 * box / 1000.0, haf=HAF,
+                                          seed=catalogs.seed_for(seed_config, 100 + i))
+        cats.append(dict(pos=torch.from_numpy(pos).cuda(), vel=torch.from_numpy(vel).cuda(),
+                         box=box, haf=HAF, grid=grid))
+    plans = [mps.Plan(c["grid"], "f32") for c in cats]
+    for p, c in zip(plans, cats):
+        p.reserve(c["pos"].shape[0])
+    args = [dict(pos=c["pos"], vel=c["vel"], box=c["box"], haf=c["haf"]) for c in cats]
+    mps.estimate_batch(plans, args)  # warm-up (tables, bins)
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mps.estimate_batch(plans, args)
+    t_batch = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for p, a in zip(plans, args):
+            p.estimate(a["pos"], a["vel"], box=a["box"], haf=a["haf"])
+    t_seq = (time.perf_counter() - t0) / reps
+    for p in plans:
+        p.close()
+    n_part = sum(int(c["pos"].shape[0]) for c in cats)
+    return {"catalogs": n_cat, "particles": n_part, "batch_ms": 1e3 * t_batch, "sequential_ms": 1e3 * t_seq,
+            "batch_catalogs_per_s": n_cat / t_batch, "sequential_catalogs_per_s": n_cat / t_seq}
+
+
 def resolution_study(mps, pos, vel, n_lo=N_GRID // 2):
     """The aliasing check of Sec. 2.4.3 on the synthetic catalog: estimates on
     N^3 and (2N)^3 grids in the same k bins (32 linear bins up to the k_N of
@@ -365,6 +410,9 @@ def main():
                                               "sub_catalogs_per_s": 64 * steps_v / wall_v}
         _log("timing the one-loop SPT predictions")
         variants["spt_one_loop_f64"] = time_spt(mps)
+        _log("timing the batched form (64 uneven catalogs)")
+        variants["batch64_f32"] = batch_workload(mps, torch)
+        _log(f"batch64: {variants['batch64_f32']}")
 
     aliasing = None
     if not args.no_variants:

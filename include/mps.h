@@ -194,8 +194,11 @@ int mps_estimate(mps_plan* plan, const mps_catalog* cat, mps_result* out,
                  hipStream_t stream);
 
 /* Estimate n catalogs, each with its own plan (plans may differ in N and
- * precision; a plan may not appear twice).  Stages of all catalogs are
- * launched together so that small catalogs share the device. */
+ * precision; a plan may not appear twice).  The catalogs' stages are
+ * enqueued round robin on four internal streams that start after the
+ * earlier work on `stream`, so that small catalogs' kernels overlap on the
+ * device; `stream` waits for all of them and the call returns after every
+ * result is copied. */
 int mps_estimate_batch(mps_plan* const* plans, const mps_catalog* cats,
                        mps_result* outs, int n, hipStream_t stream);
 

@@ -466,11 +466,34 @@ int mps_estimate_batch(mps_plan* const* plans, const mps_catalog* cats, mps_resu
     if ((st = ensure_bins(p, &cats[i])) != MPS_OK) return st;
     if ((st = ensure_particles(p, cats[i].n_particles)) != MPS_OK) return st;
   }
-  for (int i = 0; i < n; ++i) {
-    const int st = enqueue_estimate(reinterpret_cast<Plan*>(plans[i]), &cats[i], stream);
-    if (st != MPS_OK) return st;
+  // the catalogs go round robin to kBatchStreams streams, each started
+  // after the caller's earlier work on `stream`, so that small catalogs'
+  // kernels overlap; `stream` then waits for all of them
+  constexpr int kBatchStreams = 4;
+  const int ns = n < kBatchStreams ? n : kBatchStreams;
+  hipStream_t bs[kBatchStreams] = {};
+  hipEvent_t ev[kBatchStreams + 1] = {};
+  int st = MPS_OK;
+  for (int j = 0; j <= ns && st == MPS_OK; ++j)
+    if (hipEventCreateWithFlags(&ev[j], hipEventDisableTiming) != hipSuccess) st = MPS_E_HIP;
+  for (int j = 0; j < ns && st == MPS_OK; ++j)
+    if (hipStreamCreateWithFlags(&bs[j], hipStreamNonBlocking) != hipSuccess) st = MPS_E_HIP;
+  if (st == MPS_OK && hipEventRecord(ev[ns], stream) != hipSuccess) st = MPS_E_HIP;
+  for (int j = 0; j < ns && st == MPS_OK; ++j)
+    if (hipStreamWaitEvent(bs[j], ev[ns], 0) != hipSuccess) st = MPS_E_HIP;
+  for (int i = 0; i < n && st == MPS_OK; ++i)
+    st = enqueue_estimate(reinterpret_cast<Plan*>(plans[i]), &cats[i], bs[i % ns]);
+  for (int j = 0; j < ns; ++j) {  // join even after a failure, so nothing is left running
+    if (bs[j] && hipEventRecord(ev[j], bs[j]) == hipSuccess) (void)hipStreamWaitEvent(stream, ev[j], 0);
   }
-  if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
+  const bool synced = hipStreamSynchronize(stream) == hipSuccess;
+  for (int j = 0; j < ns; ++j) {
+    if (bs[j]) (void)hipStreamDestroy(bs[j]);
+  }
+  for (int j = 0; j <= ns; ++j)
+    if (ev[j]) (void)hipEventDestroy(ev[j]);
+  if (st != MPS_OK) return st;
+  if (!synced) return MPS_E_HIP;
   int first = MPS_OK;
   for (int i = 0; i < n; ++i) {
     const int st = unpack(reinterpret_cast<Plan*>(plans[i]), &cats[i], &outs[i]);
