@@ -47,7 +47,7 @@ def _log(msg):
 
 
 def algorithmic_bytes(n_grid, n_part, real):
-    """HBM bytes each stage must move at minimum."""
+    """HBM bytes each stage must move at minimum (records in, grids out)."""
     n3 = n_grid ** 3
     grid = 4 * n3 * real                     # four real (or N/2-complex) grids
     rec = 32                                 # sorted record (x, y, z, w, vx, vy, vz, pad)
@@ -346,8 +346,9 @@ def main():
                     help="after timing, copy 1 GiB device-to-device once (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the estimator's catalogs are independent and "
-              "multi-GPU runs are not part of this build (see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only (--gpus 1): independent catalogs need no "
+              "communication between GPUs, and a sharded single catalog is not implemented",
+              file=sys.stderr)
         sys.exit(2)
     if args.serving:
         serving(args)
