@@ -664,6 +664,9 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   __shared__ float red[kWaves][kNumFields];
   __shared__ float scale_s[kNumFields], inv_s[kNumFields];
   __shared__ long long s_tile;
+  // sparse tiles: tap-origin bounding box (min x, y, z, max x, y, z)
+  __shared__ int bb[6];
+  constexpr uint32_t kSparse = 128;  // at most this many particles: one per thread
   double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
   if (bulk) {
     vb0 = dsrc->vb[0];
@@ -684,6 +687,12 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   unsigned* cnt_u = reinterpret_cast<unsigned*>(acc);
   unsigned long long* acc2 = reinterpret_cast<unsigned long long*>(acc);
 
+  // largest tap-weight bound, cubed: bounds |wx wy wz| of every deposit
+  float kmax = 0.f;
+#pragma unroll
+  for (int j = 0; j < NTAP; ++j) kmax = fmaxf(kmax, kb.k[j]);
+  const float kmax3 = kmax * kmax * kmax;
+  if (t < 6) bb[t] = t < 3 ? E : -1;
   int64_t tile = next_tile<NT>(tq, n_tiles, &s_tile);
   for (int i = t; i < kNumFields * VOL; i += NT) acc[i] = 0;
   if (t < 64) bs.cnt[t] = 0;
@@ -719,6 +728,10 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     // first super-chunk: bank keys (the counters were zeroed before the
     // previous flush) and cell sums; then the cell sums of the rest
     const int m0 = static_cast<int>(min(static_cast<uint32_t>(kSuper), cnt));
+    // A sparse tile skips the per-cell bound: every cell holds at most
+    // sum_p |q_p| K^3, and only the tap-origin bounding box is flushed.
+    const bool sparse = cnt <= kSparse;  // uniform across the workgroup
+    float qsum[kNumFields] = {0.f, 0.f, 0.f, 0.f};
     unsigned key0[kPer];
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
@@ -729,9 +742,31 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         const unsigned base = tap_origin<TS, NTAP>(a, kp, ox, oy, oz);
         const unsigned b = base & 31u;
         key0[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
-        add_cell_sums(a, sorted[2 * p + 1], base + kCellOff);
+        if (sparse) {
+          const DepositQ<float> d = charges<float>(a, sorted[2 * p + 1], bulk, vb0, vb1, vb2);
+#pragma unroll
+          for (int f = 0; f < kNumFields; ++f) qsum[f] += fabsf(d.q[f]);
+          const int cx = static_cast<int>(base) / (E * E), cy = (static_cast<int>(base) / E) % E,
+                    cz = static_cast<int>(base) % E;
+          atomicMin(&bb[0], cx);
+          atomicMin(&bb[1], cy);
+          atomicMin(&bb[2], cz);
+          atomicMax(&bb[3], cx);
+          atomicMax(&bb[4], cy);
+          atomicMax(&bb[5], cz);
+        } else {
+          add_cell_sums(a, sorted[2 * p + 1], base + kCellOff);
+        }
       }
     }
+    if (sparse) {
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) {
+        float v = qsum[f];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][f] = v;
+      }
+    } else {
     for (uint32_t p = p0 + static_cast<uint32_t>(m0) + t; p < p1; p += NT) {
       const float4 a = sorted[2 * static_cast<int64_t>(p)];
       add_cell_sums(a, sorted[2 * static_cast<int64_t>(p) + 1], tap_origin<TS, NTAP>(a, kp, ox, oy, oz) + kCellOff);
@@ -788,18 +823,21 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
       if (lane == 0) red[wave][f] = m;
     }
+    }  // dense tile
     // One super-chunk: scan the bank counters, place local indices in bank
     // order, deposit.  key[r] = bank | slot << 6 of local particle t + r NT.
     auto deposit_chunk = [&](uint32_t c0, int m, const unsigned (&key)[kPer], bool first) {
       __syncthreads();
       if (first && t < kNumFields) {
         float mx = 0.f;
-        for (int w = 0; w < kWaves; ++w) mx = fmaxf(mx, red[w][t]);
-        // A in charge units (with a margin for the FP32 convolution); room
-        // for the rounding errors of up to cnt deposits per cell
-        const double bound = static_cast<double>(mx) * 1.00001 / static_cast<double>(csc[t]);
+        for (int w = 0; w < kWaves; ++w) mx = sparse ? mx + red[w][t] : fmaxf(mx, red[w][t]);
+        // A in charge units (with a margin for the FP32 convolution, or the
+        // sum bound of a sparse tile); room for the rounding errors of up to
+        // cnt deposits per cell
+        const double bound = sparse ? static_cast<double>(mx) * static_cast<double>(kmax3) * 1.0001
+                                    : static_cast<double>(mx) * 1.00001 / static_cast<double>(csc[t]);
         const double room = 0.99 * 2147483648.0 - 0.5 * static_cast<double>(cnt) - 64.0;
-        const double scl = (mx > 0.f && csc[t] > 0.f) ? fmin(room / bound, 1e30) : 0.0;
+        const double scl = (mx > 0.f && (sparse || csc[t] > 0.f)) ? fmin(room / bound, 1e30) : 0.0;
         scale_s[t] = static_cast<float>(scl);
         inv_s[t] = scl > 0.0 ? static_cast<float>(1.0 / static_cast<double>(static_cast<float>(scl))) : 0.f;
       }
@@ -870,8 +908,22 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     float inv[kNumFields];
 #pragma unroll
     for (int f = 0; f < kNumFields; ++f) inv[f] = inv_s[f];
-    for (int i = t; i < VOL; i += NT) {
-      const int ez = i % E, ey = (i / E) % E, ex = i / (E * E);
+    // dense: the whole block; sparse: the tap-origin box grown by the taps
+    int fx0 = 0, fy0 = 0, fz0 = 0, fdx = E, fdy = E, fdz = E;
+    if (sparse) {
+      fx0 = bb[0];
+      fy0 = bb[1];
+      fz0 = bb[2];
+      fdx = bb[3] + NTAP - fx0;
+      fdy = bb[4] + NTAP - fy0;
+      fdz = bb[5] + NTAP - fz0;
+      __syncthreads();  // every thread has read the box
+      if (t < 6) bb[t] = t < 3 ? E : -1;  // visible to the next tile after the final barrier
+    }
+    const int fvol = fdx * fdy * fdz;
+    for (int j = t; j < fvol; j += NT) {
+      const int ez = fz0 + j % fdz, ey = fy0 + (j / fdz) % fdy, ex = fx0 + j / (fdy * fdz);
+      const int i = (ex * E + ey) * E + ez;
       const int gx = (ox + ex - H) & (n - 1);
       const int gy = (oy + ey - H) & (n - 1);
       const int gz = (oz + ez - H) & (n - 1);
