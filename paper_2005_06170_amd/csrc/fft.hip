@@ -540,11 +540,18 @@ __global__ __launch_bounds__(NT) void mu_bin_kernel(const T* __restrict__ grid, 
     const double kx_ = mp.kf * nx, ky_ = mp.kf * ny;
     const cpx<T>* base = g + row * M;
     MuRun ra, rb;
+    // the run's bin lookups go out together (one L2 round trip, not RUN)
+    int kbs[RUN];
+#pragma unroll
     for (int r = 0; r < RUN; ++r) {
       const int nz = nz0 + r;
       const int64_t n2 = n2xy + static_cast<int64_t>(nz) * nz;
-      if (n2 == 0 || n2 >= H2) continue;
-      const int kb = lut[n2];
+      kbs[r] = (n2 == 0 || n2 >= H2) ? -1 : lut[n2];
+    }
+    for (int r = 0; r < RUN; ++r) {
+      const int nz = nz0 + r;
+      const int64_t n2 = n2xy + static_cast<int64_t>(nz) * nz;
+      const int kb = kbs[r];
       if (kb < 0) continue;
       const double iw2 = col_iw * s_iwin2[nz];
       const double cal = col_cal * s_alias[nz];
