@@ -35,6 +35,12 @@ HBM_PEAK_GBS = 8000.0
 LDS_DEPOSIT_PEAK = 256 * 16 * 2 * 2.4e9
 LDS_DEPOSIT_PROBE = 256 * 9.44 * 2 * 2.4e9
 DEPOSITS_PER_PARTICLE = 216 * 4
+# HBM bytes per dispatch of the 512^3 scatter (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, one counter per run, calibrated by a 1 GiB device copy:
+# fetched = FETCH_SIZE x 2, written = WRITE_SIZE x 1): 5.658 GB read +
+# 7.876 GB written.  Taken on the current scatter kernel; set to None
+# whenever that kernel changes, until the counters are taken again.
+SCATTER_TRAFFIC_BYTES = 5.658e9 + 7.876e9
 N_GRID = 512
 N_LAT = 512
 BOX = 1000.0
@@ -433,7 +439,9 @@ def main():
         dep_rate = DEPOSITS_PER_PARTICLE * n_part / (stages[dom] * 1e-3)
         roofline = {"kernel": dom, "bound": "alu", "achieved": dep_rate / 1e12,
                     "peak": LDS_DEPOSIT_PEAK / 1e12, "unit": "Tdeposit/s",
-                    "frac": dep_rate / LDS_DEPOSIT_PEAK, "traffic": None,
+                    "frac": dep_rate / LDS_DEPOSIT_PEAK,
+                    "traffic": SCATTER_TRAFFIC_BYTES if n_part == N_LAT ** 3 else None,
+                    "traffic_algorithmic": abytes[dom],
                     "probe_ceiling": LDS_DEPOSIT_PROBE / 1e12,
                     "frac_of_probe_ceiling": dep_rate / LDS_DEPOSIT_PROBE,
                     "hbm_frac": per_stage[dom].get("frac_hbm")}
