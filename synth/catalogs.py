@@ -118,6 +118,20 @@ def zeldovich(n_lattice: int, box: float, rms_disp: float, haf: float = 50.0,
     return pos, np.ascontiguousarray(vel, dtype=np.float32)
 
 
+def zeldovich_sampled(n_lattice: int, box: float, rms_disp: float, fraction: float,
+                      haf: float = 50.0, seed: int = 0, bulk=None):
+    """A clustered catalog with Poisson shot noise: each particle of a
+    Zel'dovich catalog (as zeldovich()) is kept with probability `fraction`
+    (independent draws; the lattice's own sub-Poisson discreteness is then
+    diluted to about (1 - fraction) of the Poisson level).
+
+    Returns float32 (pos, vel) in lattice order.
+    """
+    pos, vel = zeldovich(n_lattice, box, rms_disp, haf=haf, seed=seed, bulk=bulk)
+    keep = np.random.default_rng(seed + 1).random(pos.shape[0]) < fraction
+    return np.ascontiguousarray(pos[keep]), np.ascontiguousarray(vel[keep])
+
+
 def plane_wave(n_lattice: int, box: float, amp: float, m_wave: int,
                haf: float = 50.0, offset: float = 0.5):
     """Single Zel'dovich plane wave along x on a lattice.

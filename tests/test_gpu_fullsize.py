@@ -265,3 +265,41 @@ def test_plane_wave_control_512(mps, prec, kernel):
     assert r["p_dt"][0] > 0
     tol = 1e-3 if kernel == "bl3" else (3e-5 if prec == "f64" else 1e-4)
     assert max(errs.values()) < tol, errs
+
+
+def test_aliasing_n_vs_2n_within_the_printed_bounds(mps, zel512_dev):
+    """Sec. 2.4.3: the same catalog on 256^3 and 512^3 grids (BL3, FP32 as
+    timed), 32 linear bins up to the k_N of the 256^3 grid, against the
+    paper's bounds for its N-body sample (tests/golden/paper_claims.json):
+    below 0.2 % up to 0.5 k_N, below 0.5 % up to 0.7 k_N, and no 1 %
+    departure below the lowest of its per-spectrum thresholds (0.74 k_N).
+    The paper qualifies its third bound (under 5 % close to k_N) with
+    "generally"; on this lattice-based catalog the last bins below k_N
+    depart by up to ~12 %, so that figure is printed, not asserted."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_claims.json")))
+    g = g["aliasing_n_vs_2n_bl3"]
+    pos, vel = zel512_dev
+    kn = math.pi * (N // 2) / BOX
+    edges = kn * np.arange(33) / 32
+    res = []
+    for n in (N // 2, N):
+        plan = mps.Plan(n, "f32")
+        res.append(plan.estimate(pos, vel, box=BOX, haf=HAF, k_edges=edges))
+        plan.close()
+    lo, hi = res
+    kc = lo["k_mean"] / kn
+    first = min(g["one_percent_threshold_over_kN"].values())
+    worst = {}
+    for key in ("p_pp", "p_tt", "p_dt", "p_dd"):
+        dev = np.abs(lo[key] / hi[key] - 1.0)
+        ok = np.isfinite(dev)
+        worst[key] = (dev[ok & (kc <= 0.5)].max(), dev[ok & (kc <= 0.7)].max(),
+                      dev[ok & (kc < first)].max(), dev[ok].max())
+        print(key, "max below 0.5 k_N %.2e, 0.7 k_N %.2e, %.2f k_N %.2e, k_N %.2e" % (
+            worst[key][0], worst[key][1], first, worst[key][2], worst[key][3]), flush=True)
+    for key, (a, b, c, _) in worst.items():
+        assert a < g["max_relative_difference_at_0p5_kN"], key
+        assert b < g["max_relative_difference_below_0p7_kN"], key
+        assert c < 0.01, key
