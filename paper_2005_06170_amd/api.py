@@ -144,7 +144,10 @@ class Plan:
                  bulk_flow=False, no_shotnoise=False, no_deconvolve=False, kernel="bl3",
                  stream=None):
         """Binned P_pp, P_tt, Re P_dt, P_dd (x V) of one catalog; dict of arrays.
-        kernel: "bl3" (six-tap truncated BL3) or "bl3_exact" (untruncated)."""
+        kernel: "bl3" (six-tap truncated BL3), "bl3_exact" (untruncated, by a
+        cubic B-spline scatter and spectral correction), or a centred B-spline
+        of order p: "ngp", "cic", "tsc", "pcs", "pqs", "bspline6" (also
+        "bspline1" .. "bspline6")."""
         cat, keep = make_catalog(pos, vel, weight, box=box, haf=haf, n_bins=n_bins,
                                  k_edges=k_edges,
                                  flags=_flags(bulk_flow, no_shotnoise, no_deconvolve, kernel))
