@@ -37,10 +37,9 @@ LDS_DEPOSIT_PROBE = 256 * 9.44 * 2 * 2.4e9
 DEPOSITS_PER_PARTICLE = 216 * 4
 # HBM bytes per dispatch of the 512^3 scatter (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, one counter per run, calibrated by a 1 GiB device copy:
-# fetched = FETCH_SIZE x 2, written = WRITE_SIZE x 1): 5.658 GB read +
-# 7.876 GB written.  Taken on the current scatter kernel; set to None
-# whenever that kernel changes, until the counters are taken again.
-SCATTER_TRAFFIC_BYTES = 5.658e9 + 7.876e9
+# fetched = FETCH_SIZE x 2, written = WRITE_SIZE x 1): bytes read plus
+# written.  None: the kernel has changed since the counters were taken.
+SCATTER_TRAFFIC_BYTES = None
 N_GRID = 512
 N_LAT = 512
 BOX = 1000.0
@@ -56,7 +55,7 @@ def algorithmic_bytes(n_grid, n_part, real):
     """HBM bytes each stage must move at minimum (records in, grids out)."""
     n3 = n_grid ** 3
     grid = 4 * n3 * real                     # four real (or N/2-complex) grids
-    rec = 32                                 # sorted record (x, y, z, w, vx, vy, vz, pad)
+    rec = 24                                 # sorted record of an unweighted catalog (x, y, z, vx, vy, vz)
     inp = 24                                 # float32 pos + vel
     half = n_grid // 2
     # x pass reads only (ky, kz-block) items that intersect |n| < N/2

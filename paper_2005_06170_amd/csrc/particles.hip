@@ -341,8 +341,47 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
   if (threadIdx.x == 1023) offset[n_tiles] = part[1023];
 }
 
-// Counting-sort scatter of the particle records into tile order.  Record:
-// (x, y, z, w), (v_x, v_y, v_z, 0).  With at most kLdsTiles tiles a
+// Sorted particle records.  A catalog with weights stores (x, y, z, w) and
+// (v_x, v_y, v_z, 0) as two float4 (32 bytes); a catalog without stores
+// (x, y, z, v_x, v_y, v_z) in 24 bytes as three float2 and reads back w = 1,
+// a quarter less traffic for the permute's writes and the scatter's reads.
+template <bool kW>
+__device__ __forceinline__ float4 rec_pos(const float4* __restrict__ s, int64_t p) {
+  if constexpr (kW) {
+    return s[2 * p];
+  } else {
+    const float2* r = reinterpret_cast<const float2*>(s) + 3 * p;
+    const float2 a = r[0], b = r[1];
+    return make_float4(a.x, a.y, b.x, 1.f);
+  }
+}
+
+template <bool kW>
+__device__ __forceinline__ float4 rec_vel(const float4* __restrict__ s, int64_t p) {
+  if constexpr (kW) {
+    return s[2 * p + 1];
+  } else {
+    const float2* r = reinterpret_cast<const float2*>(s) + 3 * p;
+    const float2 b = r[1], c = r[2];
+    return make_float4(b.y, c.x, c.y, 0.f);
+  }
+}
+
+template <bool kW>
+__device__ __forceinline__ void rec_store(float4* __restrict__ s, int64_t p, const float4& a, const float4& v) {
+  if constexpr (kW) {
+    s[2 * p] = a;
+    s[2 * p + 1] = v;
+  } else {
+    float2* r = reinterpret_cast<float2*>(s) + 3 * p;
+    r[0] = make_float2(a.x, a.y);
+    r[1] = make_float2(a.z, v.x);
+    r[2] = make_float2(v.y, v.z);
+  }
+}
+
+// Counting-sort scatter of the particle records into tile order (record
+// layout above).  With at most kLdsTiles tiles a
 // workgroup first counts its own particles per tile in LDS, reserves one
 // contiguous range per tile with a single global atomic, and then hands out
 // slots from LDS; otherwise every wave claims slots with global atomics.
@@ -413,8 +452,7 @@ __global__ __launch_bounds__(kCountThreads) void permute_kernel(
       const int64_t i = base + u * kCountThreads + threadIdx.x;
       const uint32_t slot = wave_run_slot(run[u]);
       if (i < np) {
-        sorted[2 * static_cast<int64_t>(slot)] = a[u];
-        sorted[2 * static_cast<int64_t>(slot) + 1] = v[u];
+        rec_store<kHasW>(sorted, static_cast<int64_t>(slot), a[u], v[u]);
       }
     }
   }
@@ -648,7 +686,7 @@ __device__ __forceinline__ void bound_line(const float (&in)[E], const TapBound&
 // the worst-case sum of the per-deposit rounding errors (half a unit per
 // particle).  A single pass over LDS gives both the bound and the zeroed
 // accumulator.
-template <int TS, int NT, int NTAP, int DEG>
+template <int TS, int NT, int NTAP, int DEG, bool kW>
 __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, float* __restrict__ grid,
     KeyParams kp, int64_t n_tiles, TileQueues tq, TapPoly tp, TapBound kb, const Derived* dsrc, int bulk) {
@@ -738,12 +776,12 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       key0[r] = 0;
       if (t + r * NT < m0) {
         const int64_t p = static_cast<int64_t>(p0) + t + r * NT;
-        const float4 a = sorted[2 * p];
+        const float4 a = rec_pos<kW>(sorted, p);
         const unsigned base = tap_origin<TS, NTAP>(a, kp, ox, oy, oz);
         const unsigned b = base & 31u;
         key0[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
         if (sparse) {
-          const DepositQ<float> d = charges<float>(a, sorted[2 * p + 1], bulk, vb0, vb1, vb2);
+          const DepositQ<float> d = charges<float>(a, rec_vel<kW>(sorted, p), bulk, vb0, vb1, vb2);
 #pragma unroll
           for (int f = 0; f < kNumFields; ++f) qsum[f] += fabsf(d.q[f]);
           const int cx = static_cast<int>(base) / (E * E), cy = (static_cast<int>(base) / E) % E,
@@ -755,7 +793,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
           atomicMax(&bb[4], cy);
           atomicMax(&bb[5], cz);
         } else {
-          add_cell_sums(a, sorted[2 * p + 1], base + kCellOff);
+          add_cell_sums(a, rec_vel<kW>(sorted, p), base + kCellOff);
         }
       }
     }
@@ -768,8 +806,8 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       }
     } else {
     for (uint32_t p = p0 + static_cast<uint32_t>(m0) + t; p < p1; p += NT) {
-      const float4 a = sorted[2 * static_cast<int64_t>(p)];
-      add_cell_sums(a, sorted[2 * static_cast<int64_t>(p) + 1], tap_origin<TS, NTAP>(a, kp, ox, oy, oz) + kCellOff);
+      const float4 a = rec_pos<kW>(sorted, static_cast<int64_t>(p));
+      add_cell_sums(a, rec_vel<kW>(sorted, static_cast<int64_t>(p)), tap_origin<TS, NTAP>(a, kp, ox, oy, oz) + kCellOff);
     }
     __syncthreads();
     // bound convolution along z (lines of the tile's interior x, y), then y
@@ -859,8 +897,8 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         const int q = lr * slots + sl;
         if (q >= m) continue;
         const uint32_t p = c0 + bs.idx[q];
-        const float4 a = sorted[2 * static_cast<int64_t>(p)];
-        const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
+        const float4 a = rec_pos<kW>(sorted, static_cast<int64_t>(p));
+        const float4 v = rec_vel<kW>(sorted, static_cast<int64_t>(p));
         float wx[NTAP], wy[NTAP], wz[NTAP];
         const unsigned base = particle_taps<float, TS, NTAP, DEG>(a, kp, ox, oy, oz, tp, wx, wy, wz);
         const DepositQ<float> d = charges<float>(a, v, bulk, vb0, vb1, vb2);
@@ -896,7 +934,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         key[r] = 0;
         if (t + r * NT < m) {
           const unsigned b =
-              tap_origin<TS, NTAP>(sorted[2 * static_cast<int64_t>(c0 + t + r * NT)], kp, ox, oy, oz) & 31u;
+              tap_origin<TS, NTAP>(rec_pos<kW>(sorted, static_cast<int64_t>(c0 + t + r * NT)), kp, ox, oy, oz) & 31u;
           key[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
         }
       }
@@ -945,7 +983,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
 // FP64 grids: LDS accumulation with ds_add_f64 (~7 lanes/clk/CU on gfx950),
 // same tiles and bank-sorted lane order as the FP32 kernel (a double spans
 // two banks, so the key is the element index mod 32).
-template <int TS, int NT, int NTAP, int DEG>
+template <int TS, int NT, int NTAP, int DEG, bool kW>
 __global__ __launch_bounds__(NT) void scatter_f64_kernel(
     const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, double* __restrict__ grid,
     KeyParams kp, int64_t n_tiles, int64_t xcd_chunk, TapPoly tp, const Derived* dsrc, int bulk) {
@@ -984,7 +1022,7 @@ __global__ __launch_bounds__(NT) void scatter_f64_kernel(
     for (int r = 0; r < kPer; ++r) {
       const int i = t + r * NT;
       if (i < m) {
-        bank[r] = tap_origin<TS, NTAP>(sorted[2 * static_cast<int64_t>(c0 + i)], kp, ox, oy, oz) & 31u;
+        bank[r] = tap_origin<TS, NTAP>(rec_pos<kW>(sorted, static_cast<int64_t>(c0 + i)), kp, ox, oy, oz) & 31u;
         slot[r] = static_cast<unsigned>(atomicAdd(&bs.cnt[bank[r]], 1));
       }
     }
@@ -1003,8 +1041,8 @@ __global__ __launch_bounds__(NT) void scatter_f64_kernel(
       const int q = lr * slots + sl;
       if (q >= m) continue;
       const uint32_t p = c0 + bs.idx[q];
-      const float4 a = sorted[2 * static_cast<int64_t>(p)];
-      const float4 v = sorted[2 * static_cast<int64_t>(p) + 1];
+      const float4 a = rec_pos<kW>(sorted, static_cast<int64_t>(p));
+      const float4 v = rec_vel<kW>(sorted, static_cast<int64_t>(p));
       double wx[NTAP], wy[NTAP], wz[NTAP];
       const unsigned base = particle_taps<double, TS, NTAP, DEG>(a, kp, ox, oy, oz, tp, wx, wy, wz);
       const DepositQ<double> d = charges<double>(a, v, bulk, vb0, vb1, vb2);
@@ -1137,7 +1175,7 @@ hipError_t launch_clear_grid(Plan* p, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int NTAP, int DEG>
+template <int NTAP, int DEG, bool kW>
 hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int bulk, const TapPoly& tp,
                                const TapBound& tb) {
   const KeyParams kp = key_params(p, c);
@@ -1152,19 +1190,33 @@ hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int
     if (p->tile == 16) {
       // one workgroup per CU (the LDS holds one), never more than the tiles
       const int64_t blocks = p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus;
-      scatter_fixed_kernel<16, 1024, NTAP, DEG><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+      scatter_fixed_kernel<16, 1024, NTAP, DEG, kW><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
           p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk);
     } else {
       const int64_t cap = 4 * static_cast<int64_t>(p->num_cus);
       const int64_t blocks = p->n_tiles < cap ? p->n_tiles : cap;
-      scatter_fixed_kernel<8, 512, NTAP, DEG><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
+      scatter_fixed_kernel<8, 512, NTAP, DEG, kW><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
           p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk);
     }
   } else {
-    scatter_f64_kernel<8, 512, NTAP, DEG><<<static_cast<unsigned>(p->n_tiles), 512, 0, s>>>(
+    scatter_f64_kernel<8, 512, NTAP, DEG, kW><<<static_cast<unsigned>(p->n_tiles), 512, 0, s>>>(
         p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, xcd_chunk, tp, dsrc, bulk);
   }
   return hipGetLastError();
+}
+
+template <bool kW>
+hipError_t launch_scatter_kernel(Plan* p, const mps_catalog* c, hipStream_t s, int bulk, int k, const TapPoly& tp,
+                                 const TapBound& tb) {
+  switch (k) {
+    case 1: return launch_scatter_taps<1, 0, kW>(p, c, s, bulk, tp, tb);
+    case 2: return launch_scatter_taps<2, 1, kW>(p, c, s, bulk, tp, tb);
+    case 3: return launch_scatter_taps<3, 2, kW>(p, c, s, bulk, tp, tb);
+    case 4: return launch_scatter_taps<4, 3, kW>(p, c, s, bulk, tp, tb);
+    case 5: return launch_scatter_taps<5, 4, kW>(p, c, s, bulk, tp, tb);
+    case 6: return launch_scatter_taps<6, 5, kW>(p, c, s, bulk, tp, tb);
+    default: return launch_scatter_taps<6, 3, kW>(p, c, s, bulk, tp, tb);
+  }
 }
 
 // bulk: 1 = deposit w (v - v_b) (only the assign diagnostic asks for it; the
@@ -1173,15 +1225,9 @@ hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int
   const int k = kernel_id(c->flags);
   const TapPoly& tp = p->taps[k];
   const TapBound& tb = p->tap_bound[k];
-  switch (k) {
-    case 1: return launch_scatter_taps<1, 0>(p, c, s, bulk, tp, tb);
-    case 2: return launch_scatter_taps<2, 1>(p, c, s, bulk, tp, tb);
-    case 3: return launch_scatter_taps<3, 2>(p, c, s, bulk, tp, tb);
-    case 4: return launch_scatter_taps<4, 3>(p, c, s, bulk, tp, tb);
-    case 5: return launch_scatter_taps<5, 4>(p, c, s, bulk, tp, tb);
-    case 6: return launch_scatter_taps<6, 5>(p, c, s, bulk, tp, tb);
-    default: return launch_scatter_taps<6, 3>(p, c, s, bulk, tp, tb);
-  }
+  // the record layout the permute wrote for this catalog
+  return c->weight ? launch_scatter_kernel<true>(p, c, s, bulk, k, tp, tb)
+                   : launch_scatter_kernel<false>(p, c, s, bulk, k, tp, tb);
 }
 
 hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s) {
