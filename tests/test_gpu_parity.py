@@ -134,6 +134,30 @@ def test_ragged_many_tiles(mps, prec):
     compare_spectra(g, o, TOL[prec], f"ragged {prec}")
 
 
+@pytest.mark.parametrize("prec,kernel", [("f32", "bl3"), ("f64", "bl3"), ("f32", "bl3_exact"),
+                                         ("f32", "pqs")])
+def test_unit_weights_match_no_weights(mps, prec, kernel):
+    """A catalog with explicit unit weights is sorted into 32-byte records
+    (x, y, z, w | v), one without weights into 24-byte ones (x, y, z, v):
+    both must give the same spectra and the oracle's.  64^3 grid, clustered
+    so that tiles hold uneven counts."""
+    box, n, haf = 1000.0, 64, 50.0
+    pos, vel = catalogs.zeldovich(64, box, 12.0, haf=haf, seed=catalogs.seed_for(1, 30))
+    w = np.ones(pos.shape[0], dtype=np.float32)
+    plan = mps.Plan(n, prec)
+    a = plan.estimate(*_dev(pos, vel), box=box, haf=haf, n_bins=24, kernel=kernel, bulk_flow=True)
+    b = plan.estimate(*_dev(pos, vel, w), box=box, haf=haf, n_bins=24, kernel=kernel, bulk_flow=True)
+    for key, sn in (("p_pp", a["sn_pp"]), ("p_tt", a["sn_tt"]), ("p_dd", a["sn_dd"]),
+                    ("p_dt", np.sqrt(a["sn_dd"] * a["sn_tt"]))):
+        # the two differ only by the order of the flush's atomic additions
+        e = np.abs(a[key] - b[key]) / (np.abs(b[key]) + np.abs(sn))
+        assert np.nanmax(e) < (1e-12 if prec == "f64" else 1e-6), (key, np.nanmax(e))
+    np.testing.assert_allclose(a["v_bulk"], b["v_bulk"], rtol=1e-12)
+    o = oracle.estimate(pos, vel, box=box, n_grid=n, haf=haf, n_bins=24, kernel=kernel,
+                        flags=oracle.FLAG_BULKFLOW_SUBTRACT)
+    compare_spectra(a, o, TOL[prec], f"no weights {prec} {kernel}")
+
+
 def test_error_paths(mps):
     from paper_2005_06170_amd._lib import MpsError
     box = 100.0
