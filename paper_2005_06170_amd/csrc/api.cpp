@@ -29,7 +29,7 @@ void dfree(void* p) {
 
 size_t real_bytes(mps_precision prec) { return prec == MPS_F64 ? 8 : 4; }
 
-int tile_for(int n, mps_precision prec) { return (prec == MPS_F32 && n >= 16) ? 16 : 8; }
+int tile_for(int n, mps_precision) { return n >= 16 ? 16 : 8; }
 
 int num_cus() {
   int dev = 0, cus = 0;

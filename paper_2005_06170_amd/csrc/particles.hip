@@ -1175,6 +1175,126 @@ hipError_t launch_clear_grid(Plan* p, hipStream_t s) {
   return hipGetLastError();
 }
 
+// FP64 grids on 16^3 tiles.  Four FP64 fields of a 21^3 block would need
+// 296 KB of LDS, so the block holds two at a time (148 KB, one workgroup per
+// CU) and each tile is deposited and flushed twice: (rho, rho v_x), then
+// (rho v_y, rho v_z).  Against 8^3 tiles (one 13^3 block per tile, 4.3x the
+// tile's cells) the flush's global FP64 atomics fall to 2.3x the tile's
+// cells.  Persistent over the same tile queues as the FP32 kernel; lanes in
+// the same bank-sorted order.
+template <int TS, int NT, int NTAP, int DEG, bool kW>
+__global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
+    const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, double* __restrict__ grid,
+    KeyParams kp, int64_t n_tiles, TileQueues tq, TapPoly tp, const Derived* dsrc, int bulk) {
+  constexpr int H = kHaloLo<NTAP>;
+  constexpr int E = TS + NTAP - 1;
+  constexpr int VOL = E * E * E;
+  constexpr int kPer = 6;
+  constexpr int kSuper = kPer * NT;
+  constexpr int kWaves = NT / 64;
+  __shared__ double acc[2 * VOL];
+  __shared__ BankSort<NT, kPer> bs;
+  __shared__ long long s_tile;
+  double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
+  if (bulk) {
+    vb0 = dsrc->vb[0];
+    vb1 = dsrc->vb[1];
+    vb2 = dsrc->vb[2];
+  }
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+  const int nt = kp.nt;
+  const int n = kp.n;
+  const int64_t n3 = static_cast<int64_t>(n) * n * n;
+  for (int i = t; i < 2 * VOL; i += NT) acc[i] = 0.0;
+  int64_t tile = next_tile<NT>(tq, n_tiles, &s_tile);
+  while (tile >= 0) {
+    const uint32_t p0 = offset[tile], p1 = offset[tile + 1];
+    if (p0 == p1) {  // nothing to deposit or flush (uniform across the workgroup)
+      tile = next_tile<NT>(tq, n_tiles, &s_tile);
+      continue;
+    }
+    const int tz = static_cast<int>(tile % nt);
+    const int ty = static_cast<int>((tile / nt) % nt);
+    const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
+    const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (uint32_t c0 = p0; c0 < p1; c0 += kSuper) {
+        const int m = static_cast<int>(min(static_cast<uint32_t>(kSuper), p1 - c0));
+        if (t < 64) bs.cnt[t] = 0;
+        __syncthreads();
+        unsigned bank[kPer], slot[kPer];
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+          const int i = t + r * NT;
+          if (i < m) {
+            bank[r] = tap_origin<TS, NTAP>(rec_pos<kW>(sorted, static_cast<int64_t>(c0 + i)), kp, ox, oy, oz) & 31u;
+            slot[r] = static_cast<unsigned>(atomicAdd(&bs.cnt[bank[r]], 1));
+          }
+        }
+        __syncthreads();
+        bank_scan<NT, kPer>(bs);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+          const int i = t + r * NT;
+          if (i < m) bs.idx[bs.cnt[bank[r]] + slot[r]] = static_cast<unsigned short>(i);
+        }
+        __syncthreads();
+        const int slots = (m + 63) >> 6;
+        const int lr = ((lane & 31) << 1) | (lane >> 5);
+        for (int sl = wave; sl < slots; sl += kWaves) {
+          const int q = lr * slots + sl;
+          if (q >= m) continue;
+          const uint32_t p = c0 + bs.idx[q];
+          const float4 a = rec_pos<kW>(sorted, static_cast<int64_t>(p));
+          const float4 v = rec_vel<kW>(sorted, static_cast<int64_t>(p));
+          double wx[NTAP], wy[NTAP], wz[NTAP];
+          const unsigned base = particle_taps<double, TS, NTAP, DEG>(a, kp, ox, oy, oz, tp, wx, wy, wz);
+          const DepositQ<double> d = charges<double>(a, v, bulk, vb0, vb1, vb2);
+          const double q0 = pass ? d.q[2] : d.q[0];
+          const double q1 = pass ? d.q[3] : d.q[1];
+          double qz[2][NTAP];
+#pragma unroll
+          for (int j = 0; j < NTAP; ++j) {
+            qz[0][j] = q0 * wz[j];
+            qz[1][j] = q1 * wz[j];
+          }
+          double* accf[2] = {acc + base, acc + VOL + base};
+#pragma unroll
+          for (int jx = 0; jx < NTAP; ++jx) {
+#pragma unroll
+            for (int jy = 0; jy < NTAP; ++jy) {
+              const double wxy = wx[jx] * wy[jy];
+#pragma unroll
+              for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int jz = 0; jz < NTAP; ++jz) atomicAdd(accf[k] + (jx * E + jy) * E + jz, wxy * qz[k][jz]);
+            }
+          }
+        }
+        __syncthreads();
+      }
+      // flush this pass's two fields, clearing the block for the next
+      for (int i = t; i < VOL; i += NT) {
+        const int ez = i % E, ey = (i / E) % E, ex = i / (E * E);
+        const int gx = (ox + ex - H) & (n - 1);
+        const int gy = (oy + ey - H) & (n - 1);
+        const int gz = (oz + ez - H) & (n - 1);
+        const int64_t gi = (static_cast<int64_t>(gx) * n + gy) * n + gz;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const double val = acc[k * VOL + i];
+          acc[k * VOL + i] = 0.0;
+          if (val != 0.0) atomicAdd(grid + (2 * pass + k) * n3 + gi, val);
+        }
+      }
+      __syncthreads();
+    }
+    tile = next_tile<NT>(tq, n_tiles, &s_tile);
+  }
+}
+
 template <int NTAP, int DEG, bool kW>
 hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int bulk, const TapPoly& tp,
                                const TapBound& tb) {
@@ -1198,6 +1318,15 @@ hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int
       scatter_fixed_kernel<8, 512, NTAP, DEG, kW><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
           p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk);
     }
+  } else if (p->tile == 16) {
+    TileQueues tq;
+    tq.counter = p->tile_queue;
+    tq.nq = xcd_chunk > 0 ? 8 : 1;
+    tq.per_queue = xcd_chunk > 0 ? xcd_chunk : p->n_tiles;
+    clear_kernel<uint32_t><<<1, 64, 0, s>>>(p->tile_queue, 8);
+    const int64_t blocks = p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus;
+    scatter_f64_pair_kernel<16, 1024, NTAP, DEG, kW><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+        p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, tq, tp, dsrc, bulk);
   } else {
     scatter_f64_kernel<8, 512, NTAP, DEG, kW><<<static_cast<unsigned>(p->n_tiles), 512, 0, s>>>(
         p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, xcd_chunk, tp, dsrc, bulk);
