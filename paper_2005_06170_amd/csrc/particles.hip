@@ -697,6 +697,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   constexpr int kSuper = kPer * NT;
   constexpr int kWaves = NT / 64;
   constexpr int kCellOff = (H * E + H) * E + H;  // tap origin -> the particle's own cell
+  constexpr int kBoundFields = 2;                 // rho, and the momentum fields together
   __shared__ __align__(16) int acc[kNumFields * VOL];
   __shared__ BankSort<NT, kPer> bs;
   __shared__ float red[kWaves][kNumFields];
@@ -755,13 +756,18 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       csc[f] = (qmax[f] > 0.0 && cnt > 0)
                    ? static_cast<float>((4294967295.0 - cnt) * (1.0 - 1e-6) / (static_cast<double>(cnt) * qmax[f]))
                    : 0.f;
+    // Two bound fields: rho's scaled charges, and for the three momentum
+    // fields the largest of their scaled charges (each field's own scale
+    // then divides that bound); u32 cannot overflow, since every scaled
+    // charge is at most (2^32 - 1 - cnt) / cnt.
     auto add_cell_sums = [&](const float4& a, const float4& v, unsigned cell) {
       const DepositQ<float> d = charges<float>(a, v, bulk, vb0, vb1, vb2);
+      const unsigned u0 = static_cast<unsigned>(ceilf(fabsf(d.q[0]) * csc[0]));
+      unsigned u1 = 0;
 #pragma unroll
-      for (int f = 0; f < kNumFields; ++f) {
-        const unsigned u = static_cast<unsigned>(ceilf(fabsf(d.q[f]) * csc[f]));
-        if (u) atomicAdd(cnt_u + f * VOL + cell, u);
-      }
+      for (int f = 1; f < kNumFields; ++f) u1 = max(u1, static_cast<unsigned>(ceilf(fabsf(d.q[f]) * csc[f])));
+      if (u0) atomicAdd(cnt_u + cell, u0);
+      if (u1) atomicAdd(cnt_u + VOL + cell, u1);
     };
     // first super-chunk: bank keys (the counters were zeroed before the
     // previous flush) and cell sums; then the cell sums of the rest
@@ -812,7 +818,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     __syncthreads();
     // bound convolution along z (lines of the tile's interior x, y), then y
     // (interior x), as floats in place
-    for (int rr = t; rr < kNumFields * TS * TS; rr += NT) {
+    for (int rr = t; rr < kBoundFields * TS * TS; rr += NT) {
       const int f = rr / (TS * TS);
       const int x = H + (rr / TS) % TS, y = H + rr % TS;
       int* line = acc + f * VOL + (x * E + y) * E;
@@ -824,7 +830,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       for (int g = 0; g < E; ++g) line[g] = __float_as_int(out[g]);
     }
     __syncthreads();
-    for (int rr = t; rr < kNumFields * TS * E; rr += NT) {
+    for (int rr = t; rr < kBoundFields * TS * E; rr += NT) {
       const int f = rr / (TS * E);
       const int x = H + (rr / E) % TS, z = rr % E;
       int* line = acc + f * VOL + x * E * E + z;
@@ -837,8 +843,8 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     }
     __syncthreads();
     // along x: the maximum only; the lines are cleared for the deposits
-    float amax[kNumFields] = {0.f, 0.f, 0.f, 0.f};
-    for (int rr = t; rr < kNumFields * E * E; rr += NT) {
+    float amax[kBoundFields] = {0.f, 0.f};
+    for (int rr = t; rr < kBoundFields * E * E; rr += NT) {
       const int f = rr / (E * E);
       int* line = acc + f * VOL + rr % (E * E);
       float in[E], out[E];
@@ -852,11 +858,11 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
 #pragma unroll
       for (int g = 0; g < E; ++g) m = fmaxf(m, out[g]);
 #pragma unroll
-      for (int ff = 0; ff < kNumFields; ++ff)
+      for (int ff = 0; ff < kBoundFields; ++ff)
         if (ff == f) amax[ff] = fmaxf(amax[ff], m);
     }
 #pragma unroll
-    for (int f = 0; f < kNumFields; ++f) {
+    for (int f = 0; f < kBoundFields; ++f) {
       float m = amax[f];
       for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
       if (lane == 0) red[wave][f] = m;
@@ -868,7 +874,8 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       __syncthreads();
       if (first && t < kNumFields) {
         float mx = 0.f;
-        for (int w = 0; w < kWaves; ++w) mx = sparse ? mx + red[w][t] : fmaxf(mx, red[w][t]);
+        const int bf = t < kBoundFields ? t : kBoundFields - 1;  // dense: the field's bound field
+        for (int w = 0; w < kWaves; ++w) mx = sparse ? mx + red[w][t] : fmaxf(mx, red[w][bf]);
         // A in charge units (with a margin for the FP32 convolution, or the
         // sum bound of a sparse tile); room for the rounding errors of up to
         // cnt deposits per cell
