@@ -38,8 +38,9 @@ DEPOSITS_PER_PARTICLE = 216 * 4
 # HBM bytes per dispatch of the 512^3 scatter (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, one counter per run, calibrated by a 1 GiB device copy:
 # fetched = FETCH_SIZE x 2, written = WRITE_SIZE x 1): bytes read plus
-# written.  None: the kernel has changed since the counters were taken.
-SCATTER_TRAFFIC_BYTES = None
+# written, 3.352 GB + 7.876 GB, on the current kernel.  Set to None whenever
+# the kernel changes, until the counters are taken again.
+SCATTER_TRAFFIC_BYTES = 3.352e9 + 7.876e9
 N_GRID = 512
 N_LAT = 512
 BOX = 1000.0
