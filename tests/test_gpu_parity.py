@@ -158,6 +158,36 @@ def test_unit_weights_match_no_weights(mps, prec, kernel):
     compare_spectra(a, o, TOL[prec], f"no weights {prec} {kernel}")
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_plan_reuse_across_entry_points(mps, prec):
+    """A plan keeps its grid, sorted records and tables between calls.  One
+    plan driven through the isotropic and (k, mu_b) estimates and the
+    assignment in turn must give each estimate exactly what a fresh plan
+    gives (up to the order of the flush's atomic additions)."""
+    box, n, haf = 1000.0, 32, 50.0
+    cats = [catalogs.uniform_gaussian(20_000 + 1000 * i, box, seed=catalogs.seed_for(1, 40 + i)) for i in range(3)]
+    cats[2] = catalogs.zeldovich(24, box, 15.0, haf=haf, seed=catalogs.seed_for(1, 43))
+
+    def fresh(pos, vel):
+        return mps.Plan(n, prec).estimate(*_dev(pos, vel), box=box, haf=haf, n_bins=12)
+
+    want = [fresh(*c) for c in cats]
+    plan = mps.Plan(n, prec)
+    got = [plan.estimate(*_dev(*cats[0]), box=box, haf=haf, n_bins=12)]
+    got.append(plan.estimate(*_dev(*cats[1]), box=box, haf=haf, n_bins=12))
+    plan.estimate_mu(*_dev(*cats[2]), box=box, haf=haf, n_mu=3, n_bins=12)
+    got.append(plan.estimate(*_dev(*cats[0]), box=box, haf=haf, n_bins=12))
+    plan.assign(*_dev(*cats[1]), box=box)
+    got.append(plan.estimate(*_dev(*cats[2]), box=box, haf=haf, n_bins=12))
+    got.append(plan.estimate(*_dev(*cats[1]), box=box, haf=haf, n_bins=12))
+    tol = 1e-12 if prec == "f64" else 1e-6
+    for g, w in zip(got, [want[0], want[1], want[0], want[2], want[1]]):
+        for key, sn in (("p_pp", w["sn_pp"]), ("p_tt", w["sn_tt"]), ("p_dd", w["sn_dd"]),
+                        ("p_dt", np.sqrt(w["sn_dd"] * w["sn_tt"]))):
+            e = np.abs(g[key] - w[key]) / (np.abs(w[key]) + np.abs(sn))
+            assert np.nanmax(e) < tol, (prec, key, np.nanmax(e))
+
+
 def test_error_paths(mps):
     from paper_2005_06170_amd._lib import MpsError
     box = 100.0
