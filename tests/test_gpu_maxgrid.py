@@ -9,7 +9,12 @@ this size, so the checks are exact closed forms and properties:
   all four spectra against their closed forms (Bessel functions of
   z = k0 A), as at 512^3;
 * exact shell mode counts against an integer count;
-* the FP32 path against the FP64 path on a clustered catalog.
+* the FP32 path against the FP64 path on a clustered catalog;
+* the largest catalog a plan accepts, 2^31 - 1 particles (uniform, on a
+  128^3 grid: 4.2M particles per 16^3 tile): N times the density shot term
+  (V C(k) / (N W^2(k)) per bin for unit weights) equals that of a 10^6
+  particle catalog on the same grid, so the FP64 moment sums hold all
+  2^31 - 1 particles, and FP32 matches FP64.
 """
 import math
 
@@ -123,4 +128,35 @@ def test_maxgrid_fp32_matches_fp64(mps, clustered):
                     ("p_dt", np.sqrt(b["sn_dd"] * b["sn_tt"]))):
         errs[key] = float(guarded_rel(a[key], b[key], sn).max())
     print("1024^3 FP32 vs FP64 max guarded per-bin error:", errs, flush=True)
+    assert max(errs.values()) <= 3e-4, errs
+
+
+def test_max_particle_count(mps):
+    n_part = 2 ** 31 - 1
+    g = torch.Generator(device="cuda").manual_seed(catalogs.seed_for(3, 5))
+    pos = torch.rand((n_part, 3), generator=g, device="cuda") * BOX
+    vel = torch.randn((n_part, 3), generator=g, device="cuda") * 300.0
+    n_small = 10 ** 6
+    outs = {}
+    for p in ("f32", "f64"):
+        plan = mps.Plan(128, p)
+        outs[p] = plan.estimate(pos, vel, box=BOX, haf=HAF, n_bins=16)
+        if p == "f64":
+            small = plan.estimate(pos[:n_small].contiguous(), vel[:n_small].contiguous(),
+                                  box=BOX, haf=HAF, n_bins=16)
+        plan.close()
+        _release()
+    del pos, vel
+    _release()
+    a, b = outs["f32"], outs["f64"]
+    ok = b["n_modes"] > 0
+    # unit weights: S_dd = W_2 / W^2 = 1 / N, so N sn_dd depends on the grid only
+    for r in (a, b):
+        np.testing.assert_allclose(r["sn_dd"][ok] * n_part, small["sn_dd"][ok] * n_small, rtol=1e-12)
+    assert np.array_equal(a["n_modes"], b["n_modes"])
+    errs = {}
+    for key, sn in (("p_pp", b["sn_pp"]), ("p_tt", b["sn_tt"]), ("p_dd", b["sn_dd"]),
+                    ("p_dt", np.sqrt(b["sn_dd"] * b["sn_tt"]))):
+        errs[key] = float(guarded_rel(a[key], b[key], sn).max())
+    print("2^31 - 1 particles on 128^3, FP32 vs FP64 max guarded per-bin error:", errs, flush=True)
     assert max(errs.values()) <= 3e-4, errs
