@@ -90,6 +90,20 @@ def test_three_cubes_per_axis_with_weights(mps, prec):
     _compare_stats(g, want, TOL[prec], f"{prec} n_div=3")
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_largest_split(mps, prec):
+    """n_div = 8, the largest split (512 sub-samples of 125 Mpc/h, 8^3
+    grids), clustered so that the cubes hold very different counts."""
+    pos, vel = catalogs.zeldovich(64, BOX, 20.0, haf=HAF, seed=catalogs.seed_for(4, 3))
+    want = S.estimate_subcubes(pos, vel, box=BOX, n_div=8, n_grid=8, haf=HAF, n_bins=4)
+    g = mps.Plan(8, prec).estimate_subcubes(*_dev(pos, vel), box=BOX, haf=HAF, n_div=8, n_bins=4)
+    assert len(g["sub"]) == 512 and np.all(g["status"] == 0)
+    for s, (gs, ws) in enumerate(zip(g["sub"], want["sub"])):
+        compare_spectra(gs, ws, TOL[prec], f"{prec} n_div=8 cube {s}")
+        assert gs["n_eff"] == ws.n_eff
+    _compare_stats(g, want, TOL[prec], f"{prec} n_div=8")
+
+
 def test_empty_cubes_report_zero_weight(mps):
     pos, vel = catalogs.uniform_gaussian(20000, BOX, seed=catalogs.seed_for(4, 3))
     pos[:, 0] *= 0.5  # x < L / 2: the cubes with m_x = 1 are empty
