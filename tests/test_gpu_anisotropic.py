@@ -62,6 +62,20 @@ def test_mu_spectra_match_oracle(mps, prec, case):
     compare_mu(g, o, TOL[prec], f"{case} {prec}")
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_most_mu_cells(mps, prec):
+    """64 mu bins, the most allowed, times 8 k bins: 512 cells, the most
+    allowed (most hold a handful of modes on a 64^3 grid)."""
+    pos, vel = catalogs.zeldovich(48, BOX, 10.0, haf=HAF, seed=catalogs.seed_for(2, 5))
+    vel = (vel.astype(np.float64) + catalogs.bulk_vector(51.5)[None, :]).astype(np.float32)
+    o = oracle.estimate_mu(pos, vel, box=BOX, n_grid=64, haf=HAF, n_mu=64, n_bins=8,
+                           flags=oracle.FLAG_BULKFLOW_SUBTRACT)
+    g = mps.Plan(64, prec).estimate_mu(*_dev(pos, vel), box=BOX, haf=HAF, n_mu=64, n_bins=8,
+                                       bulk_flow=True)
+    assert g["n_modes"].shape == (8, 64)
+    compare_mu(g, o, TOL[prec], f"512 cells {prec}")
+
+
 def test_mu_marginal_matches_isotropic_estimate(mps):
     """The library's own (k, mu) cells sum back to its isotropic bins."""
     pos, vel = catalogs.zeldovich(32, BOX, 10.0, haf=HAF, seed=catalogs.seed_for(2, 4))

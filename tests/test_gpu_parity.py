@@ -107,6 +107,22 @@ def test_user_edges_and_zeldovich(mps, prec):
     compare_spectra(g, o, TOL[prec], f"edges {prec}")
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_most_bins(mps, prec):
+    """128 bins, the most allowed, linear up to k_N of a 64^3 grid (the
+    lowest hold a few modes, some none), then 129 edges are refused."""
+    box, n, haf = 1000.0, 64, 50.0
+    pos, vel = catalogs.zeldovich(48, box, 6.0, haf=haf, seed=catalogs.seed_for(1, 50))
+    edges = np.linspace(0.0, math.pi * n / box, 129)
+    o = oracle.estimate(pos, vel, box=box, n_grid=n, haf=haf, k_edges=edges)
+    g = mps.Plan(n, prec).estimate(*_dev(pos, vel), box=box, haf=haf, k_edges=edges)
+    assert g["n_modes"].shape == (128,) and np.any(g["n_modes"] == 0)
+    compare_spectra(g, o, TOL[prec], f"128 bins {prec}")
+    with pytest.raises(mps.MpsError):
+        mps.Plan(n, prec).estimate(*_dev(pos, vel), box=box, haf=haf,
+                                   k_edges=np.linspace(0.0, math.pi * n / box, 130))
+
+
 def test_tiny_grid_and_single_particle(mps):
     box = 10.0
     pos = np.array([[3.3, 9.99, 0.0]], np.float32)

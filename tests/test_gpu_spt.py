@@ -50,6 +50,36 @@ def test_fine_table_and_many_k(mps):
             assert abs(got[key][i] / v - 1) < 1e-8, (i, key, got[key][i], v)
 
 
+def test_largest_table(mps, oracle24):
+    """2048 nodes, the most a table may hold: the 24-node table refined 89
+    times per interval with values on its own log-log lines, so that P0 is
+    the same function and the spectra must be the 24-node oracle's."""
+    tk, tp, ks, want = oracle24
+    sub = np.linspace(0.0, 1.0, 90)[:-1]
+    lk = (np.log(tk[:-1])[:, None] + sub[None, :] * np.diff(np.log(tk))[:, None]).ravel()
+    fk = np.exp(np.append(lk, np.log(tk[-1])))
+    assert fk.size == 2048
+    fp = np.exp(np.interp(np.log(fk), np.log(tk), np.log(tp)))
+    got = mps.spt_one_loop(ks, fk, fp, d_z=0.8, haf=50.0)
+    for key in spt.QUANTITIES:
+        err = np.abs(got[key] - want[key]) / np.abs(want[key])
+        print(key, "2048-node table: max relative error", float(err.max()), flush=True)
+        assert err.max() < 1e-7, (key, got[key], want[key])
+
+
+def test_most_wavenumbers(mps, oracle24):
+    """65536 wavenumbers, the most one call takes, with the oracle's five
+    among them."""
+    tk, tp, ks, want = oracle24
+    grid = np.geomspace(0.002, 1.0, 65536 - ks.size)
+    allk = np.concatenate([grid, ks])
+    got = mps.spt_one_loop(allk, tk, tp, d_z=0.8, haf=50.0)
+    for key in spt.QUANTITIES:
+        assert np.all(np.isfinite(got[key])), key
+        err = np.abs(got[key][-ks.size:] - want[key]) / np.abs(want[key])
+        assert err.max() < 1e-8, (key, err.max())
+
+
 def test_errors(mps):
     tk, tp = _power_law_table(16)
     for bad in (dict(k=[0.1, -1.0]), dict(table_k=tk[::-1]), dict(table_p=-tp), dict(haf=0.0)):
