@@ -1226,28 +1226,32 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
     const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
     const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
     for (int pass = 0; pass < 2; ++pass) {
+      // a tile of one super-chunk keeps its bank order for the second pass
+      const bool resort = pass == 0 || p1 - p0 > static_cast<uint32_t>(kSuper);
       for (uint32_t c0 = p0; c0 < p1; c0 += kSuper) {
         const int m = static_cast<int>(min(static_cast<uint32_t>(kSuper), p1 - c0));
-        if (t < 64) bs.cnt[t] = 0;
-        __syncthreads();
-        unsigned bank[kPer], slot[kPer];
+        if (resort) {
+          if (t < 64) bs.cnt[t] = 0;
+          __syncthreads();
+          unsigned bank[kPer], slot[kPer];
 #pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-          const int i = t + r * NT;
-          if (i < m) {
-            bank[r] = tap_origin<TS, NTAP>(rec_pos<kW>(sorted, static_cast<int64_t>(c0 + i)), kp, ox, oy, oz) & 31u;
-            slot[r] = static_cast<unsigned>(atomicAdd(&bs.cnt[bank[r]], 1));
+          for (int r = 0; r < kPer; ++r) {
+            const int i = t + r * NT;
+            if (i < m) {
+              bank[r] = tap_origin<TS, NTAP>(rec_pos<kW>(sorted, static_cast<int64_t>(c0 + i)), kp, ox, oy, oz) & 31u;
+              slot[r] = static_cast<unsigned>(atomicAdd(&bs.cnt[bank[r]], 1));
+            }
           }
-        }
-        __syncthreads();
-        bank_scan<NT, kPer>(bs);
-        __syncthreads();
+          __syncthreads();
+          bank_scan<NT, kPer>(bs);
+          __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-          const int i = t + r * NT;
-          if (i < m) bs.idx[bs.cnt[bank[r]] + slot[r]] = static_cast<unsigned short>(i);
+          for (int r = 0; r < kPer; ++r) {
+            const int i = t + r * NT;
+            if (i < m) bs.idx[bs.cnt[bank[r]] + slot[r]] = static_cast<unsigned short>(i);
+          }
+          __syncthreads();
         }
-        __syncthreads();
         const int slots = (m + 63) >> 6;
         const int lr = ((lane & 31) << 1) | (lane >> 5);
         for (int sl = wave; sl < slots; sl += kWaves) {
