@@ -1224,12 +1224,6 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
     vb1 = dsrc->vb[1];
     vb2 = dsrc->vb[2];
   }
-  // catalog-wide bound of |q| per field for the charges deposited here
-  double qmax[kNumFields];
-  qmax[0] = dsrc->qmax[0];
-  qmax[1] = dsrc->qmax[1] + (bulk ? dsrc->qmax[0] * fabs(vb0) : 0.0);
-  qmax[2] = dsrc->qmax[2] + (bulk ? dsrc->qmax[0] * fabs(vb1) : 0.0);
-  qmax[3] = dsrc->qmax[3] + (bulk ? dsrc->qmax[0] * fabs(vb2) : 0.0);
   double kmax = 0.0;
 #pragma unroll
   for (int j = 0; j < NTAP; ++j) kmax = fmax(kmax, static_cast<double>(kb.k[j]));
@@ -1258,7 +1252,12 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
       double scl[2], inv[2];
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
-        const double dep = qmax[2 * pass + k] * kmax3 * 1.0001;
+        // catalog-wide bound of |q| for the field's charges (with the bulk
+        // term when the assign diagnostic deposits v - v_b)
+        const int f = 2 * pass + k;
+        const double vbf = f == 1 ? vb0 : (f == 2 ? vb1 : vb2);
+        const double qmax = dsrc->qmax[f] + (bulk && f > 0 ? dsrc->qmax[0] * fabs(vbf) : 0.0);
+        const double dep = qmax * kmax3 * 1.0001;
         const double cell = static_cast<double>(p1 - p0) * dep;
         scl[k] = dep > 0.0 ? fmin(0x1p50 / dep, 0x1p62 / cell) : 0.0;
         inv[k] = dep > 0.0 ? 1.0 / scl[k] : 0.0;
