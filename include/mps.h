@@ -177,7 +177,14 @@ typedef struct mps_server mps_server;
 /* Create a plan for N^3 grids (N a power of two in [8, 1024]) on the current
  * HIP device.  The plan owns the four grids, FFT twiddles, the BL3 tables
  * and the bin tables; particle workspace grows on demand (or see
- * mps_plan_reserve).  A plan is not thread-safe. */
+ * mps_plan_reserve).  A plan is not thread-safe.
+ *
+ * prec is the grid and FFT precision.  MPS_F32: the assignment sums in
+ * 32-bit fixed point scaled per tile from a bound on every cell, so the
+ * grid carries FP32-level resolution.  MPS_F64: the assignment sums in
+ * 64-bit fixed point with a unit of 2^-50 of the largest possible deposit
+ * (coarser only for tiles of more than 4096 particles), FP64-level.  The
+ * moments, tables, per-mode estimator and shell sums are FP64 in both. */
 int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec);
 int mps_plan_destroy(mps_plan* plan);
 
