@@ -55,21 +55,6 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-def build_probes(verbose: bool = False) -> str:
-    """Build the LDS atomic throughput probe (a standalone executable)."""
-    exe = os.path.join(HERE, "lds_atomic_probe")
-    src = os.path.join(CSRC, "probes", "lds_atomic_probe.cpp")
-    cmd = [HIPCC, "-xhip", *FLAGS, src, "-o", exe]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed on the probe:\n{res.stdout}\n{res.stderr}")
-    if verbose:
-        print("built", exe)
-    return exe
-
-
 if __name__ == "__main__":
     build(verbose=True)
-    if "--probes" in sys.argv:
-        build_probes(verbose=True)
     sys.exit(0)
