@@ -8,6 +8,6 @@ from .estimator import (  # noqa: F401
     FLAG_BULKFLOW_SUBTRACT, FLAG_NO_DECONVOLVE, FLAG_NO_SHOTNOISE, Spectra,
     assign, assign_cells, bin_modes, cell_and_fraction, default_bin_index, edge_thresholds,
     edges_bin_index, estimate, fourier_fields, mode_quantities, moments)
-from . import bl3  # noqa: F401
+from . import bl3, bl3_quadratic  # noqa: F401
 from .anisotropic import estimate_mu, mu_bin, unit_axis  # noqa: F401
 from . import bspline, subcubes  # noqa: F401

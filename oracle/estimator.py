@@ -42,7 +42,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.fft
 
-from . import bl3
+from . import bl3, bl3_quadratic
 
 FLAG_BULKFLOW_SUBTRACT = 1
 FLAG_NO_SHOTNOISE = 2
@@ -80,7 +80,7 @@ def cell_and_fraction(pos, box: float, n_grid: int):
     return cell, frac
 
 
-KERNELS = ("bl3", "bl3_exact", "ngp", "cic", "tsc", "pcs", "pqs", "bspline6",
+KERNELS = ("bl3", "bl3q", "bl3_exact", "ngp", "cic", "tsc", "pcs", "pqs", "bspline6",
            "bspline1", "bspline2", "bspline3", "bspline4", "bspline5")
 
 
@@ -88,8 +88,10 @@ def assign(pos, charges, box: float, n_grid: int, kernel: str = "bl3"):
     """Assign charges q[c, j] of particles j to 4 periodic grids with BL3.
 
     kernel "bl3" (default) is the six-tap truncated function described below;
-    "bl3_exact" is the untruncated function (oracle.exact_bl3); the B-spline
-    kernels ("ngp" .. "bspline6") are in oracle.bspline.
+    "bl3q" is the same six-tap assignment with the quadratic-spline reading of
+    the function (oracle.bl3_quadratic); "bl3_exact" is the untruncated cubic
+    function (oracle.exact_bl3); the B-spline kernels ("ngp" .. "bspline6")
+    are in oracle.bspline.
 
     Each particle deposits q * phi(jx - fx) phi(jy - fy) phi(jz - fz) on node
     (cell + (jx, jy, jz)) mod N for every tap j in {-2..3}^3 (Eq. rawFFTed with
@@ -102,11 +104,12 @@ def assign(pos, charges, box: float, n_grid: int, kernel: str = "bl3"):
     from . import bspline
     if bspline.order_of(kernel):
         return bspline.assign(pos, charges, box, n_grid, bspline.order_of(kernel))
-    if kernel != "bl3":
+    if kernel not in ("bl3", "bl3q"):
         raise ValueError(f"unknown kernel {kernel!r}")
+    fn = bl3 if kernel == "bl3" else bl3_quadratic
     charges = np.atleast_2d(np.asarray(charges, dtype=np.float64))
     cell, frac = cell_and_fraction(pos, box, n_grid)
-    wts = [bl3.tap_weights(frac[:, a]) for a in range(3)]   # (6, n) each
+    wts = [fn.tap_weights(frac[:, a]) for a in range(3)]   # (6, n) each
     n = n_grid
     grids = np.zeros((charges.shape[0], n * n * n))
     for ix, jx in enumerate(bl3.TAPS):
@@ -245,7 +248,8 @@ def axis_tables(n_grid: int, kernel: str = "bl3"):
     from . import bspline
     if bspline.order_of(kernel):
         return bspline.axis_tables(n_grid, bspline.order_of(kernel))
-    return bl3.window_trunc(omega) ** 2, bl3.alias_sum_trunc(omega)
+    fn = bl3_quadratic if kernel == "bl3q" else bl3
+    return fn.window_trunc(omega) ** 2, fn.alias_sum_trunc(omega)
 
 
 def mode_quantities(F, mom_used, box, n_grid, haf, flags=0, kernel="bl3"):
