@@ -192,7 +192,7 @@ def resolution_study(mps, pos, vel, n_lo=N_GRID // 2):
     kn = math.pi * n_lo / BOX
     edges = kn * np.arange(33) / 32
     out = {}
-    for kernel in ("bl3", "pqs", "ngp"):
+    for kernel in ("bl3", "bl3q", "pqs", "ngp"):
         res = []
         for n in (n_lo, 2 * n_lo):
             plan = mps.Plan(n, "f32")
@@ -404,7 +404,8 @@ def main():
     if not args.no_variants:
         variants = {}
         steps_v = max(3, args.steps // 4)
-        for name, kw in (("bl3_exact_f32", {"kernel": "bl3_exact"}), ("pqs_f32", {"kernel": "pqs"}),
+        for name, kw in (("bl3_exact_f32", {"kernel": "bl3_exact"}), ("bl3q_f32", {"kernel": "bl3q"}),
+                         ("pqs_f32", {"kernel": "pqs"}),
                          ("ngp_f32", {"kernel": "ngp"}), ("mu16_f32", {"n_mu": 16})):
             _log(f"timing variant {name}")
             wall_v, _, stages_v, _ = time_path(mps, torch, pos, vel, "f32", steps_v, 1, **kw)

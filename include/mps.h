@@ -93,6 +93,17 @@ enum {
 #define MPS_KERNEL_ORDER_SHIFT 4
 #define MPS_KERNEL_BSPLINE(p) ((uint32_t)(p) << MPS_KERNEL_ORDER_SHIFT)
 
+/* The other reading of the "third-order" Battle-Lemarie function of
+ * Sec. 2.4.1, order counted as the number of polynomial coefficients: the
+ * quadratic-spline member, phi_hat(w) = sinc^3(w/2) / sqrt(A2(w)) with
+ * A2(w) = (66 + 52 cos w + 2 cos 2w) / 120, phi = sum_n c_n beta2(x - n)
+ * (knots at the half-integers).  Same six taps and support d in (-3, 3] as
+ * the default cubic reading; each tap weight is two quadratics in the
+ * fraction, split at f = 1/2.  Deconvolved by the truncated function's own
+ * window, shot terms scaled by its own alias sum.  Cannot be combined with
+ * MPS_KERNEL_BL3_EXACT. */
+#define MPS_KERNEL_BL3_QUADRATIC (7u << MPS_KERNEL_ORDER_SHIFT)
+
 /* The catalog's pos, vel and weight are host pointers: the plan copies them
  * to device workspace (28 bytes per particle, kept for reuse) on the call's
  * stream before the first kernel.  Page-locked (pinned) host memory lets the
@@ -326,11 +337,26 @@ int mps_plan_stage_times(const mps_plan* plan, double* ms, int n);
  * size are batched together.  mps_submit copies the catalog descriptor (not
  * the buffers) and returns a ticket; mps_wait blocks until the ticket is done
  * (then its mps_result is filled and its status returned) or timeout_s
- * elapses (MPS_E_TIMEOUT).  The server is thread-safe. */
+ * elapses (MPS_E_TIMEOUT).  The server is thread-safe.
+ *
+ * Ordering: `stream` is the stream on which the catalog's device buffers are
+ * produced (NULL: the null stream).  mps_submit records an event on it, and
+ * the request's kernels start only after everything enqueued on `stream`
+ * before the call has completed, so a catalog written by a kernel still in
+ * flight is never read early.  Host-resident catalogs (MPS_CATALOG_HOST)
+ * must be complete when mps_submit is called.
+ *
+ * Admission: a request runs once a worker is free and a plan of its grid
+ * size and precision with room for its particles fits the budget (idle
+ * plans are evicted least-recently-used; plans are created, grown and
+ * destroyed outside the server's lock).  Later requests may overtake a
+ * waiting one, at most 8 times; after that nothing behind it is admitted
+ * until it fits. */
 int mps_server_create(mps_server** out, size_t hbm_budget_bytes,
                       int max_inflight, int64_t small_particles);
 int mps_submit(mps_server* srv, const mps_catalog* cat, int n_grid,
-               mps_precision prec, mps_result* out, uint64_t* ticket);
+               mps_precision prec, mps_result* out, hipStream_t stream,
+               uint64_t* ticket);
 int mps_wait(mps_server* srv, uint64_t ticket, double timeout_s);
 int mps_server_destroy(mps_server* srv);
 

@@ -15,7 +15,8 @@ MPS_F32, MPS_F64 = 1, 2
 BULKFLOW_SUBTRACT, NO_SHOTNOISE, NO_DECONVOLVE, KERNEL_BL3_EXACT = 1, 2, 4, 8
 KERNEL_ORDER_SHIFT = 4
 CATALOG_HOST = 1 << 7
-KERNELS = {"bl3": 0, "bl3_exact": KERNEL_BL3_EXACT}
+KERNEL_BL3_QUADRATIC = 7 << KERNEL_ORDER_SHIFT
+KERNELS = {"bl3": 0, "bl3_exact": KERNEL_BL3_EXACT, "bl3q": KERNEL_BL3_QUADRATIC}
 # centred B-splines of order p (MPS_KERNEL_BSPLINE(p))
 for _name, _p in (("ngp", 1), ("cic", 2), ("tsc", 3), ("pcs", 4), ("pqs", 5), ("bspline6", 6)):
     KERNELS[_name] = _p << KERNEL_ORDER_SHIFT
@@ -106,7 +107,7 @@ def lib():
     }
     optional = {
         "mps_server_create": (i32, [C.POINTER(vp), C.c_size_t, i32, i64]),
-        "mps_submit": (i32, [vp, C.POINTER(Catalog), i32, i32, C.POINTER(Result), C.POINTER(C.c_uint64)]),
+        "mps_submit": (i32, [vp, C.POINTER(Catalog), i32, i32, C.POINTER(Result), vp, C.POINTER(C.c_uint64)]),
         "mps_wait": (i32, [vp, C.c_uint64, dbl]),
         "mps_server_destroy": (i32, [vp]),
     }

@@ -144,7 +144,8 @@ class Plan:
                  bulk_flow=False, no_shotnoise=False, no_deconvolve=False, kernel="bl3",
                  stream=None):
         """Binned P_pp, P_tt, Re P_dt, P_dd (x V) of one catalog; dict of arrays.
-        kernel: "bl3" (six-tap truncated BL3), "bl3_exact" (untruncated, by a
+        kernel: "bl3" (six-tap truncated BL3), "bl3q" (its quadratic-spline
+        reading, same six taps), "bl3_exact" (untruncated, by a
         cubic B-spline scatter and spectral correction), or a centred B-spline
         of order p: "ngp", "cic", "tsc", "pcs", "pqs", "bspline6" (also
         "bspline1" .. "bspline6")."""
@@ -333,14 +334,18 @@ class Server:
         self._pending = {}
 
     def submit(self, pos, vel, weight=None, *, box, haf, n_grid, precision="f32", n_bins=32,
-               k_edges=None, bulk_flow=False, no_shotnoise=False, no_deconvolve=False) -> int:
+               k_edges=None, bulk_flow=False, no_shotnoise=False, no_deconvolve=False,
+               stream=None) -> int:
+        """Queue one catalog.  Its kernels start after the work already
+        enqueued on `stream` (default: torch's current stream), the stream
+        that produced the catalog."""
         cat, keep = make_catalog(pos, vel, weight, box=box, haf=haf, n_bins=n_bins,
                                  k_edges=k_edges,
                                  flags=_flags(bulk_flow, no_shotnoise, no_deconvolve))
         res, arrays = make_result(cat.n_bins)
         ticket = C.c_uint64()
         L.check(L.lib().mps_submit(self._h, C.byref(cat), int(n_grid), _prec(precision),
-                                   C.byref(res), C.byref(ticket)), "mps_submit")
+                                   C.byref(res), _stream(stream), C.byref(ticket)), "mps_submit")
         self._pending[ticket.value] = (res, arrays, keep, cat, box, n_grid, k_edges)
         return ticket.value
 

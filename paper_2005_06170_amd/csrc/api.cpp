@@ -29,7 +29,6 @@ void dfree(void* p) {
 
 size_t real_bytes(mps_precision prec) { return prec == MPS_F64 ? 8 : 4; }
 
-int tile_for(int n, mps_precision) { return n >= 16 ? 16 : 8; }
 
 int num_cus() {
   int dev = 0, cus = 0;
@@ -39,11 +38,6 @@ int num_cus() {
   return cus;
 }
 
-int x_bin_items(int n, mps_precision prec) {
-  int b = (prec == MPS_F32 ? 8 : 4) * 512 / (n > 512 ? n : 512);
-  if (b > n / 2) b = n / 2;
-  return n * ((n / 2) / b);
-}
 
 void release(Plan* p) {
   if (!p) return;
@@ -96,7 +90,7 @@ int validate_catalog(const Plan* p, const mps_catalog* c) {
   if (c->n_bins < 1 || c->n_bins > kMaxBins) return MPS_E_ARG;
   if (c->flags & ~(15u | (7u << MPS_KERNEL_ORDER_SHIFT) | MPS_CATALOG_HOST)) return MPS_E_ARG;
   const uint32_t order = (c->flags >> MPS_KERNEL_ORDER_SHIFT) & 7u;
-  if (order > 6 || (order != 0 && (c->flags & MPS_KERNEL_BL3_EXACT))) return MPS_E_ARG;
+  if (order != 0 && (c->flags & MPS_KERNEL_BL3_EXACT)) return MPS_E_ARG;
   (void)p;
   return MPS_OK;
 }
@@ -313,11 +307,17 @@ int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec) {
       bl3_axis_tables(n_grid, &iwin2, &alias);
       // the x pass multiplies by W_t^-2 per axis
       for (double& w : iwin2) w = 1.0 / w;
+      p->tap_bound[k] = tap_bounds(p->taps[k], kernel_taps(k));
+    } else if (k == kKernelBl3Quadratic) {
+      p->taps[k] = bl3q_tap_polynomials();
+      bl3q_axis_tables(n_grid, &iwin2, &alias);
+      for (double& w : iwin2) w = 1.0 / w;
+      p->tap_bound[k] = bl3q_tap_bounds(p->taps[k]);
     } else {
       p->taps[k] = bspline_tap_polynomials(k);
       bspline_axis_tables(n_grid, k, &iwin2, &alias);
+      p->tap_bound[k] = tap_bounds(p->taps[k], kernel_taps(k));
     }
-    p->tap_bound[k] = tap_bounds(p->taps[k], kernel_taps(k));
     up = up && hipMemcpy(p->d_iwin2[k], iwin2.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) ==
                    hipSuccess;
     up = up && hipMemcpy(p->d_alias[k], alias.data(), sizeof(double) * (half + 1), hipMemcpyHostToDevice) ==

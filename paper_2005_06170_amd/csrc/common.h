@@ -49,16 +49,21 @@ struct TapPoly {
 // Assignment kernels: 0 the truncated BL3 function (6 taps, cubic pieces);
 // p = 1..6 the centred B-spline of order p (p taps, degree p - 1; order 4
 // also serves the untruncated BL3 function, whose deconvolved spectra are
-// those of the cubic B-spline).
-constexpr int kNumKernels = 7;
+// those of the cubic B-spline); 7 the quadratic-spline reading of BL3 (6
+// taps, two quadratic pieces per tap split at f = 1/2, see kDegSplit2).
+constexpr int kNumKernels = 8;
+constexpr int kKernelBl3Quadratic = 7;
 inline int kernel_id(uint32_t flags) {
   if (flags & MPS_KERNEL_BL3_EXACT) return 4;
   return static_cast<int>((flags >> MPS_KERNEL_ORDER_SHIFT) & 7u);
 }
-inline int kernel_taps(int id) { return id == 0 ? kTaps : id; }
-inline int kernel_degree(int id) { return id == 0 ? 3 : id - 1; }
-// half a cell for odd orders: taps are centred on the nearest node
-inline double kernel_shift(int id) { return (id & 1) ? 0.5 : 0.0; }
+inline int kernel_taps(int id) { return (id == 0 || id == kKernelBl3Quadratic) ? kTaps : id; }
+// half a cell for odd B-spline orders: taps are centred on the nearest node
+inline double kernel_shift(int id) { return (id != kKernelBl3Quadratic && (id & 1)) ? 0.5 : 0.0; }
+
+// Tap polynomials of the quadratic-spline BL3 reading: c[j][0..2] is the
+// weight for f < 1/2 and c[j][3..5] for f >= 1/2, both as quadratics in f.
+constexpr int kDegSplit2 = -2;
 
 // Upper bounds of |w_j(f)| over f in [0, 1) for the six taps.
 struct TapBound {
@@ -97,6 +102,12 @@ TapPoly bl3_tap_polynomials();
 TapBound tap_bounds(const TapPoly& tp, int n_taps);
 // Tap polynomials of the centred B-spline of order p = 1..6.
 TapPoly bspline_tap_polynomials(int order);
+// Quadratic-spline BL3 reading: tap polynomials in the split layout
+// (kDegSplit2), bounds of |w_j| over both pieces, and per-axis tables
+// W_t(2 pi n / N)^2 and C_t(2 pi n / N), n = 0..N/2.
+TapPoly bl3q_tap_polynomials();
+TapBound bl3q_tap_bounds(const TapPoly& tp);
+void bl3q_axis_tables(int n_grid, std::vector<double>* win2, std::vector<double>* alias);
 // 1 / sinc^(2p)(w/2) and the alias sum sum_m beta_{2p-1}(m) cos(m w) for
 // w = 2 pi n / N, n = 0..N/2.
 void bspline_axis_tables(int n_grid, int order, std::vector<double>* inv_win2, std::vector<double>* alias);
@@ -181,6 +192,15 @@ struct Plan {
 };
 
 constexpr int kMomentBlocks = 1024;
+
+// Sort/scatter tile edge for an N^3 grid.
+inline int tile_for(int n, mps_precision) { return n >= 16 ? 16 : 8; }
+// Work items of the fused x pass (ky rows times kz blocks of the pencils).
+inline int x_bin_items(int n, mps_precision prec) {
+  int b = (prec == MPS_F32 ? 8 : 4) * 512 / (n > 512 ? n : 512);
+  if (b > n / 2) b = n / 2;
+  return n * ((n / 2) / b);
+}
 
 // Estimate steps shared by the C ABI and the server (api.cpp).
 int validate_catalog(const Plan* p, const mps_catalog* c);

@@ -464,12 +464,23 @@ __global__ __launch_bounds__(256) void clear_kernel(T* __restrict__ g, int64_t n
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) g[i] = T(0);
 }
 
+// w_j(f): one polynomial of degree DEG, or (DEG == kDegSplit2) the
+// quadratic-spline BL3 reading's two quadratics, c[j][0..2] for f < 1/2 and
+// c[j][3..5] for f >= 1/2.
 template <int DEG>
 __device__ __forceinline__ double tap_weight(const TapPoly& tp, int j, double f) {
-  double v = tp.c[j][DEG];
+  if constexpr (DEG == kDegSplit2) {
+    const bool upper = f >= 0.5;
+    const double c0 = upper ? tp.c[j][3] : tp.c[j][0];
+    const double c1 = upper ? tp.c[j][4] : tp.c[j][1];
+    const double c2 = upper ? tp.c[j][5] : tp.c[j][2];
+    return (c2 * f + c1) * f + c0;
+  } else {
+    double v = tp.c[j][DEG];
 #pragma unroll
-  for (int q = DEG - 1; q >= 0; --q) v = v * f + tp.c[j][q];
-  return v;
+    for (int q = DEG - 1; q >= 0; --q) v = v * f + tp.c[j][q];
+    return v;
+  }
 }
 
 template <typename T>
@@ -1391,6 +1402,7 @@ hipError_t launch_scatter_kernel(Plan* p, const mps_catalog* c, hipStream_t s, i
     case 4: return launch_scatter_taps<4, 3, kW>(p, c, s, bulk, tp, tb);
     case 5: return launch_scatter_taps<5, 4, kW>(p, c, s, bulk, tp, tb);
     case 6: return launch_scatter_taps<6, 5, kW>(p, c, s, bulk, tp, tb);
+    case kKernelBl3Quadratic: return launch_scatter_taps<6, kDegSplit2, kW>(p, c, s, bulk, tp, tb);
     default: return launch_scatter_taps<6, 3, kW>(p, c, s, bulk, tp, tb);
   }
 }

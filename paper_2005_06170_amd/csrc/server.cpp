@@ -30,6 +30,9 @@ namespace mps {
 namespace {
 
 constexpr int kMaxBatch = 16;
+// A queued request may be passed over by later ones at most this many times;
+// after that, nothing behind it is admitted until it fits.
+constexpr int kMaxPassed = 8;
 
 struct Request {
   uint64_t ticket = 0;
@@ -39,12 +42,14 @@ struct Request {
   mps_precision prec = MPS_F32;
   mps_result* out = nullptr;
   size_t bytes = 0;           // footprint of a plan serving it
+  hipEvent_t ready = nullptr; // recorded on the submitter's stream
+  int passed = 0;             // later requests admitted while this one waited
   bool done = false;
   int status = MPS_OK;
 };
 
 struct PooledPlan {
-  mps_plan* plan = nullptr;
+  mps_plan* plan = nullptr;   // nullptr while a worker creates it
   int n_grid = 0;
   mps_precision prec = MPS_F32;
   int64_t cap = 0;            // particles reserved
@@ -54,11 +59,21 @@ struct PooledPlan {
   uint64_t last_use = 0;
 };
 
+// What a worker must do, outside the server lock, before it can run a
+// request on `pp`: destroy the evicted plans (their bytes are still counted
+// until then), then create the plan or grow its reservation.
+struct Admission {
+  PooledPlan* pp = nullptr;
+  enum { kReady, kGrow, kCreate } action = kReady;
+  int64_t cap = 0, host_cap = 0;          // reservation to make (grow, create)
+  std::vector<std::pair<mps_plan*, size_t>> victims;
+};
+
 }  // namespace
 
 struct Server {
   size_t budget = 0;
-  size_t used = 0;             // bytes held by pooled plans
+  size_t used = 0;             // bytes held by pooled plans (and dying ones)
   int max_inflight = 1;
   int64_t small = 0;
   int device = 0;
@@ -72,22 +87,33 @@ struct Server {
   std::deque<std::shared_ptr<Request>> queue;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
   std::list<PooledPlan> pool;
+  std::vector<hipEvent_t> free_events;
   std::vector<std::thread> workers;
 };
 
 namespace {
 
-// Evict idle plans (least recently used first, never `keep`) until `need`
-// more bytes fit the budget.  Returns false if running requests hold too much.
-bool make_room(Server* s, size_t need, const PooledPlan* keep) {
-  while (s->used + need > s->budget) {
+// Take idle plans (least recently used first, never `keep`) out of the pool
+// until `need` more bytes fit the budget.  Their bytes stay in s->used until
+// the caller has destroyed them outside the lock.  Returns false (and puts
+// nothing back) if running requests hold too much.
+bool make_room(Server* s, size_t need, const PooledPlan* keep, Admission* adm) {
+  size_t freed = 0;
+  std::vector<std::list<PooledPlan>::iterator> take;
+  while (s->used - freed + need > s->budget) {
     auto victim = s->pool.end();
-    for (auto it = s->pool.begin(); it != s->pool.end(); ++it)
-      if (!it->busy && &*it != keep && (victim == s->pool.end() || it->last_use < victim->last_use)) victim = it;
+    for (auto it = s->pool.begin(); it != s->pool.end(); ++it) {
+      if (it->busy || &*it == keep) continue;
+      if (std::find(take.begin(), take.end(), it) != take.end()) continue;
+      if (victim == s->pool.end() || it->last_use < victim->last_use) victim = it;
+    }
     if (victim == s->pool.end()) return false;
-    mps_plan_destroy(victim->plan);
-    s->used -= victim->bytes;
-    s->pool.erase(victim);
+    take.push_back(victim);
+    freed += victim->bytes;
+  }
+  for (auto it : take) {
+    adm->victims.emplace_back(it->plan, it->bytes);
+    s->pool.erase(it);
   }
   return true;
 }
@@ -96,17 +122,17 @@ size_t plan_bytes(int n_grid, mps_precision prec, int64_t cap, int64_t host_cap)
   return mps_footprint(n_grid, prec, cap) + kHostStageBytes * static_cast<size_t>(host_cap);
 }
 
-// An idle pooled plan of this shape with room for np particles (and, for a
-// host-resident catalog, np particles of staging): reuse one that is large
-// enough, else grow the largest idle one of the shape, else create one.
-// Called with mu held; returns nullptr if the budget cannot host it right
-// now (*status stays MPS_OK) or never can / creation failed.
-PooledPlan* acquire_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host, int* status) {
+// Under the lock: choose an idle pooled plan of this shape with room for np
+// particles (and, for a host-resident catalog, np particles of staging),
+// else one to grow, else a new one, and reserve its bytes.  Returns false if
+// the budget cannot host it right now (*status stays MPS_OK) or never can
+// (*status = MPS_E_TOOBIG).
+bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host, Admission* adm, int* status) {
   *status = MPS_OK;
   const int64_t hp = host ? np : 0;
   if (plan_bytes(n_grid, prec, np, hp) > s->budget) {
     *status = MPS_E_TOOBIG;
-    return nullptr;
+    return false;
   }
   PooledPlan* fit = nullptr;
   PooledPlan* grow = nullptr;
@@ -121,55 +147,110 @@ PooledPlan* acquire_plan(Server* s, int n_grid, mps_precision prec, int64_t np, 
   if (fit) {
     fit->busy = true;
     fit->last_use = ++s->clock;
-    return fit;
+    adm->pp = fit;
+    adm->action = Admission::kReady;
+    return true;
   }
   if (grow) {
     const int64_t cap = std::max(grow->cap, np), hcap = std::max(grow->host_cap, hp);
     const size_t need = plan_bytes(n_grid, prec, cap, hcap);
-    if (!make_room(s, need - grow->bytes, grow)) return nullptr;
-    int st = mps_plan_reserve(grow->plan, cap);
-    if (st == MPS_OK && hcap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(grow->plan), hcap);
-    if (st != MPS_OK) {
-      *status = st;
-      return nullptr;
-    }
+    if (!make_room(s, need - grow->bytes, grow, adm)) return false;
+    adm->pp = grow;
+    adm->action = Admission::kGrow;
+    adm->cap = cap;
+    adm->host_cap = hcap;
     s->used += need - grow->bytes;
     grow->bytes = need;
-    grow->cap = cap;
-    grow->host_cap = hcap;
     grow->busy = true;
     grow->last_use = ++s->clock;
-    return grow;
+    return true;
   }
   const size_t need = plan_bytes(n_grid, prec, np, hp);
-  if (!make_room(s, need, nullptr)) return nullptr;
-  mps_plan* plan = nullptr;
-  int st = mps_plan_create(&plan, n_grid, prec);
-  if (st == MPS_OK) st = mps_plan_reserve(plan, np);
-  if (st == MPS_OK && hp > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(plan), hp);
-  if (st != MPS_OK) {
-    if (plan) mps_plan_destroy(plan);
-    *status = st;
-    return nullptr;
-  }
+  if (!make_room(s, need, nullptr, adm)) return false;
   PooledPlan pp;
-  pp.plan = plan;
   pp.n_grid = n_grid;
   pp.prec = prec;
-  pp.cap = np;
-  pp.host_cap = hp;
   pp.bytes = need;
   pp.busy = true;
   pp.last_use = ++s->clock;
   s->used += need;
   s->pool.push_back(pp);
-  return &s->pool.back();
+  adm->pp = &s->pool.back();
+  adm->action = Admission::kCreate;
+  adm->cap = np;
+  adm->host_cap = hp;
+  return true;
+}
+
+// Outside the lock: destroy the victims, then create or grow the plan.
+// Re-locks to settle the byte counts; returns the status of the reservation.
+int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
+  lk.unlock();
+  size_t freed = 0;
+  for (auto& v : adm->victims) {
+    mps_plan_destroy(v.first);
+    freed += v.second;
+  }
+  int st = MPS_OK;
+  PooledPlan* pp = adm->pp;
+  mps_plan* created = nullptr;
+  if (adm->action == Admission::kCreate) {
+    st = mps_plan_create(&created, pp->n_grid, pp->prec);
+    if (st == MPS_OK) st = mps_plan_reserve(created, adm->cap);
+    if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(created), adm->host_cap);
+    if (st != MPS_OK && created) {
+      mps_plan_destroy(created);
+      created = nullptr;
+    }
+  } else if (adm->action == Admission::kGrow) {
+    st = mps_plan_reserve(pp->plan, adm->cap);
+    if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(pp->plan), adm->host_cap);
+  }
+  lk.lock();
+  s->used -= freed;
+  if (adm->action == Admission::kCreate) {
+    if (st == MPS_OK) {
+      pp->plan = created;
+      pp->cap = adm->cap;
+      pp->host_cap = adm->host_cap;
+    } else {
+      s->used -= pp->bytes;
+      for (auto it = s->pool.begin(); it != s->pool.end(); ++it)
+        if (&*it == pp) {
+          s->pool.erase(it);
+          break;
+        }
+      adm->pp = nullptr;
+    }
+  } else if (adm->action == Admission::kGrow) {
+    if (st == MPS_OK) {
+      pp->cap = adm->cap;
+      pp->host_cap = adm->host_cap;
+    } else {  // a failed reservation may have dropped part of the old one
+      mps_plan* dead = pp->plan;
+      s->used -= pp->bytes;
+      for (auto it = s->pool.begin(); it != s->pool.end(); ++it)
+        if (&*it == pp) {
+          s->pool.erase(it);
+          break;
+        }
+      adm->pp = nullptr;
+      lk.unlock();
+      mps_plan_destroy(dead);
+      lk.lock();
+    }
+  }
+  if (freed > 0 || st != MPS_OK) s->cv_work.notify_all();
+  return st;
 }
 
 void finish(Server* s, const std::shared_ptr<Request>& r, int status) {
   r->status = status;
   r->done = true;
-  (void)s;
+  if (r->ready) {
+    s->free_events.push_back(r->ready);
+    r->ready = nullptr;
+  }
 }
 
 void worker_main(Server* s) {
@@ -179,45 +260,51 @@ void worker_main(Server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     std::vector<std::shared_ptr<Request>> batch;
-    std::vector<PooledPlan*> plans;
-    // admit: the oldest request that fits; small requests pull same-shape peers
+    std::vector<Admission> adms;
+    // admit: the oldest request that fits, unless an older one has been
+    // passed over kMaxPassed times; small requests pull same-shape peers
     while (batch.empty()) {
       if (s->stop && s->queue.empty()) {
         lk.unlock();
         if (stream) (void)hipStreamDestroy(stream);
         return;
       }
-      for (auto it = s->queue.begin(); it != s->queue.end();) {
+      size_t pos = 0;
+      for (auto it = s->queue.begin(); it != s->queue.end(); ++pos) {
         const auto r = *it;
         int st = MPS_OK;
-        PooledPlan* pp = acquire_plan(s, r->n_grid, r->prec, r->cat.n_particles,
-                                      (r->cat.flags & MPS_CATALOG_HOST) != 0, &st);
-        if (!pp && st != MPS_OK) {  // can never run (too big, or creation failed)
-          it = s->queue.erase(it);
-          finish(s, r, st);
-          s->cv_done.notify_all();
-          continue;
-        }
-        if (!pp) {
+        Admission adm;
+        if (!admit_plan(s, r->n_grid, r->prec, r->cat.n_particles, (r->cat.flags & MPS_CATALOG_HOST) != 0, &adm,
+                        &st)) {
+          if (st != MPS_OK) {  // can never run
+            it = s->queue.erase(it);
+            finish(s, r, st);
+            s->cv_done.notify_all();
+            continue;
+          }
+          if (r->passed >= kMaxPassed) break;  // its turn: wait until it fits
           ++it;
           continue;
         }
+        // every older request still queued has been passed over once more
+        for (auto jt = s->queue.begin(); jt != it; ++jt) ++(*jt)->passed;
         batch.push_back(r);
-        plans.push_back(pp);
+        adms.push_back(std::move(adm));
         it = s->queue.erase(it);
         if (r->cat.n_particles <= s->small) {
-          for (auto jt = s->queue.begin(); jt != s->queue.end() && batch.size() < kMaxBatch;) {
+          for (auto jt = it; jt != s->queue.end() && batch.size() < kMaxBatch;) {
             const auto q = *jt;
             if (q->n_grid != r->n_grid || q->prec != r->prec || q->cat.n_particles > s->small) {
               ++jt;
               continue;
             }
             int st2 = MPS_OK;
-            PooledPlan* p2 = acquire_plan(s, q->n_grid, q->prec, q->cat.n_particles,
-                                          (q->cat.flags & MPS_CATALOG_HOST) != 0, &st2);
-            if (!p2) break;
+            Admission a2;
+            if (!admit_plan(s, q->n_grid, q->prec, q->cat.n_particles, (q->cat.flags & MPS_CATALOG_HOST) != 0,
+                            &a2, &st2))
+              break;
             batch.push_back(q);
-            plans.push_back(p2);
+            adms.push_back(std::move(a2));
             jt = s->queue.erase(jt);
           }
         }
@@ -225,13 +312,21 @@ void worker_main(Server* s) {
       }
       if (batch.empty()) s->cv_work.wait(lk);
     }
+    // plan creation, growth and eviction run outside the lock
+    std::vector<int> status(batch.size(), MPS_OK);
+    for (size_t i = 0; i < batch.size(); ++i)
+      if (!adms[i].victims.empty() || adms[i].action != Admission::kReady) status[i] = carry_out(s, &adms[i], lk);
     lk.unlock();
 
-    // run the batch: all stages enqueued back to back, one synchronisation
-    std::vector<int> status(batch.size(), MPS_OK);
+    // run the batch: each request's stages start after its catalog is ready
+    // on the submitter's stream; all are enqueued back to back, one
+    // synchronisation
     for (size_t i = 0; i < batch.size(); ++i) {
-      Plan* p = reinterpret_cast<Plan*>(plans[i]->plan);
-      int st = ensure_bins(p, &batch[i]->cat);
+      if (status[i] != MPS_OK) continue;
+      Plan* p = reinterpret_cast<Plan*>(adms[i].pp->plan);
+      int st = MPS_OK;
+      if (batch[i]->ready && hipStreamWaitEvent(stream, batch[i]->ready, 0) != hipSuccess) st = MPS_E_HIP;
+      if (st == MPS_OK) st = ensure_bins(p, &batch[i]->cat);
       if (st == MPS_OK) st = ensure_particles(p, batch[i]->cat.n_particles);
       if (st == MPS_OK) st = enqueue_estimate(p, &batch[i]->cat, stream);
       status[i] = st;
@@ -239,13 +334,13 @@ void worker_main(Server* s) {
     const bool synced = hipStreamSynchronize(stream) == hipSuccess;
     for (size_t i = 0; i < batch.size(); ++i) {
       if (status[i] == MPS_OK)
-        status[i] = synced ? unpack(reinterpret_cast<Plan*>(plans[i]->plan), &batch[i]->cat, batch[i]->out)
+        status[i] = synced ? unpack(reinterpret_cast<Plan*>(adms[i].pp->plan), &batch[i]->cat, batch[i]->out)
                            : MPS_E_HIP;
     }
 
     lk.lock();
     for (size_t i = 0; i < batch.size(); ++i) {
-      plans[i]->busy = false;
+      if (adms[i].pp) adms[i].pp->busy = false;
       finish(s, batch[i], status[i]);
     }
     s->cv_done.notify_all();
@@ -290,7 +385,7 @@ int mps_server_create(mps_server** out, size_t hbm_budget_bytes, int max_infligh
 }
 
 int mps_submit(mps_server* srv, const mps_catalog* cat, int n_grid, mps_precision prec, mps_result* out,
-               uint64_t* ticket) {
+               hipStream_t stream, uint64_t* ticket) {
   if (!srv || !cat || !out || !ticket) return MPS_E_ARG;
   Server* s = reinterpret_cast<Server*>(srv);
   if (n_grid < 8 || n_grid > 1024 || (n_grid & (n_grid - 1)) || (prec != MPS_F32 && prec != MPS_F64))
@@ -312,6 +407,20 @@ int mps_submit(mps_server* srv, const mps_catalog* cat, int n_grid, mps_precisio
     if (s->stop) return MPS_E_ARG;
     if (r->bytes > s->budget) return MPS_E_TOOBIG;
     if (s->queue.size() >= 4096) return MPS_E_BUSY;
+    // the request's kernels wait for what is already enqueued on `stream`
+    // (the producer of the catalog)
+    if (!s->free_events.empty()) {
+      r->ready = s->free_events.back();
+      s->free_events.pop_back();
+    } else if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess) {
+      r->ready = nullptr;
+      return MPS_E_HIP;
+    }
+    if (hipEventRecord(r->ready, stream) != hipSuccess) {
+      s->free_events.push_back(r->ready);
+      r->ready = nullptr;
+      return MPS_E_HIP;
+    }
     r->ticket = s->next_ticket++;
     s->queue.push_back(r);
     s->tickets[r->ticket] = r;
@@ -346,7 +455,9 @@ int mps_server_destroy(mps_server* srv) {
   }
   s->cv_work.notify_all();
   for (auto& t : s->workers) t.join();
-  for (auto& pp : s->pool) mps_plan_destroy(pp.plan);
+  for (auto& pp : s->pool)
+    if (pp.plan) mps_plan_destroy(pp.plan);
+  for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
   delete s;
   return MPS_OK;
 }

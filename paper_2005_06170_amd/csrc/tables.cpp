@@ -261,6 +261,118 @@ void bl3_axis_tables(int n_grid, std::vector<double>* win2, std::vector<double>*
   }
 }
 
+// ------------------------------------------------ quadratic-spline reading
+// phi(x) = sum_n c_n beta2(x - n), c_n the Fourier coefficients of
+// A2(w)^(-1/2), A2(w) = (66 + 52 cos w + 2 cos 2w) / 120 (the alias sum of
+// |beta2_hat|^2).  With s = x - m in [-1/2, 1/2] only n = m - 1, m, m + 1
+// contribute: phi = c_m (3/4 - s^2) + c_{m-1} (1/2 - s)^2 / 2
+// + c_{m+1} (1/2 + s)^2 / 2.
+namespace {
+
+constexpr int kFilterHalf2 = 48;  // |c_48| ~ 3e-18
+
+std::vector<double> filter_coefficients2() {
+  std::vector<double> c(kFilterHalf2 + 1, 0.0);
+  for (int k = 0; k < kTrapezoid; ++k) {
+    const double w = 2.0 * M_PI * k / kTrapezoid;
+    const double g = 1.0 / std::sqrt((66.0 + 52.0 * std::cos(w) + 2.0 * std::cos(2.0 * w)) / 120.0);
+    for (int n = 0; n <= kFilterHalf2; ++n) c[n] += g * std::cos(n * w);
+  }
+  for (double& v : c) v /= kTrapezoid;
+  return c;
+}
+
+double cn2(const std::vector<double>& c, int n) {
+  n = n < 0 ? -n : n;
+  return n <= kFilterHalf2 ? c[n] : 0.0;
+}
+
+// phi on [m - 1/2, m + 1/2] as a quadratic in s = x - m: coefficients of
+// 1, s, s^2.
+void piece2(const std::vector<double>& c, int m, double out[3]) {
+  const double a = cn2(c, m - 1), b = cn2(c, m), d = cn2(c, m + 1);
+  out[0] = 0.75 * b + 0.125 * a + 0.125 * d;
+  out[1] = -0.5 * a + 0.5 * d;
+  out[2] = -b + 0.5 * a + 0.5 * d;
+}
+
+double phi2(const std::vector<double>& c, double x) {
+  const int m = static_cast<int>(std::floor(x + 0.5));
+  double a[3];
+  piece2(c, m, a);
+  const double s = x - m;
+  return (a[2] * s + a[1]) * s + a[0];
+}
+
+}  // namespace
+
+TapPoly bl3q_tap_polynomials() {
+  const std::vector<double> c = filter_coefficients2();
+  TapPoly tp{};
+  for (int t = 0; t < kTaps; ++t) {
+    const int j = t + kTapLo;
+    double a[3];
+    // f < 1/2: x = j - f lies in [j - 1/2, j], s = -f
+    piece2(c, j, a);
+    tp.c[t][0] = a[0];
+    tp.c[t][1] = -a[1];
+    tp.c[t][2] = a[2];
+    // f >= 1/2: x = j - f lies in (j - 1, j - 1/2], s = 1 - f
+    piece2(c, j - 1, a);
+    tp.c[t][3] = a[0] + a[1] + a[2];
+    tp.c[t][4] = -a[1] - 2.0 * a[2];
+    tp.c[t][5] = a[2];
+  }
+  return tp;
+}
+
+TapBound bl3q_tap_bounds(const TapPoly& tp) {
+  TapBound b;
+  for (int j = 0; j < kTaps; ++j) {
+    double m = 0.0;
+    for (int h = 0; h < 2; ++h) {
+      const double* q = tp.c[j] + 3 * h;
+      const double lo = 0.5 * h, hi = 0.5 * h + 0.5;
+      double cand[3] = {lo, hi, -1.0};
+      if (q[2] != 0.0) cand[2] = -q[1] / (2.0 * q[2]);
+      for (double f : cand) {
+        if (f < lo || f > hi) continue;
+        m = std::max(m, std::fabs((q[2] * f + q[1]) * f + q[0]));
+      }
+    }
+    b.k[j] = static_cast<float>(m * 1.0001);
+  }
+  return b;
+}
+
+void bl3q_axis_tables(int n_grid, std::vector<double>* win2, std::vector<double>* alias) {
+  const std::vector<double> c = filter_coefficients2();
+  std::vector<double> gx, gw;
+  gauss_legendre(16, &gx, &gw);
+  // phi_t on (-3, 3] integrated over the half-unit pieces [h/2 - 3, h/2 - 5/2]
+  auto integrate = [&](auto&& f, double lo, double hi) {
+    double acc = 0.0;
+    const int pieces = static_cast<int>(std::lround(2.0 * (hi - lo)));
+    for (int i = 0; i < pieces; ++i)
+      for (size_t k = 0; k < gx.size(); ++k) acc += 0.5 * gw[k] * f(lo + 0.5 * (i + gx[k]));
+    return acc;
+  };
+  double a[6];
+  for (int s = 0; s < 6; ++s)
+    a[s] = integrate([&](double x) { return phi2(c, x) * phi2(c, x + s); }, -3.0, 3.0 - s);
+  const int half = n_grid / 2;
+  win2->assign(half + 1, 0.0);
+  alias->assign(half + 1, 0.0);
+  for (int n = 0; n <= half; ++n) {
+    const double w = 2.0 * M_PI * n / n_grid;
+    const double wt = integrate([&](double x) { return phi2(c, x) * std::cos(w * x); }, -3.0, 3.0);
+    (*win2)[n] = wt * wt;
+    double cs = a[0];
+    for (int s = 1; s < 6; ++s) cs += 2.0 * a[s] * std::cos(s * w);
+    (*alias)[n] = cs;
+  }
+}
+
 std::vector<double> twiddles(int n_grid) {
   std::vector<double> t(2 * n_grid);
   for (int m = 0; m < n_grid; ++m) {

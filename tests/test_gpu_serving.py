@@ -1,8 +1,11 @@
-"""Batched and served estimates equal the same catalogs estimated alone.
+"""Batched and served estimates equal the same catalogs estimated alone,
+and the oracle's spectra.
 
 The batch entry point and the continuous-batching server run the same
 kernels as mps_estimate; results may differ only by the order of the
 scatter's global atomic adds (FP32 grids), far below the parity tolerance.
+Five of the pool's catalogs (the ones the oracle estimates in seconds) are
+also compared with oracle.estimate, in the batch and in the served mix.
 """
 import threading
 
@@ -10,8 +13,13 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from synth import catalogs
-from gpu_common import guarded_rel
+from gpu_common import compare_spectra, guarded_rel
+
+TOL = {"f64": 1e-5, "f32": 3e-4}
+# pool entries small enough for the oracle
+ORACLE_CHECKED = (0, 1, 3, 4, 7)
 
 pytestmark = pytest.mark.gpu
 
@@ -35,8 +43,19 @@ def _pool():
         else:
             pos, vel = catalogs.zeldovich(n, box, 3.0 * box / 1000.0, seed=catalogs.seed_for(4, i))
         out.append(dict(pos=torch.from_numpy(pos).cuda(), vel=torch.from_numpy(vel).cuda(),
-                        box=box, haf=50.0, n_bins=24, grid=grid, prec=prec))
+                        box=box, haf=50.0, n_bins=24, grid=grid, prec=prec, host=(pos, vel)))
     return out
+
+
+@pytest.fixture(scope="module")
+def pool_oracle():
+    pool = _pool()
+    want = {}
+    for i in ORACLE_CHECKED:
+        c = pool[i]
+        print(f"oracle for pool catalog {i}: {c['host'][0].shape[0]} particles, {c['grid']}^3", flush=True)
+        want[i] = oracle.estimate(*c["host"], box=c["box"], n_grid=c["grid"], haf=c["haf"], n_bins=c["n_bins"])
+    return pool, want
 
 
 def _same(a, b, tol):
@@ -53,18 +72,20 @@ def _alone(mps, c):
                                                    n_bins=c["n_bins"])
 
 
-def test_batch_equals_alone(mps):
-    pool = _pool()
+def test_batch_equals_alone(mps, pool_oracle):
+    pool, want = pool_oracle
     alone = [_alone(mps, c) for c in pool]
     plans = [mps.Plan(c["grid"], c["prec"]) for c in pool]
     cats = [dict(pos=c["pos"], vel=c["vel"], box=c["box"], haf=c["haf"], n_bins=c["n_bins"]) for c in pool]
     batch = mps.estimate_batch(plans, cats)
     for a, b, c in zip(batch, alone, pool):
         _same(a, b, 1e-6 if c["prec"] == "f32" else 1e-12)
+    for i in ORACLE_CHECKED:
+        compare_spectra(batch[i], want[i], TOL[pool[i]["prec"]], f"batch catalog {i}")
 
 
-def test_server_mix_equals_alone(mps):
-    pool = _pool()
+def test_server_mix_equals_alone(mps, pool_oracle):
+    pool, want = pool_oracle
     alone = [_alone(mps, c) for c in pool]
     srv = mps.Server(hbm_budget_bytes=24 << 30, max_inflight=3, small_particles=400_000)
     order = list(range(len(pool))) * 3
@@ -92,6 +113,35 @@ def test_server_mix_equals_alone(mps):
         got = srv.wait(t, timeout_s=120.0)
         c = pool[order[j]]
         _same(got, alone[order[j]], 1e-6 if c["prec"] == "f32" else 1e-12)
+        if order[j] in ORACLE_CHECKED:
+            compare_spectra(got, want[order[j]], TOL[c["prec"]], f"served catalog {order[j]}")
+    srv.close()
+
+
+def test_server_waits_for_the_producing_stream(mps):
+    """A catalog written on a side stream by work still in flight at submit
+    time: the request's kernels wait for that stream (mps_submit records an
+    event on it), so the result equals the estimate of the finished catalog."""
+    pos, vel = catalogs.uniform_gaussian(400_000, 500.0, 300.0, seed=catalogs.seed_for(4, 50))
+    src_p, src_v = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
+    want = mps.Plan(64, "f32").estimate(src_p, src_v, box=500.0, haf=50.0, n_bins=16)
+    srv = mps.Server(hbm_budget_bytes=4 << 30, max_inflight=2)
+    side = torch.cuda.Stream()
+    a = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    for rep in range(3):
+        dst_p = torch.zeros_like(src_p)
+        dst_v = torch.zeros_like(src_v)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            for _ in range(8):           # keep the side stream busy first
+                a = torch.tanh(a @ a * 1e-3)
+            dst_p.copy_(src_p)
+            dst_v.copy_(src_v)
+            t = srv.submit(dst_p, dst_v, box=500.0, haf=50.0, n_grid=64, n_bins=16, stream=side)
+        got = srv.wait(t, timeout_s=120.0)
+        torch.cuda.synchronize()
+        _same(got, want, 1e-6)
     srv.close()
 
 
