@@ -114,7 +114,10 @@ def test_kernel_flags_are_validated(mps):
     pos, vel = catalogs.uniform_gaussian(100, BOX, seed=catalogs.seed_for(6, 50))
     p, v = _dev(pos, vel)
     plan = mps.Plan(8, "f32")
-    for flags in (L.KERNEL_BL3_EXACT | (2 << L.KERNEL_ORDER_SHIFT), 7 << L.KERNEL_ORDER_SHIFT, 1 << 8):
+    # order 7 of the kernel field is the quadratic BL3 reading, valid on its
+    # own but not with the exact kernel
+    for flags in (L.KERNEL_BL3_EXACT | (2 << L.KERNEL_ORDER_SHIFT), L.KERNEL_BL3_EXACT | L.KERNEL_BL3_QUADRATIC,
+                  1 << 8):
         cat, keep = make_catalog(p, v, box=BOX, haf=HAF, flags=flags)
         res, _ = make_result(cat.n_bins)
         st = L.lib().mps_estimate(plan.handle, C.byref(cat), C.byref(res),
