@@ -60,7 +60,8 @@ extern "C" {
 #define MPS_E_HIP (-5)        /* a HIP runtime call failed */
 #define MPS_E_TIMEOUT (-6)    /* mps_wait timed out */
 #define MPS_E_BUSY (-7)       /* the server queue is full */
-#define MPS_E_TOOBIG (-8)     /* request can never fit the server's budget */
+#define MPS_E_TOOBIG (-8)     /* request can never fit the server's budget,
+                                 or exceeds the static workspace */
 
 #define MPS_MAX_BINS 128
 
@@ -359,6 +360,25 @@ int mps_submit(mps_server* srv, const mps_catalog* cat, int n_grid,
                uint64_t* ticket);
 int mps_wait(mps_server* srv, uint64_t ticket, double timeout_s);
 int mps_server_destroy(mps_server* srv);
+
+/* The estimate of mps_estimate with no device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  No plan: every buffer a plan would own
+ * lives in a fixed workspace, a file-scope device array of the library
+ * (about 43 MB, held on each GPU the call runs on until the process ends).
+ * Limits: n_grid a power of two in [8, MPS_STATIC_MAX_GRID] and at most
+ * MPS_STATIC_MAX_PARTICLES particles, else MPS_E_TOOBIG; device-resident
+ * catalogs only (MPS_CATALOG_HOST gives MPS_E_ARG); every other argument,
+ * flag and error as mps_estimate.  Enqueues on `stream` and returns after the
+ * results are copied back.  All calls on one GPU share the workspace, which
+ * keeps the last call's contents (every stage clears what it accumulates
+ * into): the host side is serialised, but calls whose work overlaps on the
+ * device, on different streams, race.  Host-side tables are rebuilt only
+ * when the grid size, precision, kernel or bins change. */
+#define MPS_STATIC_MAX_GRID 64
+#define MPS_STATIC_MAX_PARTICLES (1 << 20)
+int mps_estimate_static(const mps_catalog* cat, int n_grid, mps_precision prec,
+                        mps_result* out, hipStream_t stream);
 
 const char* mps_strerror(int status);
 

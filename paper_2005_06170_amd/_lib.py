@@ -23,6 +23,8 @@ for _name, _p in (("ngp", 1), ("cic", 2), ("tsc", 3), ("pcs", 4), ("pqs", 5), ("
 for _p in range(1, 7):
     KERNELS[f"bspline{_p}"] = _p << KERNEL_ORDER_SHIFT
 MAX_BINS = 128
+STATIC_MAX_GRID = 64              # MPS_STATIC_MAX_GRID
+STATIC_MAX_PARTICLES = 1 << 20    # MPS_STATIC_MAX_PARTICLES
 NUM_STAGES = 9
 STAGES = ("moments+count", "scan", "permute", "clear", "scatter",
           "fft_z", "fft_y", "fft_x+bin", "finalize")
@@ -104,6 +106,7 @@ def lib():
         "mps_plan_set_timing": (i32, [vp, i32]),
         "mps_plan_stage_times": (i32, [vp, C.POINTER(dbl), i32]),
         "mps_strerror": (C.c_char_p, [i32]),
+        "mps_estimate_static": (i32, [C.POINTER(Catalog), i32, i32, C.POINTER(Result), vp]),
     }
     optional = {
         "mps_server_create": (i32, [C.POINTER(vp), C.c_size_t, i32, i64]),
@@ -142,5 +145,5 @@ def exported_symbols():
              "mps_estimate", "mps_estimate_batch", "mps_estimate_mu", "mps_estimate_subcubes",
              "mps_spt_one_loop", "mps_assign", "mps_fft",
              "mps_plan_set_timing", "mps_plan_stage_times", "mps_server_create",
-             "mps_submit", "mps_wait", "mps_server_destroy", "mps_strerror"]
+             "mps_submit", "mps_wait", "mps_server_destroy", "mps_strerror", "mps_estimate_static"]
     return {n: hasattr(L, n) for n in names}

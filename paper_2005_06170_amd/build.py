@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmps.so")
-SOURCES = ["particles.hip", "fft.hip", "subcubes.hip", "spt.hip", "api.cpp", "tables.cpp", "server.cpp"]
+SOURCES = ["particles.hip", "fft.hip", "subcubes.hip", "spt.hip", "static_ws.hip", "api.cpp", "tables.cpp",
+           "server.cpp"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -769,7 +769,7 @@ const char* mps_strerror(int status) {
     case MPS_E_HIP: return "HIP runtime error";
     case MPS_E_TIMEOUT: return "timed out";
     case MPS_E_BUSY: return "server queue full";
-    case MPS_E_TOOBIG: return "request exceeds the server's memory budget";
+    case MPS_E_TOOBIG: return "request exceeds the server's memory budget or the static workspace";
   }
   return "unknown status";
 }
