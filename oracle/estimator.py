@@ -252,19 +252,22 @@ def axis_tables(n_grid: int, kernel: str = "bl3"):
     return fn.window_trunc(omega) ** 2, fn.alias_sum_trunc(omega)
 
 
-def mode_quantities(F, mom_used, box, n_grid, haf, flags=0, kernel="bl3"):
+def mode_quantities(F, mom_used, box, n_grid, haf, flags=0, kernel="bl3", xs=None):
     """Per-mode estimator values over the full N^3 cube.
 
     Returns a dict of arrays with shape (N, N, N): integer n2, |k|, and the
     deconvolved, shot-subtracted P_dd, P_pp, P_tt, Re P_dt plus the shot terms.
+    With xs (a slice of x indices, for grids too large to hold every per-mode
+    array at once) only the modes F[:, xs] are evaluated, shape (len, N, N).
     """
     n = n_grid
     W = mom_used["W"]
-    delta = F[0] / W
-    p = F[1:4] / W
+    xs = slice(None) if xs is None else xs
+    delta = F[0, xs] / W
+    p = F[1:4, xs] / W
     nf = _integer_freqs(n)
     kf = 2.0 * math.pi / box
-    nx, ny, nz = np.meshgrid(nf, nf, nf, indexing="ij")
+    nx, ny, nz = np.meshgrid(nf[xs], nf, nf, indexing="ij")
     kvec = kf * np.stack([nx, ny, nz]).astype(np.float64)
     n2 = nx * nx + ny * ny + nz * nz
     kmag = kf * np.sqrt(n2.astype(np.float64))
@@ -272,8 +275,8 @@ def mode_quantities(F, mom_used, box, n_grid, haf, flags=0, kernel="bl3"):
     w1, c1 = axis_tables(n, kernel)
     if flags & FLAG_NO_DECONVOLVE:
         w1 = np.ones(n)
-    win2 = w1[:, None, None] * w1[None, :, None] * w1[None, None, :]
-    calias = c1[:, None, None] * c1[None, :, None] * c1[None, None, :]
+    win2 = w1[xs, None, None] * w1[None, :, None] * w1[None, None, :]
+    calias = c1[xs, None, None] * c1[None, :, None] * c1[None, None, :]
 
     s_dd = mom_used["W2"] / W ** 2
     s_ab = mom_used["s2vv"] / W ** 2
@@ -299,8 +302,12 @@ def mode_quantities(F, mom_used, box, n_grid, haf, flags=0, kernel="bl3"):
             "delta": delta, "p": p, "theta": theta}
 
 
-def bin_modes(q, box, n_grid, k_edges=None, n_bins=32):
-    """Average per-mode quantities in |k| shells; multiply by V = L^3."""
+BINNED = ("kmag", "p_pp", "p_tt", "p_dt", "p_dd", "sn_pp", "sn_tt", "sn_dd")
+
+
+def bin_sums(q, box, n_grid, k_edges=None, n_bins=32):
+    """Mode counts and sums of the per-mode quantities in |k| shells.
+    Returns (edges, counts, {name: sums})."""
     n = n_grid
     kf = 2.0 * math.pi / box
     k_nyq = kf * (n // 2)
@@ -314,21 +321,27 @@ def bin_modes(q, box, n_grid, k_edges=None, n_bins=32):
     sel = idx >= 0
     b = idx[sel]
     counts = np.bincount(b, minlength=n_bins).astype(np.int64)
+    sums = {key: np.bincount(b, weights=q[key][sel], minlength=n_bins) for key in BINNED}
+    return edges, counts, sums
+
+
+def bin_means(edges, counts, sums, box):
+    """Shell means from bin_sums; spectra multiplied by V = L^3."""
     vol = box ** 3
 
-    def mean_of(arr, scale):
-        s = np.bincount(b, weights=arr[sel], minlength=n_bins)
+    def mean_of(s, scale):
         with np.errstate(invalid="ignore", divide="ignore"):
             return np.where(counts > 0, scale * s / counts, np.nan)
 
-    return {
-        "k_edges": edges, "n_modes": counts,
-        "k_mean": mean_of(q["kmag"], 1.0),
-        "p_pp": mean_of(q["p_pp"], vol), "p_tt": mean_of(q["p_tt"], vol),
-        "p_dt": mean_of(q["p_dt"], vol), "p_dd": mean_of(q["p_dd"], vol),
-        "sn_pp": mean_of(q["sn_pp"], vol), "sn_tt": mean_of(q["sn_tt"], vol),
-        "sn_dd": mean_of(q["sn_dd"], vol),
-    }
+    out = {"k_edges": edges, "n_modes": counts, "k_mean": mean_of(sums["kmag"], 1.0)}
+    for key in BINNED[1:]:
+        out[key] = mean_of(sums[key], vol)
+    return out
+
+
+def bin_modes(q, box, n_grid, k_edges=None, n_bins=32):
+    """Average per-mode quantities in |k| shells; multiply by V = L^3."""
+    return bin_means(*bin_sums(q, box, n_grid, k_edges, n_bins), box)
 
 
 def estimate(pos, vel, weight=None, *, box, n_grid, haf, k_edges=None,

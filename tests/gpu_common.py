@@ -1,5 +1,11 @@
 """Helpers shared by the GPU parity tests."""
+import hashlib
+import json
+import os
+
 import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def guarded_rel(gpu, orc, sn):
@@ -63,3 +69,40 @@ def compare_mu(g, o, tol, label=""):
     bad = {k: v for k, v in errs.items() if not v <= tol}
     assert not bad, (label, errs)
     return errs
+
+
+def load_reference(name):
+    with open(os.path.join(HERE, "golden", name)) as f:
+        return json.load(f)
+
+
+class RefSpectra:
+    """Attribute view of a stored spectrum (null -> NaN), as compare_spectra expects."""
+
+    def __init__(self, d):
+        for k, v in d.items():
+            if k == "n_modes":
+                setattr(self, k, np.asarray(v, dtype=np.int64))
+            elif isinstance(v, list):
+                setattr(self, k, np.array([np.nan if x is None else x for x in v], dtype=np.float64))
+            else:
+                setattr(self, k, v)
+
+
+def check_fingerprint(pos, vel, fp):
+    """The regenerated catalog is the recorded one: same size, FP64 velocity
+    moments and mean position (to rounding), and usually the same bytes."""
+    assert pos.shape[0] == fp["n_particles"]
+    v = vel.astype(np.float64)
+    sv = v.sum(axis=0)
+    svv = (v.T @ v).ravel()
+    scale = np.sqrt(np.abs(np.array(fp["sum_vv"])[[0, 4, 8]]).sum() * pos.shape[0])
+    assert np.all(np.abs(sv - fp["sum_v"]) <= 1e-6 * scale), (sv, fp["sum_v"])
+    assert np.allclose(svv, fp["sum_vv"], rtol=1e-9, atol=0), (svv, fp["sum_vv"])
+    assert np.allclose(np.mean(pos.astype(np.float64), axis=0), fp["mean_pos"], rtol=1e-9, atol=1e-9)
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(pos).tobytes())
+    h.update(np.ascontiguousarray(vel).tobytes())
+    same = h.hexdigest() == fp["sha256"]
+    print("catalog bytes identical to the reference's:", same, flush=True)
+    return same
