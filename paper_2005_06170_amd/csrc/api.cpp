@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -140,45 +141,50 @@ void mark(Plan* p, int i, hipStream_t s) {
   if (p->timing) (void)hipEventRecord(p->ev[i], s);
 }
 
-// Stages up to (and including) the scatter; `bulk_grid` deposits v - v_b.
-// A host-resident catalog is first copied to the plan's staging buffer.
-int enqueue_particles(Plan* p, const mps_catalog* c0, hipStream_t s, int bulk_grid) {
-  mps_catalog staged;
-  const mps_catalog* c = c0;
+// Stages before the scatter: moments, tile sort and the grid clear.  A
+// host-resident catalog is first copied to the plan's staging buffer; *used
+// receives the catalog the later particle stages read.
+int enqueue_prescatter(Plan* p, const mps_catalog* c0, hipStream_t s, mps_catalog* used) {
+  *used = *c0;
   if (c0->flags & MPS_CATALOG_HOST) {
     const int st = ensure_host_stage(p, c0->n_particles);
     if (st != MPS_OK) return st;
     const size_t n = static_cast<size_t>(c0->n_particles);
-    staged = *c0;
-    staged.flags &= ~MPS_CATALOG_HOST;
-    staged.pos = p->host_stage;
-    staged.vel = p->host_stage + 3 * n;
-    staged.weight = c0->weight ? p->host_stage + 6 * n : nullptr;
+    used->flags &= ~MPS_CATALOG_HOST;
+    used->pos = p->host_stage;
+    used->vel = p->host_stage + 3 * n;
+    used->weight = c0->weight ? p->host_stage + 6 * n : nullptr;
     MPS_TRY(hipMemcpyAsync(p->host_stage, c0->pos, sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
     MPS_TRY(hipMemcpyAsync(p->host_stage + 3 * n, c0->vel, sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
     if (c0->weight)
       MPS_TRY(hipMemcpyAsync(p->host_stage + 6 * n, c0->weight, sizeof(float) * n, hipMemcpyHostToDevice, s));
-    c = &staged;
   }
   mark(p, 0, s);
-  MPS_TRY(launch_count(p, c, s));
-  MPS_TRY(launch_derive(p, c, s));
+  MPS_TRY(launch_count(p, used, s));
+  MPS_TRY(launch_derive(p, used, s));
   mark(p, 1, s);
   MPS_TRY(launch_scan(p, s));
   mark(p, 2, s);
-  MPS_TRY(launch_permute(p, c, s));
+  MPS_TRY(launch_permute(p, used, s));
   mark(p, 3, s);
   MPS_TRY(launch_clear_grid(p, s));
   mark(p, 4, s);
-  MPS_TRY(launch_scatter_impl(p, c, s, bulk_grid));
+  return MPS_OK;
+}
+
+// Stages up to (and including) the scatter; `bulk_grid` deposits v - v_b.
+int enqueue_particles(Plan* p, const mps_catalog* c0, hipStream_t s, int bulk_grid) {
+  mps_catalog c;
+  const int st = enqueue_prescatter(p, c0, s, &c);
+  if (st != MPS_OK) return st;
+  MPS_TRY(launch_scatter_impl(p, &c, s, bulk_grid));
   mark(p, 5, s);
   return MPS_OK;
 }
 
-int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s, void* stage) {
+// The stages after the scatter and the copy of the results to `stage`.
+int enqueue_postscatter(Plan* p, const mps_catalog* c, hipStream_t s, void* stage) {
   if (!stage) stage = p->h_stage;
-  int st = enqueue_particles(p, c, s, 0);
-  if (st != MPS_OK) return st;
   MPS_TRY(launch_fft_z(p, p->grid, s));
   mark(p, 6, s);
   MPS_TRY(launch_fft_y(p, p->grid, s));
@@ -192,6 +198,98 @@ int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s, void* stage) 
   MPS_TRY(hipMemcpyAsync(static_cast<char*>(stage) + sizeof(ResultHeader), p->d_bins,
                          bytes - sizeof(ResultHeader), hipMemcpyDeviceToHost, s));
   return MPS_OK;
+}
+
+int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s, void* stage) {
+  const int st = enqueue_particles(p, c, s, 0);
+  if (st != MPS_OK) return st;
+  return enqueue_postscatter(p, c, s, stage);
+}
+
+// ------------------------------------------------------------ batches
+int BatchWorkspace::ensure(int n) {
+  if (n <= cap) return MPS_OK;
+  if (d_cats) (void)hipFree(d_cats);
+  if (d_starts) (void)hipFree(d_starts);
+  if (h_cats) (void)hipHostFree(h_cats);
+  if (h_starts) (void)hipHostFree(h_starts);
+  d_cats = nullptr;
+  d_starts = nullptr;
+  h_cats = nullptr;
+  h_starts = nullptr;
+  cap = 0;
+  const int c = n < 64 ? 64 : n;
+  bool ok = hipMalloc(reinterpret_cast<void**>(&d_cats), sizeof(ScatterCat) * c) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&d_starts), sizeof(int64_t) * (c + 2)) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h_cats), sizeof(ScatterCat) * c, hipHostMallocDefault) ==
+                 hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h_starts), sizeof(int64_t) * (c + 2), hipHostMallocDefault) ==
+                 hipSuccess;
+  if (!d_queue) ok = ok && hipMalloc(reinterpret_cast<void**>(&d_queue), sizeof(uint32_t) * 8) == hipSuccess;
+  if (!ok) return MPS_E_NOMEM;
+  cap = c;
+  return MPS_OK;
+}
+
+// Several catalogs, each with its own plan, on n_lanes streams (lanes[0]
+// joins the others for the scatter):
+//   1. per catalog, round robin on the lanes: moments, sort, clear;
+//   2. on lanes[0]: one persistent multi-catalog scatter launch over the
+//      tiles of every catalog it serves (FP32 grids, 16^3 tiles, truncated
+//      BL3; with and without weights separately), so that catalogs with few
+//      tiles fill the GPU together; the others' own scatter launches;
+//   3. per catalog, round robin: FFTs, estimator, finalize, copy back to
+//      stages[i] (the plan's own staging buffer when NULL).
+// lanes[1..] must be ordered after earlier work by the caller.
+int enqueue_batch(Plan* const* plans, const mps_catalog* cats, int n, hipStream_t* lanes, int n_lanes,
+                  hipEvent_t* events, BatchWorkspace* ws, void* const* stages) {
+  std::vector<mps_catalog> used(n);
+  int st = MPS_OK;
+  for (int i = 0; i < n && st == MPS_OK; ++i) st = enqueue_prescatter(plans[i], &cats[i], lanes[i % n_lanes], &used[i]);
+  if (st != MPS_OK) return st;
+  for (int l = 1; l < n_lanes; ++l) {
+    MPS_TRY(hipEventRecord(events[l], lanes[l]));
+    MPS_TRY(hipStreamWaitEvent(lanes[0], events[l], 0));
+  }
+  // eligible catalogs, without weights first, then with
+  std::vector<int> multi[2];
+  for (int i = 0; i < n; ++i) {
+    if (scatter_multi_eligible(plans[i], &used[i])) multi[used[i].weight ? 1 : 0].push_back(i);
+    else MPS_TRY(launch_scatter_impl(plans[i], &used[i], lanes[0], 0));
+  }
+  const int nm = static_cast<int>(multi[0].size() + multi[1].size());
+  if (nm > 0) {
+    if ((st = ws->ensure(nm)) != MPS_OK) return st;
+    int k = 0;
+    for (int g = 0; g < 2; ++g) {
+      int64_t* starts = ws->h_starts + (g == 0 ? 0 : multi[0].size() + 1);
+      starts[0] = 0;
+      for (size_t j = 0; j < multi[g].size(); ++j) {
+        Plan* p = plans[multi[g][j]];
+        ws->h_cats[k + j] = scatter_cat(p, &used[multi[g][j]]);
+        starts[j + 1] = starts[j] + p->n_tiles;
+      }
+      k += static_cast<int>(multi[g].size());
+    }
+    MPS_TRY(hipMemcpyAsync(ws->d_cats, ws->h_cats, sizeof(ScatterCat) * nm, hipMemcpyHostToDevice, lanes[0]));
+    MPS_TRY(hipMemcpyAsync(ws->d_starts, ws->h_starts, sizeof(int64_t) * (nm + 2), hipMemcpyHostToDevice, lanes[0]));
+    k = 0;
+    for (int g = 0; g < 2; ++g) {
+      const int m = static_cast<int>(multi[g].size());
+      if (m > 0) {
+        const int64_t off = g == 0 ? 0 : static_cast<int64_t>(multi[0].size()) + 1;
+        Plan* p0 = plans[multi[g][0]];
+        MPS_TRY(launch_scatter_multi(ws->d_cats + k, ws->d_starts + off, m, ws->h_starts[off + m], g == 1,
+                                     p0->taps[0], p0->tap_bound[0], ws->d_queue, p0->num_cus, lanes[0]));
+      }
+      k += m;
+    }
+  }
+  MPS_TRY(hipEventRecord(events[0], lanes[0]));
+  for (int l = 1; l < n_lanes; ++l) MPS_TRY(hipStreamWaitEvent(lanes[l], events[0], 0));
+  for (int i = 0; i < n && st == MPS_OK; ++i)
+    st = enqueue_postscatter(plans[i], &cats[i], lanes[i % n_lanes], stages ? stages[i] : nullptr);
+  return st;
 }
 
 namespace {
@@ -246,6 +344,41 @@ int unpack(Plan* p, const mps_catalog* c, mps_result* out, const void* stage) {
   return MPS_OK;
 }
 
+namespace {
+
+// Streams, events and multi-scatter workspace of mps_estimate_batch, one set
+// per device, created on first use and kept for the process.  Batch calls on
+// one device take turns.
+struct BatchLanes {
+  static constexpr int kLanes = 4;
+  std::mutex mu;
+  bool made = false;
+  hipStream_t lanes[kLanes] = {};
+  hipEvent_t ev[kLanes] = {};
+  hipEvent_t join[kLanes] = {};
+  hipEvent_t start = nullptr;
+  BatchWorkspace ws;
+  int ready() {
+    if (made) return MPS_OK;
+    for (int j = 0; j < kLanes; ++j) {
+      if (!lanes[j] && hipStreamCreateWithFlags(&lanes[j], hipStreamNonBlocking) != hipSuccess) return MPS_E_HIP;
+      if (!ev[j] && hipEventCreateWithFlags(&ev[j], hipEventDisableTiming) != hipSuccess) return MPS_E_HIP;
+      if (!join[j] && hipEventCreateWithFlags(&join[j], hipEventDisableTiming) != hipSuccess) return MPS_E_HIP;
+    }
+    if (!start && hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess) return MPS_E_HIP;
+    made = true;
+    return MPS_OK;
+  }
+};
+
+constexpr int kMaxDevices = 16;
+
+BatchLanes& batch_lanes(int dev) {
+  static BatchLanes* lanes = new BatchLanes[kMaxDevices];  // kept until the process ends
+  return lanes[dev];
+}
+
+}  // namespace
 }  // namespace mps
 
 using namespace mps;
@@ -466,38 +599,31 @@ int mps_estimate_batch(mps_plan* const* plans, const mps_catalog* cats, mps_resu
     if ((st = ensure_bins(p, &cats[i])) != MPS_OK) return st;
     if ((st = ensure_particles(p, cats[i].n_particles)) != MPS_OK) return st;
   }
-  // the catalogs go round robin to kBatchStreams streams, each started
-  // after the caller's earlier work on `stream`, so that small catalogs'
-  // kernels overlap; `stream` then waits for all of them
-  constexpr int kBatchStreams = 4;
-  const int ns = n < kBatchStreams ? n : kBatchStreams;
-  hipStream_t bs[kBatchStreams] = {};
-  hipEvent_t ev[kBatchStreams + 1] = {};
-  int st = MPS_OK;
-  for (int j = 0; j <= ns && st == MPS_OK; ++j)
-    if (hipEventCreateWithFlags(&ev[j], hipEventDisableTiming) != hipSuccess) st = MPS_E_HIP;
-  for (int j = 0; j < ns && st == MPS_OK; ++j)
-    if (hipStreamCreateWithFlags(&bs[j], hipStreamNonBlocking) != hipSuccess) st = MPS_E_HIP;
-  if (st == MPS_OK && hipEventRecord(ev[ns], stream) != hipSuccess) st = MPS_E_HIP;
-  for (int j = 0; j < ns && st == MPS_OK; ++j)
-    if (hipStreamWaitEvent(bs[j], ev[ns], 0) != hipSuccess) st = MPS_E_HIP;
-  for (int i = 0; i < n && st == MPS_OK; ++i)
-    st = enqueue_estimate(reinterpret_cast<Plan*>(plans[i]), &cats[i], bs[i % ns]);
-  for (int j = 0; j < ns; ++j) {  // join even after a failure, so nothing is left running
-    if (bs[j] && hipEventRecord(ev[j], bs[j]) == hipSuccess) (void)hipStreamWaitEvent(stream, ev[j], 0);
+  // the catalogs' stages go to the device's batch lanes (created once), each
+  // started after the caller's earlier work on `stream`; `stream` then waits
+  // for all of them
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MPS_E_HIP;
+  BatchLanes& bl = batch_lanes(dev);
+  std::lock_guard<std::mutex> guard(bl.mu);
+  int st = bl.ready();
+  if (st != MPS_OK) return st;
+  std::vector<Plan*> ps(n);
+  for (int i = 0; i < n; ++i) ps[i] = reinterpret_cast<Plan*>(plans[i]);
+  if (hipEventRecord(bl.start, stream) != hipSuccess) return MPS_E_HIP;
+  for (int j = 0; j < BatchLanes::kLanes; ++j)
+    if (hipStreamWaitEvent(bl.lanes[j], bl.start, 0) != hipSuccess) return MPS_E_HIP;
+  st = n > 0 ? enqueue_batch(ps.data(), cats, n, bl.lanes, BatchLanes::kLanes, bl.ev, &bl.ws, nullptr) : MPS_OK;
+  for (int j = 0; j < BatchLanes::kLanes; ++j) {  // join even after a failure, so nothing is left running
+    if (hipEventRecord(bl.join[j], bl.lanes[j]) == hipSuccess) (void)hipStreamWaitEvent(stream, bl.join[j], 0);
   }
   const bool synced = hipStreamSynchronize(stream) == hipSuccess;
-  for (int j = 0; j < ns; ++j) {
-    if (bs[j]) (void)hipStreamDestroy(bs[j]);
-  }
-  for (int j = 0; j <= ns; ++j)
-    if (ev[j]) (void)hipEventDestroy(ev[j]);
   if (st != MPS_OK) return st;
   if (!synced) return MPS_E_HIP;
   int first = MPS_OK;
   for (int i = 0; i < n; ++i) {
-    const int st = unpack(reinterpret_cast<Plan*>(plans[i]), &cats[i], &outs[i]);
-    if (st != MPS_OK && first == MPS_OK) first = st;
+    const int s2 = unpack(ps[i], &cats[i], &outs[i]);
+    if (s2 != MPS_OK && first == MPS_OK) first = s2;
   }
   return first;
 }

@@ -85,6 +85,25 @@ struct Derived {
   int bulk;              // 1 if p is replaced by p - v_b delta
 };
 
+// Sort parameters of a catalog on a plan's grid (see particles.hip locate()).
+struct KeyParams {
+  double scale;  // N / L
+  double shift;  // added to u = x N / L
+  int n;         // grid size
+  int tshift;    // log2(tile)
+  int nt;        // tiles per axis
+};
+
+// One catalog's part of a (possibly multi-catalog) FP32 scatter launch.
+struct ScatterCat {
+  const float4* sorted;    // tile-sorted records
+  const uint32_t* offset;  // n_tiles + 1 record offsets
+  float* grid;             // four N^3 FP32 grids (zeroed)
+  KeyParams kp;
+  const Derived* dsrc;     // moments and bounds of the catalog
+  int bulk;                // 1: deposit w (v - v_b)
+};
+
 // Layout of the device result block copied back to the host.
 struct ResultHeader {
   double sums[kMomentSums];
@@ -215,6 +234,24 @@ inline size_t host_stage_bytes(const mps_catalog* c) {
 // Async, including the copy of the results to `stage` (the plan's own
 // staging buffer when NULL).
 int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s, void* stage = nullptr);
+
+// Device and pinned buffers of the multi-catalog scatter launch: catalog
+// descriptors and tile prefix sums (two groups), queue counters.  Grown on
+// demand, kept by their owner.
+struct BatchWorkspace {
+  ScatterCat* d_cats = nullptr;
+  int64_t* d_starts = nullptr;
+  uint32_t* d_queue = nullptr;
+  ScatterCat* h_cats = nullptr;
+  int64_t* h_starts = nullptr;
+  int cap = 0;
+  int ensure(int n);
+};
+// Estimates of n catalogs (plans[i] for cats[i]) on n_lanes streams with the
+// multi-catalog scatter (events: n_lanes events for the joins); results go to
+// stages[i] (or each plan's own staging buffer).  Async.
+int enqueue_batch(Plan* const* plans, const mps_catalog* cats, int n, hipStream_t* lanes, int n_lanes,
+                  hipEvent_t* events, BatchWorkspace* ws, void* const* stages);
 // After the stream synced; reads `stage` (the plan's own when NULL).
 int unpack(Plan* p, const mps_catalog* c, mps_result* out, const void* stage = nullptr);
 
@@ -225,6 +262,15 @@ hipError_t launch_scan(Plan* p, hipStream_t s);
 hipError_t launch_permute(Plan* p, const mps_catalog* c, hipStream_t s);
 hipError_t launch_clear_grid(Plan* p, hipStream_t s);
 hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s);
+// The multi-catalog scatter: FP32 grids, 16^3 tiles, the truncated BL3
+// kernel; one launch over all the catalogs' tiles (d_cats, d_starts: device
+// arrays of n_cats descriptors and n_cats + 1 tile prefix sums; d_queue: 8
+// counters).  has_w: the records carry weights (32-byte records).
+ScatterCat scatter_cat(Plan* p, const mps_catalog* c);
+bool scatter_multi_eligible(const Plan* p, const mps_catalog* c);
+hipError_t launch_scatter_multi(const ScatterCat* d_cats, const int64_t* d_starts, int n_cats, int64_t n_items,
+                                bool has_w, const TapPoly& tp, const TapBound& tb, uint32_t* d_queue, int num_cus,
+                                hipStream_t s);
 
 // Launchers (fft.hip).
 hipError_t launch_fft_z(Plan* p, void* grid, hipStream_t s);

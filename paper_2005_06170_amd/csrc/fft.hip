@@ -632,50 +632,62 @@ __global__ __launch_bounds__(NT) void mu_bin_kernel(const T* __restrict__ grid, 
     partials[static_cast<int64_t>(blockIdx.x) * kMaxMuCells * kNumQMu + i] = lbins[i];
 }
 
+// Sum of one quantity over the per-workgroup partials (stride `stride`
+// doubles apart) by one wave, in a fixed order: lane l adds partials
+// l, l + 64, ... in turn, then the lanes combine in a fixed butterfly.  The
+// result (valid in every lane) does not depend on timing.
+__device__ __forceinline__ double wave_fixed_sum(const double* __restrict__ p, int nblocks, int64_t stride) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int b = lane; b < nblocks; b += 64) s += p[static_cast<int64_t>(b) * stride];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  return s;
+}
+
 // Fixed-order sum of the (k, mu) partials, then means (times V); empty cells
-// NaN.
-__global__ __launch_bounds__(256) void finalize_mu_kernel(const double* __restrict__ partials, int nblocks,
-                                                          int ncell, double volume, double* __restrict__ out) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= ncell) return;
-  double s[kNumQMu];
-#pragma unroll
-  for (int q = 0; q < kNumQMu; ++q) s[q] = 0.0;
-  for (int b = 0; b < nblocks; ++b) {
-    const double* pb = partials + (static_cast<int64_t>(b) * kMaxMuCells + c) * kNumQMu;
-#pragma unroll
-    for (int q = 0; q < kNumQMu; ++q) s[q] += pb[q];
-  }
-  const double cnt = s[MCount];
+// NaN.  One workgroup per cell, one wave per quantity.
+__global__ __launch_bounds__(64 * kNumQMu) void finalize_mu_kernel(const double* __restrict__ partials,
+                                                                  int nblocks, double volume,
+                                                                  double* __restrict__ out) {
+  const int c = blockIdx.x, q = threadIdx.x >> 6;
+  __shared__ double sums[kNumQMu];
+  const double s = wave_fixed_sum(partials + static_cast<int64_t>(c) * kNumQMu + q, nblocks,
+                                  static_cast<int64_t>(kMaxMuCells) * kNumQMu);
+  if ((threadIdx.x & 63) == 0) sums[q] = s;
+  __syncthreads();
+  if (threadIdx.x >= kNumQMu) return;
+  const int k = threadIdx.x;
+  const double cnt = sums[MCount];
   const double nan = __longlong_as_double(0x7ff8000000000000ll);
   const double inv = cnt > 0 ? 1.0 / cnt : 0.0;
-  double* o = out + static_cast<int64_t>(c) * kNumQMu;
-  o[MCount] = cnt;
-  o[MKsum] = cnt > 0 ? s[MKsum] * inv : nan;
-  o[MMusum] = cnt > 0 ? s[MMusum] * inv : nan;
-  for (int q = MPdd; q < kNumQMu; ++q) o[q] = cnt > 0 ? volume * s[q] * inv : nan;
+  double v;
+  if (k == MCount) v = cnt;
+  else if (k == MKsum || k == MMusum) v = cnt > 0 ? sums[k] * inv : nan;
+  else v = cnt > 0 ? volume * sums[k] * inv : nan;
+  out[static_cast<int64_t>(c) * kNumQMu + k] = v;
 }
 
 // Fixed-order reduction of the workgroup partials and the final per-bin
-// means (times V = L^3); empty bins are NaN.
-__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ partials, int nblocks,
-                                                       int n_bins, double volume, double* __restrict__ out) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n_bins * kNumQ) return;
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partials[static_cast<int64_t>(b) * kMaxBins * kNumQ + i];
-  out[i] = s;
-}
-
-__global__ void finalize_means_kernel(double* __restrict__ sums, int n_bins, double volume) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_bins) return;
-  double* s = sums + b * kNumQ;
-  const double cnt = s[QCount];
+// means (times V = L^3); empty bins are NaN.  One workgroup per bin, one
+// wave per accumulated quantity.
+__global__ __launch_bounds__(64 * kNumQ) void finalize_kernel(const double* __restrict__ partials, int nblocks,
+                                                             double volume, double* __restrict__ out) {
+  const int b = blockIdx.x, q = threadIdx.x >> 6;
+  __shared__ double sums[kNumQ];
+  const double s = wave_fixed_sum(partials + static_cast<int64_t>(b) * kNumQ + q, nblocks,
+                                  static_cast<int64_t>(kMaxBins) * kNumQ);
+  if ((threadIdx.x & 63) == 0) sums[q] = s;
+  __syncthreads();
+  if (threadIdx.x >= kNumQ) return;
+  const int k = threadIdx.x;
+  const double cnt = sums[QCount];
   const double nan = __longlong_as_double(0x7ff8000000000000ll);
   const double inv = cnt > 0 ? 1.0 / cnt : 0.0;
-  s[QKsum] = cnt > 0 ? s[QKsum] * inv : nan;
-  for (int q = QPdd; q < kNumQ; ++q) s[q] = cnt > 0 ? volume * s[q] * inv : nan;
+  double v;
+  if (k == QCount) v = cnt;
+  else if (k == QKsum) v = cnt > 0 ? sums[k] * inv : nan;
+  else v = cnt > 0 ? volume * sums[k] * inv : nan;
+  out[b * kNumQ + k] = v;
 }
 
 template <typename T>
@@ -841,17 +853,13 @@ hipError_t launch_mu_bin(Plan* p, const mps_catalog* c, int n_mu, const double* 
 hipError_t launch_finalize_mu(Plan* p, const mps_catalog* c, int n_mu, hipStream_t s) {
   const int ncell = c->n_bins * n_mu;
   const double vol = c->box * c->box * c->box;
-  finalize_mu_kernel<<<(ncell + 255) / 256, 256, 0, s>>>(p->d_mu_partials, p->num_cus, ncell, vol, p->d_mu_bins);
+  finalize_mu_kernel<<<ncell, 64 * kNumQMu, 0, s>>>(p->d_mu_partials, p->num_cus, vol, p->d_mu_bins);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(Plan* p, const mps_catalog* c, hipStream_t s) {
-  const int nq = c->n_bins * kNumQ;
   const double vol = c->box * c->box * c->box;
-  finalize_kernel<<<(nq + 255) / 256, 256, 0, s>>>(p->d_bin_partials, p->bin_blocks, c->n_bins, vol, p->d_bins);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  finalize_means_kernel<<<1, kMaxBins, 0, s>>>(p->d_bins, c->n_bins, vol);
+  finalize_kernel<<<c->n_bins, 64 * kNumQ, 0, s>>>(p->d_bin_partials, p->bin_blocks, vol, p->d_bins);
   return hipGetLastError();
 }
 

@@ -94,13 +94,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-struct KeyParams {
-  double scale;  // N / L
-  double shift;  // added to u = x N / L (see locate)
-  int n;         // grid size
-  int tshift;    // log2(tile)
-  int nt;        // tiles per axis
-};
 
 __device__ __forceinline__ uint32_t tile_key(float x, float y, float z, const KeyParams& kp, bool* ok) {
   double f;
@@ -251,8 +244,9 @@ __global__ __launch_bounds__(kCountThreads) void count_kernel(
 
 // Fixed-order sum of the per-block moment partials, then the derived shot
 // and bulk-flow scalars.  One workgroup of kMomentBlocks threads: thread b
-// holds block b's partials and a fixed reduction tree combines them.
-__global__ __launch_bounds__(kMomentBlocks) void derive_kernel(const double* __restrict__ partials,
+// holds block b's partials (zero beyond the nb blocks the count ran) and a
+// fixed reduction tree combines them.
+__global__ __launch_bounds__(kMomentBlocks) void derive_kernel(const double* __restrict__ partials, int nb,
                                                                ResultHeader* hdr, int bulk) {
   constexpr int kW = kMomentBlocks / 64;
   __shared__ double red[kW][kMomentSums + kMomentMax];
@@ -261,12 +255,12 @@ __global__ __launch_bounds__(kMomentBlocks) void derive_kernel(const double* __r
   const int b = threadIdx.x, wave = b >> 6, lane = b & 63;
 #pragma unroll
   for (int q = 0; q < kMomentSums; ++q) {
-    const double v = wave_sum(partials[b * kMomentSums + q]);
+    const double v = wave_sum(b < nb ? partials[b * kMomentSums + q] : 0.0);
     if (lane == 0) red[wave][q] = v;
   }
 #pragma unroll
   for (int q = 0; q < kMomentMax; ++q) {
-    double m = partials[kMomentBlocks * kMomentSums + b * kMomentMax + q];
+    double m = b < nb ? partials[kMomentBlocks * kMomentSums + b * kMomentMax + q] : 0.0;
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
     if (lane == 0) red[wave][kMomentSums + q] = m;
   }
@@ -559,10 +553,6 @@ __device__ __forceinline__ int round_to_int(float x) {
 // 64-bit LDS atomic.  The 64-bit sum is hi_sum 2^32 + lo_sum modulo 2^64:
 // as long as the final lo_sum fits int32, its low word is lo_sum and the high
 // word, corrected for lo_sum's sign, is hi_sum modulo 2^32.
-__device__ __forceinline__ unsigned long long pack_pair(int lo, int hi) {
-  const unsigned h = static_cast<unsigned>(hi + (lo >> 31));
-  return (static_cast<unsigned long long>(h) << 32) | static_cast<unsigned>(lo);
-}
 
 // The pair (round(wlo wz), round(whi wz)) packed as above in five VALU
 // operations: lo < 0 exactly when x = wlo wz < -1/2, and the indicator
@@ -666,6 +656,42 @@ __device__ __forceinline__ int64_t next_tile(const TileQueues& tq, int64_t n_til
   return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
+// Tiles of several catalogs in one persistent launch: the work items are the
+// catalogs' tiles one catalog after another, item i of catalog c being tile
+// i - starts[c] (starts: n_cats + 1 prefix sums of the tile counts).  Thread 0
+// claims an item from the queues and finds its catalog; the workgroup
+// receives (c << 32) | tile, or -1 when every queue is empty.
+template <int NT, bool kMulti>
+__device__ __forceinline__ int64_t next_item(const TileQueues& tq, int64_t n_items, const int64_t* starts,
+                                             int n_cats, long long* s_tile) {
+  if (threadIdx.x == 0) {
+    long long got = -1;
+    const int mine = static_cast<int>(blockIdx.x % tq.nq);
+    for (int k = 0; k < tq.nq && got < 0; ++k) {
+      const int q = (mine + k) % tq.nq;
+      const uint32_t i = atomicAdd(tq.counter + q, 1u);
+      const int64_t tl = q * tq.per_queue + static_cast<int64_t>(i);
+      if (static_cast<int64_t>(i) < tq.per_queue && tl < n_items) got = tl;
+    }
+    if (kMulti && got >= 0) {
+      int lo = 0, hi = n_cats;  // starts[lo] <= got < starts[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (starts[mid] <= got) lo = mid; else hi = mid;
+      }
+      got = (static_cast<long long>(lo) << 32) | static_cast<long long>(got - starts[lo]);
+    }
+    *s_tile = got;
+  }
+  __syncthreads();
+  const int64_t v = *s_tile;
+  __syncthreads();
+  const uint64_t u = static_cast<uint64_t>(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 // One line of the separable bound convolution: out[g] = sum_j k_j in[g - j]
 // over taps j = -2..3, with in = 0 outside the E-long line.
 template <int E, int NTAP>
@@ -697,10 +723,14 @@ __device__ __forceinline__ void bound_line(const float (&in)[E], const TapBound&
 // the worst-case sum of the per-deposit rounding errors (half a unit per
 // particle).  A single pass over LDS gives both the bound and the zeroed
 // accumulator.
-template <int TS, int NT, int NTAP, int DEG, bool kW>
+//
+// kMulti: one launch over the tiles of several catalogs (ScatterCat array
+// `cats`, item prefix sums `starts`), so that catalogs with few tiles share
+// the GPU; otherwise the one catalog `one`.
+template <int TS, int NT, int NTAP, int DEG, bool kW, bool kMulti>
 __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
-    const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, float* __restrict__ grid,
-    KeyParams kp, int64_t n_tiles, TileQueues tq, TapPoly tp, TapBound kb, const Derived* dsrc, int bulk) {
+    ScatterCat one, const ScatterCat* __restrict__ cats, const int64_t* __restrict__ starts, int n_cats,
+    int64_t n_items, TileQueues tq, TapPoly tp, TapBound kb) {
   constexpr int H = kHaloLo<NTAP>;
   constexpr int E = TS + NTAP - 1;
   constexpr int VOL = E * E * E;
@@ -717,23 +747,41 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   // sparse tiles: tap-origin bounding box (min x, y, z, max x, y, z)
   __shared__ int bb[6];
   constexpr uint32_t kSparse = 128;  // at most this many particles: one per thread
+  // the current catalog's parameters (uniform; reloaded when it changes)
+  const float4* sorted = nullptr;
+  const uint32_t* offset = nullptr;
+  float* grid = nullptr;
+  KeyParams kp = one.kp;
+  int bulk = 0;
   double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
-  if (bulk) {
-    vb0 = dsrc->vb[0];
-    vb1 = dsrc->vb[1];
-    vb2 = dsrc->vb[2];
-  }
-  // catalog-wide bound of |q| per field for the charges deposited here
-  double qmax[kNumFields];
-  qmax[0] = dsrc->qmax[0];
-  qmax[1] = dsrc->qmax[1] + (bulk ? dsrc->qmax[0] * fabs(vb0) : 0.0);
-  qmax[2] = dsrc->qmax[2] + (bulk ? dsrc->qmax[0] * fabs(vb1) : 0.0);
-  qmax[3] = dsrc->qmax[3] + (bulk ? dsrc->qmax[0] * fabs(vb2) : 0.0);
+  double qmax[kNumFields] = {0.0, 0.0, 0.0, 0.0};
+  int nt = 0, n = 0;
+  int64_t n3 = 0;
+  int cur_cat = -1;
+  auto set_cat = [&](const ScatterCat& c) {
+    sorted = c.sorted;
+    offset = c.offset;
+    grid = c.grid;
+    kp = c.kp;
+    bulk = c.bulk;
+    const Derived* dsrc = c.dsrc;
+    vb0 = vb1 = vb2 = 0.0;
+    if (bulk) {
+      vb0 = dsrc->vb[0];
+      vb1 = dsrc->vb[1];
+      vb2 = dsrc->vb[2];
+    }
+    // catalog-wide bound of |q| per field for the charges deposited here
+    qmax[0] = dsrc->qmax[0];
+    qmax[1] = dsrc->qmax[1] + (bulk ? dsrc->qmax[0] * fabs(vb0) : 0.0);
+    qmax[2] = dsrc->qmax[2] + (bulk ? dsrc->qmax[0] * fabs(vb1) : 0.0);
+    qmax[3] = dsrc->qmax[3] + (bulk ? dsrc->qmax[0] * fabs(vb2) : 0.0);
+    nt = kp.nt;
+    n = kp.n;
+    n3 = static_cast<int64_t>(n) * n * n;
+  };
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
-  const int nt = kp.nt;
-  const int n = kp.n;
-  const int64_t n3 = static_cast<int64_t>(n) * n * n;
   unsigned* cnt_u = reinterpret_cast<unsigned*>(acc);
   unsigned long long* acc2 = reinterpret_cast<unsigned long long*>(acc);
 
@@ -743,16 +791,22 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   for (int j = 0; j < NTAP; ++j) kmax = fmaxf(kmax, kb.k[j]);
   const float kmax3 = kmax * kmax * kmax;
   if (t < 6) bb[t] = t < 3 ? E : -1;
-  int64_t tile = next_tile<NT>(tq, n_tiles, &s_tile);
+  int64_t item = next_item<NT, kMulti>(tq, n_items, starts, n_cats, &s_tile);
   for (int i = t; i < kNumFields * VOL; i += NT) acc[i] = 0;
   if (t < 64) bs.cnt[t] = 0;
   __syncthreads();
 
-  while (tile >= 0) {
+  while (item >= 0) {
+    const int c_item = static_cast<int>(item >> 32);
+    const int64_t tile = item & 0xffffffffll;
+    if (c_item != cur_cat) {
+      set_cat(kMulti ? cats[c_item] : one);
+      cur_cat = c_item;
+    }
     const uint32_t p0 = offset[tile], p1 = offset[tile + 1];
     const uint32_t cnt = p1 - p0;
     if (cnt == 0) {  // nothing to deposit or flush (uniform across the workgroup)
-      tile = next_tile<NT>(tq, n_tiles, &s_tile);
+      item = next_item<NT, kMulti>(tq, n_items, starts, n_cats, &s_tile);
       continue;
     }
     const int tz = static_cast<int>(tile % nt);
@@ -959,7 +1013,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       deposit_chunk(c0, m, key, false);
     }
     // take the next tile, then flush this one (clearing it)
-    tile = next_tile<NT>(tq, n_tiles, &s_tile);
+    item = next_item<NT, kMulti>(tq, n_items, starts, n_cats, &s_tile);
     if (t < 64) bs.cnt[t] = 0;
     float inv[kNumFields];
 #pragma unroll
@@ -1134,7 +1188,9 @@ hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
                            256, 0, s>>>(p->tile_count, p->n_tiles);
   clear_kernel<uint32_t><<<1, 256, 0, s>>>(reinterpret_cast<uint32_t*>(p->d_header),
                                            static_cast<int64_t>(sizeof(ResultHeader) / sizeof(uint32_t)));
-  const int nb = kMomentBlocks;  // fixed grid: the moment sums keep one order
+  // the grid depends only on the particle count, so the moment sums of a
+  // catalog are added in one order whatever else runs
+  const int nb = count_blocks(c->n_particles);
   const bool lds = p->n_tiles <= kLdsTiles;
   auto go = [&](auto has_w, auto use_lds) {
     const size_t dyn = decltype(use_lds)::value ? sizeof(uint32_t) * static_cast<size_t>(p->n_tiles) : 0;
@@ -1153,8 +1209,8 @@ hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
 }
 
 hipError_t launch_derive(Plan* p, const mps_catalog* c, hipStream_t s) {
-  derive_kernel<<<1, kMomentBlocks, 0, s>>>(p->moment_partials, p->d_header,
-                                 (c->flags & MPS_BULKFLOW_SUBTRACT) ? 1 : 0);
+  derive_kernel<<<1, kMomentBlocks, 0, s>>>(p->moment_partials, count_blocks(c->n_particles), p->d_header,
+                                            (c->flags & MPS_BULKFLOW_SUBTRACT) ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1365,16 +1421,17 @@ hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int
     tq.nq = xcd_chunk > 0 ? 8 : 1;
     tq.per_queue = xcd_chunk > 0 ? xcd_chunk : p->n_tiles;
     clear_kernel<uint32_t><<<1, 64, 0, s>>>(p->tile_queue, 8);
+    const ScatterCat one{p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, dsrc, bulk};
     if (p->tile == 16) {
       // one workgroup per CU (the LDS holds one), never more than the tiles
       const int64_t blocks = p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus;
-      scatter_fixed_kernel<16, 1024, NTAP, DEG, kW><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
-          p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk);
+      scatter_fixed_kernel<16, 1024, NTAP, DEG, kW, false><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+          one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb);
     } else {
       const int64_t cap = 4 * static_cast<int64_t>(p->num_cus);
       const int64_t blocks = p->n_tiles < cap ? p->n_tiles : cap;
-      scatter_fixed_kernel<8, 512, NTAP, DEG, kW><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
-          p->sorted, p->tile_offset, static_cast<float*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk);
+      scatter_fixed_kernel<8, 512, NTAP, DEG, kW, false><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
+          one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb);
     }
   } else if (p->tile == 16) {
     TileQueues tq;
@@ -1420,6 +1477,34 @@ hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int
 
 hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s) {
   return launch_scatter_impl(p, c, s, 0);
+}
+
+ScatterCat scatter_cat(Plan* p, const mps_catalog* c) {
+  return ScatterCat{p->sorted, p->tile_offset, static_cast<float*>(p->grid), key_params(p, c), &p->d_header->d, 0};
+}
+
+bool scatter_multi_eligible(const Plan* p, const mps_catalog* c) {
+  return p->prec == MPS_F32 && p->tile == 16 && kernel_id(c->flags) == 0;
+}
+
+hipError_t launch_scatter_multi(const ScatterCat* d_cats, const int64_t* d_starts, int n_cats, int64_t n_items,
+                                bool has_w, const TapPoly& tp, const TapBound& tb, uint32_t* d_queue, int num_cus,
+                                hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  TileQueues tq;
+  tq.counter = d_queue;
+  tq.nq = 8;
+  tq.per_queue = (n_items + 7) / 8;
+  clear_kernel<uint32_t><<<1, 64, 0, s>>>(d_queue, 8);
+  const int64_t blocks = n_items < num_cus ? n_items : num_cus;
+  const ScatterCat none{};
+  if (has_w)
+    scatter_fixed_kernel<16, 1024, 6, 3, true, true><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+        none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
+  else
+    scatter_fixed_kernel<16, 1024, 6, 3, false, true><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+        none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
+  return hipGetLastError();
 }
 
 }  // namespace mps

@@ -257,6 +257,9 @@ void worker_main(Server* s) {
   (void)hipSetDevice(s->device);
   hipStream_t stream = nullptr;
   if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+  hipEvent_t fork = nullptr;
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) fork = nullptr;
+  BatchWorkspace ws;  // this worker's multi-catalog scatter buffers
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     std::vector<std::shared_ptr<Request>> batch;
@@ -267,6 +270,12 @@ void worker_main(Server* s) {
       if (s->stop && s->queue.empty()) {
         lk.unlock();
         if (stream) (void)hipStreamDestroy(stream);
+        if (fork) (void)hipEventDestroy(fork);
+        if (ws.d_cats) (void)hipFree(ws.d_cats);
+        if (ws.d_starts) (void)hipFree(ws.d_starts);
+        if (ws.d_queue) (void)hipFree(ws.d_queue);
+        if (ws.h_cats) (void)hipHostFree(ws.h_cats);
+        if (ws.h_starts) (void)hipHostFree(ws.h_starts);
         return;
       }
       size_t pos = 0;
@@ -319,8 +328,12 @@ void worker_main(Server* s) {
     lk.unlock();
 
     // run the batch: each request's stages start after its catalog is ready
-    // on the submitter's stream; all are enqueued back to back, one
+    // on the submitter's stream; the requests go through the multi-catalog
+    // path together (one scatter launch over all their tiles), one
     // synchronisation
+    std::vector<Plan*> run_plans;
+    std::vector<mps_catalog> run_cats;
+    std::vector<size_t> run_idx;
     for (size_t i = 0; i < batch.size(); ++i) {
       if (status[i] != MPS_OK) continue;
       Plan* p = reinterpret_cast<Plan*>(adms[i].pp->plan);
@@ -328,8 +341,19 @@ void worker_main(Server* s) {
       if (batch[i]->ready && hipStreamWaitEvent(stream, batch[i]->ready, 0) != hipSuccess) st = MPS_E_HIP;
       if (st == MPS_OK) st = ensure_bins(p, &batch[i]->cat);
       if (st == MPS_OK) st = ensure_particles(p, batch[i]->cat.n_particles);
-      if (st == MPS_OK) st = enqueue_estimate(p, &batch[i]->cat, stream);
       status[i] = st;
+      if (st == MPS_OK) {
+        run_plans.push_back(p);
+        run_cats.push_back(batch[i]->cat);
+        run_idx.push_back(i);
+      }
+    }
+    if (!run_plans.empty()) {
+      const int st = fork ? enqueue_batch(run_plans.data(), run_cats.data(), static_cast<int>(run_plans.size()),
+                                          &stream, 1, &fork, &ws, nullptr)
+                          : MPS_E_HIP;
+      if (st != MPS_OK)
+        for (size_t i : run_idx) status[i] = st;
     }
     const bool synced = hipStreamSynchronize(stream) == hipSuccess;
     for (size_t i = 0; i < batch.size(); ++i) {
