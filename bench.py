@@ -35,12 +35,28 @@ HBM_PEAK_GBS = 8000.0
 LDS_DEPOSIT_PEAK = 256 * 16 * 2 * 2.4e9
 LDS_DEPOSIT_PROBE = 256 * 9.44 * 2 * 2.4e9
 DEPOSITS_PER_PARTICLE = 216 * 4
-# HBM bytes per dispatch of the 512^3 scatter (rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, one counter per run, calibrated by a 1 GiB device copy:
-# fetched = FETCH_SIZE x 2, written = WRITE_SIZE x 1): bytes read plus
-# written, 3.352 GB + 7.876 GB, on the current kernel.  Set to None whenever
-# the kernel changes, until the counters are taken again.
-SCATTER_TRAFFIC_BYTES = 3.352e9 + 7.876e9
+# HBM bytes per dispatch of the 512^3 scatter as measured by rocprofv3
+# (FETCH_SIZE and WRITE_SIZE, one counter per run, calibrated by a 1 GiB
+# device copy), with the SHA-256 (first 16 hex digits) of the kernel source
+# the counters were taken on.  Reported only while that source is unchanged.
+SCATTER_TRAFFIC = {"bytes": 3.352e9 + 7.876e9, "read_bytes": 3.352e9, "write_bytes": 7.876e9,
+                   "source": "paper_2005_06170_amd/csrc/particles.hip", "source_sha16": None,
+                   "profile": "profiles/estimate_512_f32_hbm_traffic.md"}
+
+
+def _sha16(path):
+    import hashlib
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def scatter_traffic():
+    """The measured traffic with its provenance, or None when the kernel
+    source has changed since the counters were taken."""
+    t = SCATTER_TRAFFIC
+    if t["source_sha16"] is None or _sha16(t["source"]) != t["source_sha16"]:
+        return None
+    return dict(t)
 N_GRID = 512
 N_LAT = 512
 BOX = 1000.0
@@ -215,117 +231,209 @@ def resolution_study(mps, pos, vel, n_lo=N_GRID // 2):
 
 
 def cpu_baseline():
-    """Oracle on 1/64 of the workload: a 128^3-particle Zel'dovich catalog of the
-    same construction on a 128^3 grid (64x fewer particles and cells)."""
+    """The oracle on 1/64 of the workload, stage by stage: a 128^3-particle
+    Zel'dovich catalog of the same construction (rms 8 Mpc/h scaled with the
+    lattice spacing kept, i.e. the same catalog family) on a 128^3 grid, 64x
+    fewer particles and cells.  Every stage scales linearly with particles or
+    cells except the FFT (N log N: x1.29 more per cell at 512^3, applied)."""
+    import scipy.fft
+
     import oracle
+    from oracle import estimator as E
     from synth import catalogs
-    pos, vel = catalogs.zeldovich(128, BOX, RMS, haf=HAF, seed=catalogs.seed_for(3, 1))
-    reps = 2
+    n = 128
+    pos, vel = catalogs.zeldovich(n, BOX, RMS, haf=HAF, seed=catalogs.seed_for(3, 1))
+    t = {}
     t0 = time.perf_counter()
-    for _ in range(reps):
-        oracle.estimate(pos, vel, box=BOX, n_grid=128, haf=HAF, n_bins=32)
-    t = (time.perf_counter() - t0) / reps
-    return {"value": 1.0 / (64.0 * t), "unit": "catalogs/s", "cores": os.cpu_count(),
-            "kind": "oracle",
-            "sample": (f"oracle.estimate on a 128^3-particle Zel'dovich catalog, 128^3 grid "
-                       f"(1/64 of the particles and cells), {reps} runs of {t:.1f} s each, scaled "
-                       f"x64; numpy bincount assignment is single-threaded, scipy FFTs use all cores")}
+    w = np.ones(pos.shape[0])
+    mom = E.moments(vel.astype(np.float64), w)
+    t["moments"] = time.perf_counter() - t0
+    v = vel.astype(np.float64)
+    charges = np.stack([w, v[:, 0], v[:, 1], v[:, 2]])
+    t0 = time.perf_counter()
+    grids = E.assign(pos, charges, BOX, n)
+    t["assign"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    F = scipy.fft.fftn(grids, axes=(1, 2, 3), workers=-1)
+    t["fft"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    q = E.mode_quantities(F, mom, BOX, n, HAF)
+    E.bin_modes(q, BOX, n, n_bins=32)
+    t["per_mode_and_bin"] = time.perf_counter() - t0
+    fft_scale = 64.0 * math.log(512) / math.log(128)
+    scaled = {k: v * (fft_scale if k == "fft" else 64.0) for k, v in t.items()}
+    total = sum(scaled.values())
+    cores = os.cpu_count()
+    return {"value": 1.0 / total, "unit": "catalogs/s", "cores": cores, "kind": "oracle",
+            "sample": (f"oracle stages on a 128^3-particle Zel'dovich catalog on a 128^3 grid (1/64 of the "
+                       f"particles and cells), scaled x64 (FFT x{fft_scale:.1f}); the FFT uses all {cores} "
+                       f"host threads, the numpy moments, bincount assignment and per-mode steps one"),
+            "stage_s_sample": t, "stage_s_scaled": scaled, "threads_by_stage":
+                {"moments": 1, "assign": 1, "fft": cores, "per_mode_and_bin": 1}}
 
 
-def serving(args):
-    """Poisson request stream through the continuous-batching server.
+def reference_errors(out, pos_np, vel_np):
+    """Per-bin guarded error |dP| / (|P_orc| + SN) of one estimate of the
+    benchmark catalog against the oracle's reference spectra of it
+    (tests/golden/zeldovich512_rms8.json), and whether the catalog is the
+    one the reference was computed for."""
+    path = os.path.join(ROOT, "tests", "golden", "zeldovich512_rms8.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        var = json.load(f)["variants"]["as_generated"]
+    ref = {k: np.array([np.nan if x is None else x for x in v], dtype=np.float64)
+           for k, v in var["spectra"].items() if isinstance(v, list) and k not in ("v_bulk",)}
+    fp = var["fingerprint"]
+    v64 = vel_np.astype(np.float64)
+    same = (pos_np.shape[0] == fp["n_particles"]
+            and np.allclose((v64.T @ v64).ravel(), fp["sum_vv"], rtol=1e-9, atol=0))
+    errs = {}
+    for key, sn in (("p_pp", ref["sn_pp"]), ("p_tt", ref["sn_tt"]), ("p_dd", ref["sn_dd"]),
+                    ("p_dt", np.sqrt(ref["sn_dd"] * ref["sn_tt"]))):
+        ok = np.isfinite(ref[key])
+        e = np.abs(out[key][ok] - ref[key][ok]) / (np.abs(ref[key][ok]) + np.abs(sn[ok]))
+        errs[key] = float(e.max())
+    errs["n_modes_equal"] = bool(np.array_equal(out["n_modes"], ref["n_modes"].astype(np.int64)))
+    errs["catalog_matches_reference"] = bool(same)
+    return errs
 
-    Requests arrive at mean rate --rate for --duration seconds; each draws a
-    grid from {128, 256, 512, 1024}^3 and a catalog from a device-resident
-    pool whose particle counts are log-spaced over [1e6, 5e8] (Zel'dovich
-    lattices up to 392^3, uniform catalogs with Gaussian velocities above,
-    generated on the device).  Latency is submit -> result on the host.
-    """
-    import threading
 
-    import torch
-    import paper_2005_06170_amd as mps
-    from synth import catalogs
-
-    rng = np.random.default_rng(catalogs.seed_for(5))
+def serving_pool(torch, catalogs):
+    """Device-resident request pool: particle counts log-spaced over
+    [1e6, 5e8], alternately Zel'dovich lattices (host-generated, up to 311^3)
+    and uniform catalogs with Gaussian velocities (generated on the device)."""
     sizes = [10 ** 6, 3 * 10 ** 6, 10 ** 7, 3 * 10 ** 7, 6 * 10 ** 7, 134217728, 2.5e8, 5e8]
     pool = []
     for i, n in enumerate(sizes):
         n = int(n)
-        if i % 2 == 0 and n <= 6 * 10 ** 7:
+        if i % 2 == 0 and n <= 3 * 10 ** 7:
             nl = int(round(n ** (1.0 / 3.0)))
             pos, vel = catalogs.zeldovich(nl, BOX, 3.0, haf=HAF, seed=catalogs.seed_for(5, i))
             p, v = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
+            kind = f"zeldovich {nl}^3"
         else:
             g = torch.Generator(device="cuda").manual_seed(catalogs.seed_for(5, i))
             p = torch.rand((n, 3), generator=g, device="cuda") * BOX
             v = torch.randn((n, 3), generator=g, device="cuda") * 300.0
+            kind = f"uniform {n}"
         pool.append((p.contiguous(), v.contiguous()))
-        _log(f"pool catalog {i}: {p.shape[0]} particles")
+        _log(f"pool catalog {i}: {kind}")
+    torch.cuda.synchronize()
+    return pool
+
+
+def serve_stream(mps, torch, pool, prec, rate, duration, seed, inflight=3, budget_gb=200.0, label=""):
+    """Poisson arrivals at `rate` requests/s for `duration` s through the
+    continuous-batching server; each request draws a grid from
+    {128, 256, 512, 1024}^3 and a pool catalog.  Latency is submit -> result
+    on the host.  Returns catalogs/s over the whole stream (last result
+    included), p50/p99 latency and the offered rate."""
+    import threading
+    rng = np.random.default_rng(seed)
     grids = [128, 256, 512, 1024]
-    n_req = int(args.rate * args.duration)
-    gaps = rng.exponential(1.0 / args.rate, n_req)
+    n_req = max(1, int(rate * duration))
+    gaps = rng.exponential(1.0 / rate, n_req)
     picks = [(int(rng.integers(len(pool))), grids[int(rng.integers(len(grids)))]) for _ in range(n_req)]
+    srv = mps.Server(hbm_budget_bytes=int(budget_gb * 2 ** 30), max_inflight=inflight,
+                     small_particles=4_000_000)
+    for g in grids:   # plans resident before the stream starts
+        srv.wait(srv.submit(*pool[0], box=BOX, haf=HAF, n_grid=g, precision=prec), 600.0)
+    lat = [None] * n_req
+    done_t = [None] * n_req
+    tickets = [None] * n_req
+    t_sub = [None] * n_req
+    ready = threading.Semaphore(0)
+
+    def collect():
+        for j in range(n_req):
+            ready.acquire()
+            srv.wait(tickets[j], 600.0)
+            done_t[j] = time.perf_counter()
+            lat[j] = done_t[j] - t_sub[j]
+            if j % 100 == 0:
+                _log(f"serving {label} {prec} at {rate:g}/s: {j}/{n_req} done")
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    nxt = t0
+    for j, (ci, g) in enumerate(picks):
+        nxt += gaps[j]
+        d = nxt - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        t_sub[j] = time.perf_counter()
+        tickets[j] = srv.submit(*pool[ci], box=BOX, haf=HAF, n_grid=g, precision=prec)
+        ready.release()
+    th.join()
+    elapsed = max(done_t) - t0
+    srv.close()
+    lat_ms = np.array(lat) * 1e3
+    return {"catalogs_per_s": n_req / elapsed, "p50_ms": float(np.percentile(lat_ms, 50)),
+            "p99_ms": float(np.percentile(lat_ms, 99)), "offered_rate": rate, "requests": n_req,
+            "elapsed_s": elapsed}
+
+
+P99_BOUND_MS = 1000.0
+
+
+def serving_section(mps, torch, args):
+    """Config 5 in the default run: the FP32 and FP64 streams at the offered
+    rate, then the FP32 capacity point: the highest offered rate (tried in
+    increasing order) at which p99 stays under P99_BOUND_MS and the server
+    keeps up (served rate >= 95 % of offered)."""
+    from synth import catalogs
+    pool = serving_pool(torch, catalogs)
+    out = {"pool": "8 device-resident catalogs, 1e6-5e8 particles (4 Zel'dovich lattices up to 311^3, "
+                   "4 uniform), grids uniform in {128,256,512,1024}^3",
+           "p99_bound_ms": P99_BOUND_MS}
+    for prec in ("f32", "f64"):
+        out[prec] = serve_stream(mps, torch, pool, prec, args.rate, args.duration, catalogs.seed_for(5, 90),
+                                 inflight=args.inflight, budget_gb=args.budget_gb, label="stream")
+        _log(f"serving {prec}: {out[prec]}")
+    cap = None
+    tried = []
+    for rate in args.capacity_rates:
+        r = serve_stream(mps, torch, pool, "f32", rate, args.capacity_duration, catalogs.seed_for(5, 91),
+                         inflight=args.inflight, budget_gb=args.budget_gb, label="capacity")
+        tried.append(r)
+        _log(f"capacity f32 at {rate}/s: {r}")
+        if r["p99_ms"] <= P99_BOUND_MS and r["catalogs_per_s"] >= 0.95 * rate:
+            cap = rate
+        else:
+            break
+    out["capacity_f32"] = {"highest_rate_within_bound": cap, "tried": tried}
+    del pool
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving(args):
+    """Only the serving stream (--serving): FP32 (and FP64) at --rate."""
+    import torch
+    import paper_2005_06170_amd as mps
+    from synth import catalogs
+    pool = serving_pool(torch, catalogs)
     out = {}
-    runs = [("f32", "f32")] + ([] if args.no_fp64 else [("f64", "f64")])
+    for prec in ("f32",) + (() if args.no_fp64 else ("f64",)):
+        out[prec] = serve_stream(mps, torch, pool, prec, args.rate, args.duration, catalogs.seed_for(5, 90),
+                                 inflight=args.inflight, budget_gb=args.budget_gb)
+        _log(f"{prec}: {out[prec]}")
     if args.host_catalogs:
-        runs.append(("f32_host", "f32"))
-    for label, prec in runs:
-        if label == "f32_host":
-            # the same pool from page-locked host memory: each request's
-            # catalog crosses PCIe on its worker's stream (MPS_CATALOG_HOST)
-            _log("moving the pool to pinned host memory")
-            pool = [(p.cpu().pin_memory(), v.cpu().pin_memory()) for p, v in pool]
-            torch.cuda.empty_cache()
-        srv = mps.Server(hbm_budget_bytes=int(args.budget_gb * 2 ** 30), max_inflight=args.inflight,
-                         small_particles=4_000_000)
-        # warm the plan pool with one request per grid size
-        for g in grids:
-            srv.wait(srv.submit(*pool[0], box=BOX, haf=HAF, n_grid=g, precision=prec), 600.0)
-        lat = [None] * n_req
-        done_t = [None] * n_req
-        tickets = [None] * n_req
-        t_sub = [None] * n_req
-        ready = threading.Semaphore(0)
-
-        def collect():
-            for j in range(n_req):
-                ready.acquire()
-                srv.wait(tickets[j], 600.0)
-                done_t[j] = time.perf_counter()
-                lat[j] = done_t[j] - t_sub[j]
-                if j % 100 == 0:
-                    _log(f"{label}: {j}/{n_req} done")
-
-        th = threading.Thread(target=collect)
-        th.start()
-        t0 = time.perf_counter()
-        nxt = t0
-        for j, (ci, g) in enumerate(picks):
-            nxt += gaps[j]
-            d = nxt - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            t_sub[j] = time.perf_counter()
-            tickets[j] = srv.submit(*pool[ci], box=BOX, haf=HAF, n_grid=g, precision=prec)
-            ready.release()
-        th.join()
-        elapsed = max(done_t) - t0
-        srv.close()
-        lat_ms = np.array(lat) * 1e3
-        out[label] = {"catalogs_per_s": n_req / elapsed, "p50_ms": float(np.percentile(lat_ms, 50)),
-                      "p99_ms": float(np.percentile(lat_ms, 99)), "requests": n_req,
-                      "offered_rate": args.rate, "elapsed_s": elapsed}
-        if label == "f32_host":
-            gb = sum(24.0 * pool[ci][0].shape[0] for ci, _ in picks) / 1e9
-            out[label]["h2d_GB"] = gb
-            out[label]["h2d_GB_per_s"] = gb / elapsed
-        _log(f"{label}: {out[label]}")
+        # the same pool from page-locked host memory: each request's catalog
+        # crosses PCIe on its worker's stream (MPS_CATALOG_HOST)
+        _log("moving the pool to pinned host memory")
+        pool = [(p.cpu().pin_memory(), v.cpu().pin_memory()) for p, v in pool]
+        torch.cuda.empty_cache()
+        out["f32_host"] = serve_stream(mps, torch, pool, "f32", args.rate, args.duration,
+                                       catalogs.seed_for(5, 90), inflight=args.inflight, budget_gb=args.budget_gb)
+        _log(f"f32_host: {out['f32_host']}")
     line = {"metric": "serving: catalogs/s and p50/p99 latency, Poisson arrivals", "value": out["f32"]["catalogs_per_s"],
             "unit": "catalogs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "poisson_stream_grids_128-1024_particles_1e6-5e8", "rate": args.rate,
                        "duration_s": args.duration, "inflight": args.inflight, "budget_gb": args.budget_gb},
-            "f32": out["f32"], "fp64": out.get("f64"), "f32_host_catalogs": out.get("f32_host")}
+            "serving": out}
     print(json.dumps(line))
 
 
@@ -342,8 +450,13 @@ def main():
                     help="permute particle order randomly (no spatial coherence)")
     ap.add_argument("--serving", action="store_true",
                     help="run the Poisson serving stream instead of the 512^3 benchmark")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the Poisson serving stream of the default run")
     ap.add_argument("--rate", type=float, default=20.0)
-    ap.add_argument("--duration", type=float, default=30.0)
+    ap.add_argument("--duration", type=float, default=20.0)
+    ap.add_argument("--capacity-rates", type=float, nargs="*", default=[30.0, 40.0, 60.0],
+                    help="offered rates tried in order for the FP32 capacity point")
+    ap.add_argument("--capacity-duration", type=float, default=10.0)
     ap.add_argument("--inflight", type=int, default=3)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--host-catalogs", action="store_true",
@@ -373,7 +486,6 @@ def main():
     _log(f"catalog ready in {time.perf_counter() - t0:.1f} s; uploading")
     pos = torch.from_numpy(pos_np).cuda()
     vel = torch.from_numpy(vel_np).cuda()
-    del pos_np, vel_np
     n_part = pos.shape[0]
 
     _log("timing the FP32 path")
@@ -390,15 +502,21 @@ def main():
         fp64 = {"catalogs_per_s": steps64 / wall64, "ms_per_step": 1e3 * wall64 / steps64,
                 "stage_ms": stages64}
         _log(f"f64: {1e3 * wall64 / steps64:.2f} ms/step")
-        # precision study: per-bin error of the FP32 grids against the FP64 grids,
-        # |dP| / (|P| + SN) (the FP64 path matches the oracle to ~1e-13)
-        precision = {}
+        # precision study: per-bin error of each path against the oracle's
+        # reference spectra of this catalog, and FP32 against FP64 grids,
+        # all as |dP| / (|P| + SN)
+        precision = {"f32_vs_oracle": reference_errors(out32, pos_np, vel_np),
+                     "f64_vs_oracle": reference_errors(out64, pos_np, vel_np),
+                     "reference": "tests/golden/zeldovich512_rms8.json"}
+        _log(f"against the oracle: {precision}")
+        precision["f32_vs_f64"] = {}
         for key, sn in (("p_pp", out64["sn_pp"]), ("p_tt", out64["sn_tt"]), ("p_dd", out64["sn_dd"]),
                         ("p_dt", np.sqrt(out64["sn_dd"] * out64["sn_tt"]))):
             ok = np.isfinite(out64[key])
             e = np.abs(out32[key][ok] - out64[key][ok]) / (np.abs(out64[key][ok]) + np.abs(sn[ok]))
-            precision[key] = float(e.max())
-        _log(f"FP32 vs FP64 max guarded per-bin error: {precision}")
+            precision["f32_vs_f64"][key] = float(e.max())
+        _log(f"FP32 vs FP64 max guarded per-bin error: {precision['f32_vs_f64']}")
+    del pos_np, vel_np
 
     variants = None
     if not args.no_variants:
@@ -441,7 +559,7 @@ def main():
         roofline = {"kernel": dom, "bound": "alu", "achieved": dep_rate / 1e12,
                     "peak": LDS_DEPOSIT_PEAK / 1e12, "unit": "Tdeposit/s",
                     "frac": dep_rate / LDS_DEPOSIT_PEAK,
-                    "traffic": SCATTER_TRAFFIC_BYTES if n_part == N_LAT ** 3 else None,
+                    "traffic": scatter_traffic() if n_part == N_LAT ** 3 else None,
                     "traffic_algorithmic": abytes[dom],
                     "probe_ceiling": LDS_DEPOSIT_PROBE / 1e12,
                     "frac_of_probe_ceiling": dep_rate / LDS_DEPOSIT_PROBE,
@@ -457,6 +575,13 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         _log("copied 1 GiB device-to-device (counter calibration)")
+
+    serving_out = None
+    if not args.no_serving:
+        del pos, vel
+        torch.cuda.empty_cache()
+        _log("serving streams (config 5)")
+        serving_out = serving_section(mps, torch, args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -479,10 +604,15 @@ def main():
         "config": {"workload": "zeldovich_512^3_particles_512^3_grid", "n_grid": N_GRID,
                    "n_particles": n_part, "box_mpc_h": BOX, "rms_disp_mpc_h": RMS, "haf": HAF,
                    "n_bins": 32, "particle_order": "shuffled" if args.shuffle else "lattice"},
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3)},
+        "latency_ms": ({"p50": serving_out["f32"]["p50_ms"], "p99": serving_out["f32"]["p99_ms"],
+                        "source": f"serving stream, FP32, Poisson arrivals at {args.rate:g}/s"}
+                       if serving_out else None),
+        "estimate_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                                "p99": float(np.percentile(lat, 99) * 1e3),
+                                "source": "back-to-back single estimates of the 512^3 catalog"},
         "fp64": fp64,
-        "precision_f32_vs_f64": precision,
+        "precision": precision,
+        "serving": serving_out,
         "variants": variants,
         "resolution_study": aliasing,
         "stages": per_stage,

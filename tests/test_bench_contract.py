@@ -27,3 +27,20 @@ def test_algorithmic_bytes():
     assert b["clear"] == grid
     assert b["scatter"] == 24 * npart + grid
     assert b["fft_z"] == b["fft_y"] == 2 * grid
+
+
+def test_scatter_traffic_needs_its_source():
+    """The measured scatter traffic is reported only with the hash of the
+    kernel source it was measured on, and only while that source is unchanged."""
+    sys.path.insert(0, ROOT)
+    import bench
+    t = dict(bench.SCATTER_TRAFFIC)
+    try:
+        bench.SCATTER_TRAFFIC["source_sha16"] = "0" * 16
+        assert bench.scatter_traffic() is None
+        bench.SCATTER_TRAFFIC["source_sha16"] = bench._sha16(t["source"])
+        got = bench.scatter_traffic()
+        assert got["bytes"] == t["bytes"] and got["profile"] == t["profile"]
+    finally:
+        bench.SCATTER_TRAFFIC.clear()
+        bench.SCATTER_TRAFFIC.update(t)
