@@ -196,14 +196,14 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
   mps_plan* created = nullptr;
   if (adm->action == Admission::kCreate) {
     st = mps_plan_create(&created, pp->n_grid, pp->prec);
-    if (st == MPS_OK) st = mps_plan_reserve(created, adm->cap);
+    if (st == MPS_OK && adm->cap > 0) st = mps_plan_reserve(created, adm->cap);
     if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(created), adm->host_cap);
     if (st != MPS_OK && created) {
       mps_plan_destroy(created);
       created = nullptr;
     }
   } else if (adm->action == Admission::kGrow) {
-    st = mps_plan_reserve(pp->plan, adm->cap);
+    if (adm->cap > 0) st = mps_plan_reserve(pp->plan, adm->cap);
     if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(pp->plan), adm->host_cap);
   }
   lk.lock();
@@ -244,6 +244,34 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
   return st;
 }
 
+// A worker's particle workspace (sorted records and host-catalog staging),
+// lent to the plan of each large request it runs, so that plans of large
+// requests hold only their grids and tables and a plan pool does not keep
+// one catalog-sized buffer per plan.  Grows (never shrinks); its bytes count
+// against the budget from the moment they are reserved.
+struct ParticleSpace {
+  float4* sorted = nullptr;
+  int64_t cap = 0;
+  float* host = nullptr;
+  int64_t host_cap = 0;
+  size_t bytes = 0;             // allocated
+  size_t reserved = 0;          // counted in the budget (>= bytes)
+  int64_t want_cap = 0, want_host = 0;
+  static size_t size_of(int64_t cap, int64_t host_cap) {
+    return static_cast<size_t>(cap) * 2 * sizeof(float4) + kHostStageBytes * static_cast<size_t>(host_cap);
+  }
+};
+
+// Round a particle count up so that a workspace is not regrown for every
+// slightly larger catalog: to a multiple of 2^20, and at least 1.5x the old
+// capacity when it must grow.
+int64_t grown(int64_t need, int64_t old) {
+  if (need <= old) return old;
+  int64_t c = need > old + old / 2 ? need : old + old / 2;
+  c = (c + (1 << 20) - 1) & ~static_cast<int64_t>((1 << 20) - 1);
+  return c < 0x7fffffffll ? c : 0x7fffffffll;
+}
+
 void finish(Server* s, const std::shared_ptr<Request>& r, int status) {
   r->status = status;
   r->done = true;
@@ -260,6 +288,8 @@ void worker_main(Server* s) {
   hipEvent_t fork = nullptr;
   if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) fork = nullptr;
   BatchWorkspace ws;  // this worker's multi-catalog scatter buffers
+  ParticleSpace wp;   // this worker's particle workspace for large requests
+  std::vector<std::pair<mps_plan*, size_t>> dead;  // evicted plans not yet freed
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     std::vector<std::shared_ptr<Request>> batch;
@@ -276,6 +306,10 @@ void worker_main(Server* s) {
         if (ws.d_queue) (void)hipFree(ws.d_queue);
         if (ws.h_cats) (void)hipHostFree(ws.h_cats);
         if (ws.h_starts) (void)hipHostFree(ws.h_starts);
+        if (wp.sorted) (void)hipFree(wp.sorted);
+        if (wp.host) (void)hipFree(wp.host);
+        lk.lock();
+        s->used -= wp.reserved;
         return;
       }
       size_t pos = 0;
@@ -283,8 +317,44 @@ void worker_main(Server* s) {
         const auto r = *it;
         int st = MPS_OK;
         Admission adm;
-        if (!admit_plan(s, r->n_grid, r->prec, r->cat.n_particles, (r->cat.flags & MPS_CATALOG_HOST) != 0, &adm,
-                        &st)) {
+        const bool large = r->cat.n_particles > s->small;
+        const bool host = (r->cat.flags & MPS_CATALOG_HOST) != 0;
+        if (large) {
+          // the plan holds its grids only; the records live in this worker's
+          // workspace, reserved (and grown if needed) first
+          const int64_t np = r->cat.n_particles;
+          if (plan_bytes(r->n_grid, r->prec, 0, 0) + ParticleSpace::size_of(np, host ? np : 0) > s->budget) {
+            it = s->queue.erase(it);
+            finish(s, r, MPS_E_TOOBIG);
+            s->cv_done.notify_all();
+            continue;
+          }
+          const int64_t cap = grown(np, wp.want_cap > wp.cap ? wp.want_cap : wp.cap);
+          const int64_t hcap = host ? grown(np, wp.want_host > wp.host_cap ? wp.want_host : wp.host_cap)
+                                    : (wp.want_host > wp.host_cap ? wp.want_host : wp.host_cap);
+          size_t need = ParticleSpace::size_of(cap, hcap);
+          if (need + plan_bytes(r->n_grid, r->prec, 0, 0) > s->budget)
+            need = ParticleSpace::size_of(np, host ? np : 0);  // no headroom: exactly what it needs
+          if (need > wp.reserved) {
+            Admission wadm;
+            if (!make_room(s, need - wp.reserved, nullptr, &wadm)) {
+              if (r->passed >= kMaxPassed) break;
+              ++it;
+              continue;
+            }
+            s->used += need - wp.reserved;
+            wp.reserved = need;
+            wp.want_cap = need == ParticleSpace::size_of(cap, hcap) ? cap : np;
+            wp.want_host = need == ParticleSpace::size_of(cap, hcap) ? hcap : (host ? np : 0);
+            for (auto& v : wadm.victims) adm.victims.push_back(v);  // destroyed with the plan's victims
+          }
+        }
+        Admission padm;
+        if (!admit_plan(s, r->n_grid, r->prec, large ? 0 : r->cat.n_particles, !large && host, &padm, &st)) {
+          // plans a workspace reservation evicted are freed before this
+          // worker waits (their bytes stay counted until then)
+          for (auto& v : adm.victims) dead.push_back(v);
+          adm.victims.clear();
           if (st != MPS_OK) {  // can never run
             it = s->queue.erase(it);
             finish(s, r, st);
@@ -295,6 +365,8 @@ void worker_main(Server* s) {
           ++it;
           continue;
         }
+        for (auto& v : adm.victims) padm.victims.push_back(v);
+        adm = std::move(padm);
         // every older request still queued has been passed over once more
         for (auto jt = s->queue.begin(); jt != it; ++jt) ++(*jt)->passed;
         batch.push_back(r);
@@ -319,13 +391,77 @@ void worker_main(Server* s) {
         }
         break;
       }
-      if (batch.empty()) s->cv_work.wait(lk);
+      if (batch.empty()) {
+        if (!dead.empty()) {
+          std::vector<std::pair<mps_plan*, size_t>> d;
+          d.swap(dead);
+          lk.unlock();
+          size_t freed = 0;
+          for (auto& v : d) {
+            mps_plan_destroy(v.first);
+            freed += v.second;
+          }
+          lk.lock();
+          s->used -= freed;
+          s->cv_work.notify_all();
+          continue;
+        }
+        s->cv_work.wait(lk);
+      }
+    }
+    if (!dead.empty()) {  // freed outside the lock with the first admission's victims
+      for (auto& v : dead) adms[0].victims.push_back(v);
+      dead.clear();
     }
     // plan creation, growth and eviction run outside the lock
     std::vector<int> status(batch.size(), MPS_OK);
     for (size_t i = 0; i < batch.size(); ++i)
       if (!adms[i].victims.empty() || adms[i].action != Admission::kReady) status[i] = carry_out(s, &adms[i], lk);
     lk.unlock();
+
+    // a large request borrows the worker's particle workspace (allocated or
+    // grown here, outside the lock)
+    struct Lent {
+      Plan* p;
+      float4* sorted;
+      int64_t cap;
+      float* host;
+      int64_t host_cap;
+    };
+    std::vector<Lent> lent;
+    for (size_t i = 0; i < batch.size(); ++i) {
+      if (status[i] != MPS_OK || batch[i]->cat.n_particles <= s->small) continue;
+      if (wp.cap < wp.want_cap || wp.host_cap < wp.want_host) {
+        if (wp.sorted) (void)hipFree(wp.sorted);
+        if (wp.host) (void)hipFree(wp.host);
+        wp.sorted = nullptr;
+        wp.host = nullptr;
+        wp.cap = wp.host_cap = 0;
+        wp.bytes = 0;
+        bool ok = hipMalloc(reinterpret_cast<void**>(&wp.sorted),
+                            static_cast<size_t>(wp.want_cap) * 2 * sizeof(float4)) == hipSuccess;
+        if (ok && wp.want_host > 0)
+          ok = hipMalloc(reinterpret_cast<void**>(&wp.host), kHostStageBytes * static_cast<size_t>(wp.want_host)) ==
+               hipSuccess;
+        if (ok) {
+          wp.cap = wp.want_cap;
+          wp.host_cap = wp.want_host;
+          wp.bytes = ParticleSpace::size_of(wp.cap, wp.host_cap);
+        } else {
+          if (wp.sorted) (void)hipFree(wp.sorted);
+          wp.sorted = nullptr;
+          wp.host = nullptr;
+          status[i] = MPS_E_NOMEM;
+          continue;
+        }
+      }
+      Plan* p = reinterpret_cast<Plan*>(adms[i].pp->plan);
+      lent.push_back({p, p->sorted, p->sorted_cap, p->host_stage, p->host_cap});
+      p->sorted = wp.sorted;
+      p->sorted_cap = wp.cap;
+      p->host_stage = wp.host;
+      p->host_cap = wp.host_cap;
+    }
 
     // run the batch: each request's stages start after its catalog is ready
     // on the submitter's stream; the requests go through the multi-catalog
@@ -360,6 +496,12 @@ void worker_main(Server* s) {
       if (status[i] == MPS_OK)
         status[i] = synced ? unpack(reinterpret_cast<Plan*>(adms[i].pp->plan), &batch[i]->cat, batch[i]->out)
                            : MPS_E_HIP;
+    }
+    for (const Lent& l : lent) {  // the plans get their own buffers back
+      l.p->sorted = l.sorted;
+      l.p->sorted_cap = l.cap;
+      l.p->host_stage = l.host;
+      l.p->host_cap = l.host_cap;
     }
 
     lk.lock();
