@@ -692,21 +692,6 @@ __device__ __forceinline__ int64_t next_item(const TileQueues& tq, int64_t n_ite
   return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
-// One line of the separable bound convolution: out[g] = sum_j k_j in[g - j]
-// over taps j = -2..3, with in = 0 outside the E-long line.
-template <int E, int NTAP>
-__device__ __forceinline__ void bound_line(const float (&in)[E], const TapBound& kb, float (&out)[E]) {
-  constexpr int H = kHaloLo<NTAP>;
-#pragma unroll
-  for (int g = 0; g < E; ++g) {
-    float o = 0.f;
-#pragma unroll
-    for (int j = -H; j < NTAP - H; ++j)
-      if (g - j >= 0 && g - j < E) o = fmaf(kb.k[j + H], in[g - j], o);
-    out[g] = o;
-  }
-}
-
 // FP32 grids.  A persistent grid of one workgroup per CU walks the occupied
 // T^3 tiles.  LDS holds the four fields over the tile plus a halo (2 cells
 // below and 3 above along each axis for taps -2..3; 1 and 2 for the cubic
@@ -787,9 +772,15 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
 
   // largest tap-weight bound, cubed: bounds |wx wy wz| of every deposit
   float kmax = 0.f;
+  double ksum = 0.0;
 #pragma unroll
-  for (int j = 0; j < NTAP; ++j) kmax = fmaxf(kmax, kb.k[j]);
+  for (int j = 0; j < NTAP; ++j) {
+    kmax = fmaxf(kmax, kb.k[j]);
+    ksum += static_cast<double>(kb.k[j]);
+  }
   const float kmax3 = kmax * kmax * kmax;
+  // a cell receives from the 6^3 cells around it: A(g) <= max_c C(c) (sum_j k_j)^3
+  const double ksum3 = ksum * ksum * ksum * 1.00001;
   if (t < 6) bb[t] = t < 3 ? E : -1;
   int64_t item = next_item<NT, kMulti>(tq, n_items, starts, n_cats, &s_tile);
   for (int i = t; i < kNumFields * VOL; i += NT) acc[i] = 0;
@@ -881,50 +872,18 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       add_cell_sums(a, rec_vel<kW>(sorted, static_cast<int64_t>(p)), tap_origin<TS, NTAP>(a, kp, ox, oy, oz) + kCellOff);
     }
     __syncthreads();
-    // bound convolution along z (lines of the tile's interior x, y), then y
-    // (interior x), as floats in place
-    for (int rr = t; rr < kBoundFields * TS * TS; rr += NT) {
-      const int f = rr / (TS * TS);
-      const int x = H + (rr / TS) % TS, y = H + rr % TS;
-      int* line = acc + f * VOL + (x * E + y) * E;
-      float in[E], out[E];
-#pragma unroll
-      for (int g = 0; g < E; ++g) in[g] = static_cast<float>(static_cast<unsigned>(line[g]));
-      bound_line<E, NTAP>(in, kb, out);
-#pragma unroll
-      for (int g = 0; g < E; ++g) line[g] = __float_as_int(out[g]);
-    }
-    __syncthreads();
-    for (int rr = t; rr < kBoundFields * TS * E; rr += NT) {
-      const int f = rr / (TS * E);
-      const int x = H + (rr / E) % TS, z = rr % E;
-      int* line = acc + f * VOL + x * E * E + z;
-      float in[E], out[E];
-#pragma unroll
-      for (int g = 0; g < E; ++g) in[g] = __int_as_float(line[g * E]);
-      bound_line<E, NTAP>(in, kb, out);
-#pragma unroll
-      for (int g = 0; g < E; ++g) line[g * E] = __float_as_int(out[g]);
-    }
-    __syncthreads();
-    // along x: the maximum only; the lines are cleared for the deposits
+    // the largest cell sum of each bound field (only the tile's own cells
+    // hold sums), clearing the sums for the deposits
     float amax[kBoundFields] = {0.f, 0.f};
-    for (int rr = t; rr < kBoundFields * E * E; rr += NT) {
-      const int f = rr / (E * E);
-      int* line = acc + f * VOL + rr % (E * E);
-      float in[E], out[E];
-#pragma unroll
-      for (int g = 0; g < E; ++g) {
-        in[g] = __int_as_float(line[g * E * E]);
-        line[g * E * E] = 0;
-      }
-      bound_line<E, NTAP>(in, kb, out);
-      float m = 0.f;
-#pragma unroll
-      for (int g = 0; g < E; ++g) m = fmaxf(m, out[g]);
+    for (int rr = t; rr < kBoundFields * TS * TS * TS; rr += NT) {
+      const int f = rr / (TS * TS * TS);
+      const int c = rr % (TS * TS * TS);
+      int* cell = acc + f * VOL + ((H + c / (TS * TS)) * E + H + (c / TS) % TS) * E + H + c % TS;
+      const float v = static_cast<float>(static_cast<unsigned>(*cell));
+      *cell = 0;
 #pragma unroll
       for (int ff = 0; ff < kBoundFields; ++ff)
-        if (ff == f) amax[ff] = fmaxf(amax[ff], m);
+        if (ff == f) amax[ff] = fmaxf(amax[ff], v);
     }
 #pragma unroll
     for (int f = 0; f < kBoundFields; ++f) {
@@ -945,7 +904,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         // sum bound of a sparse tile); room for the rounding errors of up to
         // cnt deposits per cell
         const double bound = sparse ? static_cast<double>(mx) * static_cast<double>(kmax3) * 1.0001
-                                    : static_cast<double>(mx) * 1.00001 / static_cast<double>(csc[t]);
+                                    : static_cast<double>(mx) * ksum3 / static_cast<double>(csc[t]);
         const double room = 0.99 * 2147483648.0 - 0.5 * static_cast<double>(cnt) - 64.0;
         const double scl = (mx > 0.f && (sparse || csc[t] > 0.f)) ? fmin(room / bound, 1e30) : 0.0;
         scale_s[t] = static_cast<float>(scl);
