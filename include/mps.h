@@ -182,6 +182,16 @@ typedef struct {
 #define MPS_MAX_MU_CELLS 512   /* n_bins * n_mu */
 #define MPS_MAX_DIV 8          /* sub-cubes per axis in mps_estimate_subcubes */
 #define MPS_MAX_SUBCUBES 512   /* MPS_MAX_DIV^3 */
+/* MPS_F32 with the truncated BL3 kernel on grids of N >= MPS_SCATTER_MIN_GRID:
+ * the scatter's form follows the mean number of particles per 16^3 tile,
+ * m = n_particles / (N/16)^3 (see mps_plan_create): m <=
+ * MPS_SCATTER_GATHER_MAX_MEAN, the owner-computes scatter; else m <=
+ * MPS_SCATTER_HALO_MAX_MEAN, the halo scatter (its halo buffer, 5165 x 16
+ * bytes per tile, is allocated on first use and counted by mps_footprint);
+ * else, and on smaller grids, the atomic scatter. */
+#define MPS_SCATTER_MIN_GRID 128
+#define MPS_SCATTER_GATHER_MAX_MEAN 256
+#define MPS_SCATTER_HALO_MAX_MEAN 2048
 
 typedef struct mps_plan mps_plan;
 typedef struct mps_server mps_server;
@@ -193,7 +203,14 @@ typedef struct mps_server mps_server;
  *
  * prec is the grid and FFT precision.  MPS_F32: the assignment sums in
  * 32-bit fixed point scaled per tile from a bound on every cell, so the
- * grid carries FP32-level resolution.  MPS_F64: the assignment sums in
+ * grid carries FP32-level resolution.  Each 16^3 tile deposits its
+ * particles over itself and a halo (2 cells below, 3 above per axis) and
+ * adds the block to the grid with FP32 atomics (the atomic scatter), or
+ * stores its own cells and its halo in a halo buffer, a fix-up pass adding
+ * the neighbours' halos to each cell in a fixed order (the halo scatter,
+ * deterministic), or gathers the particles whose taps reach it and stores
+ * its own cells (the owner-computes scatter, deterministic); see
+ * MPS_SCATTER_GATHER_MAX_MEAN.  MPS_F64: the assignment sums in
  * 64-bit fixed point with a unit of 2^-50 of the largest possible deposit
  * (coarser only for tiles of more than 4096 particles), FP64-level.  The
  * moments, tables, per-mode estimator and shell sums are FP64 in both. */
@@ -201,7 +218,9 @@ int mps_plan_create(mps_plan** out, int n_grid, mps_precision prec);
 int mps_plan_destroy(mps_plan* plan);
 
 /* Pre-allocate workspace for catalogs of up to max_particles particles so
- * that later calls allocate nothing. */
+ * that later calls allocate nothing: the sorted records and, for MPS_F32
+ * plans on which such a catalog can take the halo scatter, the halo buffer
+ * (see MPS_SCATTER_GATHER_MAX_MEAN). */
 int mps_plan_reserve(mps_plan* plan, int64_t max_particles);
 
 /* Device bytes a plan of this shape holds when used for n_particles. */

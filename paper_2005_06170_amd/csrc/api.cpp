@@ -48,6 +48,7 @@ void release(Plan* p) {
   dfree(p->tile_offset);
   dfree(p->tile_cursor);
   dfree(p->tile_queue);
+  dfree(p->halo);
   dfree(p->moment_partials);
   dfree(p->d_header);
   for (int k = 0; k < kNumKernels; ++k) {
@@ -122,6 +123,20 @@ int ensure_particles(Plan* p, int64_t np) {
   return MPS_OK;
 }
 
+int ensure_halo(Plan* p) {
+  if (p->halo) return MPS_OK;
+  const size_t b = halo_bytes(p->n, p->prec);
+  if (b == 0) return MPS_OK;
+  return dalloc(&p->halo, b) == hipSuccess ? MPS_OK : MPS_E_NOMEM;
+}
+
+int ensure_scatter_space(Plan* p, const mps_catalog* c) {
+  const int st = ensure_particles(p, c->n_particles);
+  if (st != MPS_OK) return st;
+  if (kernel_id(c->flags) == 0 && scatter_form_for(p->n, p->prec, c->n_particles) == kFormHalo) return ensure_halo(p);
+  return MPS_OK;
+}
+
 int ensure_host_stage(Plan* p, int64_t np) {
   if (np <= p->host_cap) return MPS_OK;
   dfree(p->host_stage);
@@ -167,7 +182,8 @@ int enqueue_prescatter(Plan* p, const mps_catalog* c0, hipStream_t s, mps_catalo
   mark(p, 2, s);
   MPS_TRY(launch_permute(p, used, s));
   mark(p, 3, s);
-  MPS_TRY(launch_clear_grid(p, s));
+  // only the atomic scatter adds into the grid; the other forms store every cell
+  if (scatter_form(p, used) == kFormAtomic) MPS_TRY(launch_clear_grid(p, s));
   mark(p, 4, s);
   return MPS_OK;
 }
@@ -220,10 +236,11 @@ int BatchWorkspace::ensure(int n) {
   cap = 0;
   const int c = n < 64 ? 64 : n;
   bool ok = hipMalloc(reinterpret_cast<void**>(&d_cats), sizeof(ScatterCat) * c) == hipSuccess;
-  ok = ok && hipMalloc(reinterpret_cast<void**>(&d_starts), sizeof(int64_t) * (c + 2)) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&d_starts), sizeof(int64_t) * (c + kScatterGroups)) == hipSuccess;
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h_cats), sizeof(ScatterCat) * c, hipHostMallocDefault) ==
                  hipSuccess;
-  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h_starts), sizeof(int64_t) * (c + 2), hipHostMallocDefault) ==
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h_starts), sizeof(int64_t) * (c + kScatterGroups),
+                           hipHostMallocDefault) ==
                  hipSuccess;
   if (!d_queue) ok = ok && hipMalloc(reinterpret_cast<void**>(&d_queue), sizeof(uint32_t) * 8) == hipSuccess;
   if (!ok) return MPS_E_NOMEM;
@@ -251,18 +268,22 @@ int enqueue_batch(Plan* const* plans, const mps_catalog* cats, int n, hipStream_
     MPS_TRY(hipEventRecord(events[l], lanes[l]));
     MPS_TRY(hipStreamWaitEvent(lanes[0], events[l], 0));
   }
-  // eligible catalogs, without weights first, then with
-  std::vector<int> multi[2];
+  // the multi-catalog groups (see scatter_group); the others' own launches
+  constexpr int kGroups = kScatterGroups;
+  std::vector<int> multi[kGroups];
   for (int i = 0; i < n; ++i) {
-    if (scatter_multi_eligible(plans[i], &used[i])) multi[used[i].weight ? 1 : 0].push_back(i);
+    const int g = scatter_group(plans[i], &used[i]);
+    if (g >= 0) multi[g].push_back(i);
     else MPS_TRY(launch_scatter_impl(plans[i], &used[i], lanes[0], 0));
   }
-  const int nm = static_cast<int>(multi[0].size() + multi[1].size());
+  int nm = 0;
+  for (int g = 0; g < kGroups; ++g) nm += static_cast<int>(multi[g].size());
   if (nm > 0) {
+    // descriptors of group g at [k_g, k_g + m_g), its prefix sums at [k_g + g, k_g + g + m_g]
     if ((st = ws->ensure(nm)) != MPS_OK) return st;
     int k = 0;
-    for (int g = 0; g < 2; ++g) {
-      int64_t* starts = ws->h_starts + (g == 0 ? 0 : multi[0].size() + 1);
+    for (int g = 0; g < kGroups; ++g) {
+      int64_t* starts = ws->h_starts + k + g;
       starts[0] = 0;
       for (size_t j = 0; j < multi[g].size(); ++j) {
         Plan* p = plans[multi[g][j]];
@@ -272,14 +293,14 @@ int enqueue_batch(Plan* const* plans, const mps_catalog* cats, int n, hipStream_
       k += static_cast<int>(multi[g].size());
     }
     MPS_TRY(hipMemcpyAsync(ws->d_cats, ws->h_cats, sizeof(ScatterCat) * nm, hipMemcpyHostToDevice, lanes[0]));
-    MPS_TRY(hipMemcpyAsync(ws->d_starts, ws->h_starts, sizeof(int64_t) * (nm + 2), hipMemcpyHostToDevice, lanes[0]));
+    MPS_TRY(hipMemcpyAsync(ws->d_starts, ws->h_starts, sizeof(int64_t) * (nm + kGroups), hipMemcpyHostToDevice,
+                           lanes[0]));
     k = 0;
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < kGroups; ++g) {
       const int m = static_cast<int>(multi[g].size());
       if (m > 0) {
-        const int64_t off = g == 0 ? 0 : static_cast<int64_t>(multi[0].size()) + 1;
         Plan* p0 = plans[multi[g][0]];
-        MPS_TRY(launch_scatter_multi(ws->d_cats + k, ws->d_starts + off, m, ws->h_starts[off + m], g == 1,
+        MPS_TRY(launch_scatter_multi(ws->d_cats + k, ws->d_starts + k + g, m, ws->h_starts[k + g + m], g,
                                      p0->taps[0], p0->tap_bound[0], ws->d_queue, p0->num_cus, lanes[0]));
       }
       k += m;
@@ -478,7 +499,15 @@ int mps_plan_destroy(mps_plan* plan) {
 
 int mps_plan_reserve(mps_plan* plan, int64_t max_particles) {
   if (!plan || max_particles < 1 || max_particles > 0x7fffffffll) return MPS_E_ARG;
-  return ensure_particles(reinterpret_cast<Plan*>(plan), max_particles);
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  const int st = ensure_particles(p, max_particles);
+  if (st != MPS_OK) return st;
+  // the halo buffer too, if a catalog of at most max_particles can take the
+  // halo scatter (the catalogs just above the owner-computes range)
+  const int64_t nt = p->n / 16;
+  const int64_t above = static_cast<int64_t>(MPS_SCATTER_GATHER_MAX_MEAN) * nt * nt * nt + 1;
+  if (max_particles >= above && scatter_form_for(p->n, p->prec, above) == kFormHalo) return ensure_halo(p);
+  return MPS_OK;
 }
 
 size_t mps_footprint(int n_grid, mps_precision prec, int64_t n_particles) {
@@ -495,6 +524,7 @@ size_t mps_footprint(int n_grid, mps_precision prec, int64_t n_particles) {
   b += sizeof(double) * (static_cast<size_t>(256) + 1) * kMaxBins * kNumQ;
   b += sizeof(double) * (kMomentBlocks * (kMomentSums + kMomentMax) + 2 * kNumKernels * (half + 1)) +
        2 * rs * n_grid + sizeof(ResultHeader);
+  if (scatter_form_for(n_grid, prec, n_particles) == kFormHalo) b += halo_bytes(n_grid, prec);
   return b;
 }
 
@@ -505,7 +535,7 @@ int mps_estimate(mps_plan* plan, const mps_catalog* cat, mps_result* out, hipStr
   if (st != MPS_OK) return st;
   if (hipSetDevice(p->device) != hipSuccess) return MPS_E_HIP;
   if ((st = ensure_bins(p, cat)) != MPS_OK) return st;
-  if ((st = ensure_particles(p, cat->n_particles)) != MPS_OK) return st;
+  if ((st = ensure_scatter_space(p, cat)) != MPS_OK) return st;
   if ((st = enqueue_estimate(p, cat, stream)) != MPS_OK) return st;
   if (hipStreamSynchronize(stream) != hipSuccess) return MPS_E_HIP;
   return unpack(p, cat, out);
@@ -538,7 +568,7 @@ int mps_estimate_mu(mps_plan* plan, const mps_catalog* cat, int n_mu, const doub
     }
   }
   if ((st = ensure_bins(p, cat)) != MPS_OK) return st;
-  if ((st = ensure_particles(p, cat->n_particles)) != MPS_OK) return st;
+  if ((st = ensure_scatter_space(p, cat)) != MPS_OK) return st;
   if ((st = enqueue_particles(p, cat, stream, 0)) != MPS_OK) return st;
   MPS_TRY(launch_fft_z(p, p->grid, stream));
   mark(p, 6, stream);
@@ -597,7 +627,7 @@ int mps_estimate_batch(mps_plan* const* plans, const mps_catalog* cats, mps_resu
     Plan* p = reinterpret_cast<Plan*>(plans[i]);
     int st;
     if ((st = ensure_bins(p, &cats[i])) != MPS_OK) return st;
-    if ((st = ensure_particles(p, cats[i].n_particles)) != MPS_OK) return st;
+    if ((st = ensure_scatter_space(p, &cats[i])) != MPS_OK) return st;
   }
   // the catalogs' stages go to the device's batch lanes (created once), each
   // started after the caller's earlier work on `stream`; `stream` then waits
@@ -805,10 +835,14 @@ int mps_estimate_subcubes(mps_plan* plan, const mps_catalog* cat, int n_div, mps
   // small grids' kernels overlap
   if ((st = ensure_sub_lanes(p)) != MPS_OK) return st;
   Plan* lane[Plan::kSubLanes];
+  bool halo = false;  // a sub-catalog takes the halo scatter
+  for (uint32_t c : count)
+    halo = halo || (c > 0 && kernel_id(sub.flags) == 0 && scatter_form_for(p->n, p->prec, c) == kFormHalo);
   for (int i = 0; i < Plan::kSubLanes; ++i) {
     lane[i] = i == 0 ? p : p->sub_plan[i - 1];
     if ((st = ensure_bins(lane[i], &sub)) != MPS_OK) return st;
     if ((st = ensure_particles(lane[i], largest)) != MPS_OK) return st;
+    if (halo && (st = ensure_halo(lane[i])) != MPS_OK) return st;
   }
   std::vector<mps_catalog> cats(n_cubes, sub);
   int64_t off = 0;
@@ -847,7 +881,7 @@ int mps_assign(mps_plan* plan, const mps_catalog* cat, void* grids, hipStream_t 
   int st = validate_catalog(p, cat);
   if (st != MPS_OK) return st;
   if (hipSetDevice(p->device) != hipSuccess) return MPS_E_HIP;
-  if ((st = ensure_particles(p, cat->n_particles)) != MPS_OK) return st;
+  if ((st = ensure_scatter_space(p, cat)) != MPS_OK) return st;
   const bool was = p->timing;
   p->timing = false;
   st = enqueue_particles(p, cat, stream, (cat->flags & MPS_BULKFLOW_SUBTRACT) ? 1 : 0);

@@ -98,11 +98,27 @@ struct KeyParams {
 struct ScatterCat {
   const float4* sorted;    // tile-sorted records
   const uint32_t* offset;  // n_tiles + 1 record offsets
-  float* grid;             // four N^3 FP32 grids (zeroed)
+  float* grid;             // four N^3 FP32 grids (zeroed for the atomic form)
   KeyParams kp;
   const Derived* dsrc;     // moments and bounds of the catalog
   int bulk;                // 1: deposit w (v - v_b)
+  float* halo;             // halo form: kHaloCells x 4 fields per tile
 };
+
+// The FP32 scatter's forms (16^3 tiles, truncated BL3).  Each tile
+// accumulates its particles' deposits over the tile and a halo (2 cells
+// below, 3 above per axis) in LDS, then
+//   kFormAtomic: adds the whole block to the (cleared) grid with FP32 atomics;
+//   kFormHalo:   stores its own cells in the grid and its halo cells in a
+//                per-tile halo buffer, and a fix-up pass adds each cell's
+//                neighbour halos in a fixed order (no atomics, no clear);
+//   kFormGather: (owner-computes) gathers the particles of its 27-tile
+//                neighbourhood whose taps reach it and stores its own cells.
+// The gather pays for its candidate reads at all but low densities, the
+// halo form for its halo traffic once the tiles are dense enough that the
+// atomic form's deposits, not its flush, dominate.
+enum ScatterForm { kFormAtomic = 0, kFormGather = 1, kFormHalo = 2 };
+constexpr int kHaloCells = 21 * 21 * 21 - 16 * 16 * 16;  // halo cells of a 16^3 tile's block
 
 // Layout of the device result block copied back to the host.
 struct ResultHeader {
@@ -154,6 +170,7 @@ struct Plan {
   uint32_t* tile_offset = nullptr;   // n_tiles + 1
   uint32_t* tile_cursor = nullptr;   // n_tiles
   uint32_t* tile_queue = nullptr;    // 8 work-queue counters of the scatter
+  float* halo = nullptr;             // halo form: n_tiles x 4 x kHaloCells (allocated on first use)
   int num_cus = 256;
   double* moment_partials = nullptr; // kMomentBlocks x (kMomentSums + kMomentMax)
   ResultHeader* d_header = nullptr;
@@ -235,9 +252,11 @@ inline size_t host_stage_bytes(const mps_catalog* c) {
 // staging buffer when NULL).
 int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s, void* stage = nullptr);
 
-// Device and pinned buffers of the multi-catalog scatter launch: catalog
-// descriptors and tile prefix sums (two groups), queue counters.  Grown on
-// demand, kept by their owner.
+// Groups of the multi-catalog scatter launches (see scatter_group).
+constexpr int kScatterGroups = 6;
+// Device and pinned buffers of the multi-catalog scatter launches: catalog
+// descriptors (cap of them), tile prefix sums (cap + kScatterGroups: one
+// array per group), queue counters.  Grown on demand, kept by their owner.
 struct BatchWorkspace {
   ScatterCat* d_cats = nullptr;
   int64_t* d_starts = nullptr;
@@ -262,14 +281,26 @@ hipError_t launch_scan(Plan* p, hipStream_t s);
 hipError_t launch_permute(Plan* p, const mps_catalog* c, hipStream_t s);
 hipError_t launch_clear_grid(Plan* p, hipStream_t s);
 hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s);
-// The multi-catalog scatter: FP32 grids, 16^3 tiles, the truncated BL3
-// kernel; one launch over all the catalogs' tiles (d_cats, d_starts: device
-// arrays of n_cats descriptors and n_cats + 1 tile prefix sums; d_queue: 8
-// counters).  has_w: the records carry weights (32-byte records).
+// The catalog's scatter form (ScatterForm; kFormAtomic for FP64 grids and
+// the kernels other than the truncated BL3).
+int scatter_form(const Plan* p, const mps_catalog* c);
+// The form a truncated-BL3 catalog of np particles takes on an N^3 grid of
+// this precision, and the halo buffer's bytes.
+int scatter_form_for(int n_grid, mps_precision prec, int64_t np);
+size_t halo_bytes(int n_grid, mps_precision prec);
+// Allocate what the catalog's scatter needs: sorted records and, for the
+// halo form, the halo buffer (api.cpp).
+int ensure_scatter_space(Plan* p, const mps_catalog* c);
+int ensure_halo(Plan* p);
+// The multi-catalog scatter: one launch over the tiles of several catalogs
+// of one group (d_cats, d_starts: device arrays of n_cats descriptors and
+// n_cats + 1 tile prefix sums; d_queue: 8 counters), followed for the halo
+// form by its fix-up.  scatter_group: the catalog's group, 2 x form +
+// (records carry weights ? 1 : 0), or -1 when it takes a launch of its own.
 ScatterCat scatter_cat(Plan* p, const mps_catalog* c);
-bool scatter_multi_eligible(const Plan* p, const mps_catalog* c);
+int scatter_group(const Plan* p, const mps_catalog* c);
 hipError_t launch_scatter_multi(const ScatterCat* d_cats, const int64_t* d_starts, int n_cats, int64_t n_items,
-                                bool has_w, const TapPoly& tp, const TapBound& tb, uint32_t* d_queue, int num_cus,
+                                int group, const TapPoly& tp, const TapBound& tb, uint32_t* d_queue, int num_cus,
                                 hipStream_t s);
 
 // Launchers (fft.hip).

@@ -18,6 +18,12 @@ namespace mps {
 namespace {
 
 constexpr int kCountThreads = 256;
+// The FP32 scatter forms (see ScatterForm): the owner-computes kernel's
+// threads per workgroup, and the largest mean numbers of particles per 16^3
+// tile for which the owner-computes and the halo forms are taken.
+constexpr int kGatherThreads = 512;
+constexpr int64_t kGatherMaxMean = MPS_SCATTER_GATHER_MAX_MEAN;
+constexpr int64_t kHaloMaxMean = MPS_SCATTER_HALO_MAX_MEAN;
 
 // Grid coordinate of one float32 coordinate: u = x * (N / L) + shift in FP64
 // (shift = 1/2 for the odd-order B-splines, whose taps are centred on the
@@ -622,6 +628,18 @@ __device__ __forceinline__ void bank_scan(BankSort<NT, kPer>& bs) {
   }
 }
 
+// Index of block cell (ex, ey, ez) among the halo cells of a 16^3 tile's
+// 21^3 block (2 cells below and 3 above the tile along each axis): the 5
+// halo x planes, then within the tile's x range the 5 halo y rows, then
+// within the tile's x and y range the 5 halo z cells.
+__device__ __forceinline__ int halo_index(int ex, int ey, int ez) {
+  constexpr int E = 21, H = 2, TS = 16, B = E - TS;
+  auto band = [](int e) { return e < H ? e : e - TS; };
+  if (ex < H || ex >= H + TS) return (band(ex) * E + ey) * E + ez;
+  if (ey < H || ey >= H + TS) return B * E * E + ((ex - H) * B + band(ey)) * E + ez;
+  return B * E * E + TS * B * E + ((ex - H) * TS + ey - H) * B + band(ez);
+}
+
 // Work queues of the persistent scatter: 8 (one per XCD, each over a
 // contiguous range of tiles, so that halo lines shared by neighbouring tiles
 // stay in one L2) or 1.  A block takes tiles from its own queue, then from
@@ -712,10 +730,11 @@ __device__ __forceinline__ int64_t next_item(const TileQueues& tq, int64_t n_ite
 // kMulti: one launch over the tiles of several catalogs (ScatterCat array
 // `cats`, item prefix sums `starts`), so that catalogs with few tiles share
 // the GPU; otherwise the one catalog `one`.
-template <int TS, int NT, int NTAP, int DEG, bool kW, bool kMulti>
+template <int TS, int NT, int NTAP, int DEG, bool kW, bool kMulti, bool kHalo = false>
 __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     ScatterCat one, const ScatterCat* __restrict__ cats, const int64_t* __restrict__ starts, int n_cats,
     int64_t n_items, TileQueues tq, TapPoly tp, TapBound kb) {
+  static_assert(!kHalo || (TS == 16 && NTAP == 6), "the halo layout is that of 16^3 tiles with taps -2..3");
   constexpr int H = kHaloLo<NTAP>;
   constexpr int E = TS + NTAP - 1;
   constexpr int VOL = E * E * E;
@@ -736,6 +755,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   const float4* sorted = nullptr;
   const uint32_t* offset = nullptr;
   float* grid = nullptr;
+  float* halo = nullptr;
   KeyParams kp = one.kp;
   int bulk = 0;
   double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
@@ -747,6 +767,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     sorted = c.sorted;
     offset = c.offset;
     grid = c.grid;
+    halo = c.halo;
     kp = c.kp;
     bulk = c.bulk;
     const Derived* dsrc = c.dsrc;
@@ -796,14 +817,21 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     }
     const uint32_t p0 = offset[tile], p1 = offset[tile + 1];
     const uint32_t cnt = p1 - p0;
-    if (cnt == 0) {  // nothing to deposit or flush (uniform across the workgroup)
-      item = next_item<NT, kMulti>(tq, n_items, starts, n_cats, &s_tile);
-      continue;
-    }
     const int tz = static_cast<int>(tile % nt);
     const int ty = static_cast<int>((tile / nt) % nt);
     const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
     const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
+    if (cnt == 0) {  // nothing to deposit (uniform across the workgroup)
+      if constexpr (kHalo) {  // the tile's own cells start at zero (no clear in this form)
+        for (int i = t; i < TS * TS * TS; i += NT) {
+          const int64_t gi = (static_cast<int64_t>(ox + i / (TS * TS)) * n + oy + (i / TS) % TS) * n + oz + i % TS;
+#pragma unroll
+          for (int f = 0; f < kNumFields; ++f) grid[f * n3 + gi] = 0.f;
+        }
+      }
+      item = next_item<NT, kMulti>(tq, n_items, starts, n_cats, &s_tile);
+      continue;
+    }
     // integer scale of the cell sums C: n_tile * qmax maps just under 2^32,
     // and upper rounding adds at most one unit per particle
     float csc[kNumFields];
@@ -977,19 +1005,24 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     float inv[kNumFields];
 #pragma unroll
     for (int f = 0; f < kNumFields; ++f) inv[f] = inv_s[f];
-    // dense: the whole block; sparse: the tap-origin box grown by the taps
+    // atomic form: a dense tile's whole block, a sparse tile's tap-origin box
+    // grown by the taps; halo form: the whole block (every halo cell is read
+    // by the fix-up)
     int fx0 = 0, fy0 = 0, fz0 = 0, fdx = E, fdy = E, fdz = E;
     if (sparse) {
-      fx0 = bb[0];
-      fy0 = bb[1];
-      fz0 = bb[2];
-      fdx = bb[3] + NTAP - fx0;
-      fdy = bb[4] + NTAP - fy0;
-      fdz = bb[5] + NTAP - fz0;
+      if constexpr (!kHalo) {
+        fx0 = bb[0];
+        fy0 = bb[1];
+        fz0 = bb[2];
+        fdx = bb[3] + NTAP - fx0;
+        fdy = bb[4] + NTAP - fy0;
+        fdz = bb[5] + NTAP - fz0;
+      }
       __syncthreads();  // every thread has read the box
       if (t < 6) bb[t] = t < 3 ? E : -1;  // visible to the next tile after the final barrier
     }
     const int fvol = fdx * fdy * fdz;
+    float* hbase = kHalo ? halo + tile * (static_cast<int64_t>(kNumFields) * kHaloCells) : nullptr;
     for (int j = t; j < fvol; j += NT) {
       const int ez = fz0 + j % fdz, ey = fy0 + (j / fdz) % fdy, ex = fx0 + j / (fdy * fdz);
       const int i = (ex * E + ey) * E + ez;
@@ -997,17 +1030,403 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       const int gy = (oy + ey - H) & (n - 1);
       const int gz = (oz + ez - H) & (n - 1);
       const int64_t gi = (static_cast<int64_t>(gx) * n + gy) * n + gz;
+      const bool core = ex >= H && ex < H + TS && ey >= H && ey < H + TS && ez >= H && ez < H + TS;
+      const int hc = kHalo && !core ? halo_index(ex, ey, ez) : 0;
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         const unsigned long long sum = acc2[k * VOL + i];
         acc2[k * VOL + i] = 0ull;
         int lo, hi;
         unpack_pair(sum, &lo, &hi);
-        if (lo != 0) atomicAdd(grid + (2 * k) * n3 + gi, static_cast<float>(lo) * inv[2 * k]);
-        if (hi != 0) atomicAdd(grid + (2 * k + 1) * n3 + gi, static_cast<float>(hi) * inv[2 * k + 1]);
+        const float vlo = static_cast<float>(lo) * inv[2 * k], vhi = static_cast<float>(hi) * inv[2 * k + 1];
+        if constexpr (kHalo) {
+          if (core) {
+            grid[(2 * k) * n3 + gi] = vlo;
+            grid[(2 * k + 1) * n3 + gi] = vhi;
+          } else {
+            hbase[(2 * k) * kHaloCells + hc] = vlo;
+            hbase[(2 * k + 1) * kHaloCells + hc] = vhi;
+          }
+        } else {
+          if (lo != 0) atomicAdd(grid + (2 * k) * n3 + gi, vlo);
+          if (hi != 0) atomicAdd(grid + (2 * k + 1) * n3 + gi, vhi);
+        }
       }
     }
     __syncthreads();
+  }
+}
+
+// FP32 grids of sparse catalogs, owner-computes ("gather") form.  A tile
+// computes the final values of its own T^3 cells (T = 16) and writes them
+// with plain stores: no halo, no global atomics and no grid clear.  Its
+// sources are the particles whose taps reach it, those in cells
+// [o - 3, o + T + 1] per axis for the truncated BL3 taps j = -2..3 (the
+// source region, 21 cells), drawn from the tile and its 26 periodic
+// neighbours (at least 4 tiles per axis, so that the neighbours are
+// distinct).  Two passes over these candidates:
+//   1. per-cell sums of the scaled |q| over the source region, whose largest
+//      value times (sum_j k_j)^3 bounds every cell of the tile, as in the
+//      atomic form;
+//   2. the deposits of the taps that land in the tile, in 32-bit fixed point,
+//      two fields per 64-bit LDS word.  Each wave queues its in-region
+//      candidates in a ring of 128 LDS slots and deposits 64 at a time, so
+//      that the many neighbour candidates outside the region do not leave
+//      lanes idle through the deposit loop.
+// The candidates' records are read from 27 tiles, twice: this pays while
+// tiles hold few particles and the atomic form's halo flush dominates.
+template <int NT, bool kW, bool kMulti>
+__global__ __launch_bounds__(NT) void scatter_gather_kernel(
+    ScatterCat one, const ScatterCat* __restrict__ cats, const int64_t* __restrict__ starts, int n_cats,
+    int64_t n_items, TileQueues tq, TapPoly tp, TapBound kb) {
+  constexpr int TS = 16, NTAP = 6, DEG = 3;
+  constexpr int H = kHaloLo<NTAP>;   // taps reach H cells below a particle's cell
+  constexpr int HI = NTAP - 1 - H;   // and HI cells above it
+  constexpr int R = TS + NTAP - 1;   // source region per axis: cells [-HI, TS + H)
+  constexpr int RV = R * R * R;
+  constexpr int CV = TS * TS * TS;
+  constexpr int kWaves = NT / 64;
+  constexpr int kRing = 128;
+  static_assert(2 * CV * 2 <= 2 * RV, "the deposit pairs alias the cell sums");
+  __shared__ __align__(16) unsigned blk[2 * RV];  // cell sums, then 2 x CV 64-bit pairs
+  __shared__ int ring[kWaves][kRing];             // each wave's queued candidates
+  __shared__ int nb_first[28];                    // prefix sums of the 27 candidate ranges
+  __shared__ uint32_t nb_start[27];
+  __shared__ float red[kWaves][2];
+  __shared__ float scale_s[kNumFields], inv_s[kNumFields];
+  __shared__ long long s_tile;
+  unsigned long long* acc2 = reinterpret_cast<unsigned long long*>(blk);
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+
+  const float4* sorted = nullptr;
+  const uint32_t* offset = nullptr;
+  float* grid = nullptr;
+  KeyParams kp = one.kp;
+  int bulk = 0;
+  double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
+  double qmax[kNumFields] = {0.0, 0.0, 0.0, 0.0};
+  int nt = 0, n = 0;
+  int64_t n3 = 0;
+  int cur_cat = -1;
+  auto set_cat = [&](const ScatterCat& c) {
+    sorted = c.sorted;
+    offset = c.offset;
+    grid = c.grid;
+    kp = c.kp;
+    bulk = c.bulk;
+    const Derived* dsrc = c.dsrc;
+    vb0 = vb1 = vb2 = 0.0;
+    if (bulk) {
+      vb0 = dsrc->vb[0];
+      vb1 = dsrc->vb[1];
+      vb2 = dsrc->vb[2];
+    }
+    qmax[0] = dsrc->qmax[0];
+    qmax[1] = dsrc->qmax[1] + (bulk ? dsrc->qmax[0] * fabs(vb0) : 0.0);
+    qmax[2] = dsrc->qmax[2] + (bulk ? dsrc->qmax[0] * fabs(vb1) : 0.0);
+    qmax[3] = dsrc->qmax[3] + (bulk ? dsrc->qmax[0] * fabs(vb2) : 0.0);
+    nt = kp.nt;
+    n = kp.n;
+    n3 = static_cast<int64_t>(n) * n * n;
+  };
+  double ksum = 0.0;
+#pragma unroll
+  for (int j = 0; j < NTAP; ++j) ksum += static_cast<double>(kb.k[j]);
+  const double ksum3 = ksum * ksum * ksum * 1.00001;
+
+  // Candidate i (0 <= i < total): its record, its tile's offset d from this
+  // tile, and its cell rc relative to this tile's origin (from its own
+  // tile's origin, so that the periodic wrap is never ambiguous) with the
+  // fractions fr.  False when the cell is outside the source region.
+  int ox = 0, oy = 0, oz = 0;
+  auto candidate = [&](int i, float4* a, uint32_t* rec, int* rc, double* fr) -> bool {
+    int lo = 0, hi = 27;  // nb_first[lo] <= i < nb_first[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (nb_first[mid] <= i) lo = mid; else hi = mid;
+    }
+    *rec = nb_start[lo] + static_cast<uint32_t>(i - nb_first[lo]);
+    *a = rec_pos<kW>(sorted, static_cast<int64_t>(*rec));
+    const int d[3] = {lo / 9 - 1, (lo / 3) % 3 - 1, lo % 3 - 1};
+    const int o[3] = {ox, oy, oz};
+    const float xs[3] = {a->x, a->y, a->z};
+    bool in = true;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      bool ok;
+      const int c = locate(xs[ax], kp.scale, kp.shift, kp.n, &fr[ax], &ok);
+      rc[ax] = c - ((o[ax] + TS * d[ax]) & (n - 1)) + TS * d[ax];
+      in = in && rc[ax] >= -HI && rc[ax] < TS + H;
+    }
+    return in;
+  };
+
+  for (int i = t; i < 2 * RV; i += NT) blk[i] = 0u;
+  int64_t item = next_item<NT, kMulti>(tq, n_items, starts, n_cats, &s_tile);
+  while (item >= 0) {
+    const int c_item = static_cast<int>(item >> 32);
+    const int64_t tile = item & 0xffffffffll;
+    if (c_item != cur_cat) {
+      set_cat(kMulti ? cats[c_item] : one);
+      cur_cat = c_item;
+    }
+    const int tz = static_cast<int>(tile % nt);
+    const int ty = static_cast<int>((tile / nt) % nt);
+    const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
+    ox = tx * TS;
+    oy = ty * TS;
+    oz = tz * TS;
+    if (t < 27) {
+      const int dx = t / 9 - 1, dy = (t / 3) % 3 - 1, dz = t % 3 - 1;
+      const int64_t tn = (static_cast<int64_t>((tx + dx + nt) % nt) * nt + (ty + dy + nt) % nt) * nt +
+                         (tz + dz + nt) % nt;
+      nb_start[t] = offset[tn];
+      nb_first[t + 1] = static_cast<int>(offset[tn + 1] - offset[tn]);
+    }
+    __syncthreads();
+    if (t == 0) {
+      nb_first[0] = 0;
+      for (int r = 0; r < 27; ++r) nb_first[r + 1] += nb_first[r];
+    }
+    __syncthreads();
+    const int total = nb_first[27];
+    if (total > 0) {  // uniform; otherwise the tile is written with zeros
+      // integer scale of the cell sums: the candidates bound the count, and
+      // upper rounding adds at most one unit per candidate
+      float csc[kNumFields];
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f)
+        csc[f] = qmax[f] > 0.0
+                     ? static_cast<float>((4294967295.0 - total) * (1.0 - 1e-6) / (static_cast<double>(total) * qmax[f]))
+                     : 0.f;
+      // pass 1: cell sums over the source region (rho; the largest of the
+      // momentum fields' scaled charges)
+      for (int i = t; i < total; i += NT) {
+        float4 a;
+        uint32_t rec;
+        int rc[3];
+        double fr[3];
+        if (!candidate(i, &a, &rec, rc, fr)) continue;
+        const DepositQ<float> q = charges<float>(a, rec_vel<kW>(sorted, static_cast<int64_t>(rec)), bulk, vb0, vb1, vb2);
+        const unsigned u0 = static_cast<unsigned>(ceilf(fabsf(q.q[0]) * csc[0]));
+        unsigned u1 = 0;
+#pragma unroll
+        for (int f = 1; f < kNumFields; ++f) u1 = max(u1, static_cast<unsigned>(ceilf(fabsf(q.q[f]) * csc[f])));
+        const int cell = ((rc[0] + HI) * R + rc[1] + HI) * R + rc[2] + HI;
+        if (u0) atomicAdd(&blk[cell], u0);
+        if (u1) atomicAdd(&blk[RV + cell], u1);
+      }
+      __syncthreads();
+      // the largest cell sums, clearing the block for the deposits
+      float amax0 = 0.f, amax1 = 0.f;
+      for (int i = t; i < RV; i += NT) {
+        amax0 = fmaxf(amax0, static_cast<float>(blk[i]));
+        amax1 = fmaxf(amax1, static_cast<float>(blk[RV + i]));
+        blk[i] = 0u;
+        blk[RV + i] = 0u;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        amax0 = fmaxf(amax0, __shfl_xor(amax0, off));
+        amax1 = fmaxf(amax1, __shfl_xor(amax1, off));
+      }
+      if (lane == 0) {
+        red[wave][0] = amax0;
+        red[wave][1] = amax1;
+      }
+      __syncthreads();
+      if (t < kNumFields) {
+        float mx = 0.f;
+        const int bf = t == 0 ? 0 : 1;
+        for (int w = 0; w < kWaves; ++w) mx = fmaxf(mx, red[w][bf]);
+        // bound in charge units; room for the rounding errors of up to
+        // `total` deposits per cell
+        const double bound = static_cast<double>(mx) * ksum3 / static_cast<double>(csc[t]);
+        const double room = 0.99 * 2147483648.0 - 0.5 * static_cast<double>(total) - 64.0;
+        const double scl = (mx > 0.f && csc[t] > 0.f) ? fmin(room / bound, 1e30) : 0.0;
+        scale_s[t] = static_cast<float>(scl);
+        inv_s[t] = scl > 0.0 ? static_cast<float>(1.0 / static_cast<double>(static_cast<float>(scl))) : 0.f;
+      }
+      __syncthreads();
+      float sc[kNumFields];
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
+      // pass 2: 64 queued candidates of this wave (slots head .. head + 63,
+      // lanes beyond `m` idle) deposit the taps that land in the tile
+      auto deposit = [&](int head, int m) {
+        if (lane >= m) return;
+        float4 a;
+        uint32_t rec;
+        int rc[3];
+        double fr[3];
+        (void)candidate(ring[wave][(head + lane) & (kRing - 1)], &a, &rec, rc, fr);
+        float wx[NTAP], wy[NTAP], wz[NTAP];
+#pragma unroll
+        for (int j = 0; j < NTAP; ++j) {
+          wx[j] = static_cast<float>(tap_weight<DEG>(tp, j, fr[0]));
+          wy[j] = static_cast<float>(tap_weight<DEG>(tp, j, fr[1]));
+          wz[j] = static_cast<float>(tap_weight<DEG>(tp, j, fr[2]));
+        }
+        const DepositQ<float> q = charges<float>(a, rec_vel<kW>(sorted, static_cast<int64_t>(rec)), bulk, vb0, vb1, vb2);
+        float qs[kNumFields];
+#pragma unroll
+        for (int f = 0; f < kNumFields; ++f) qs[f] = q.q[f] * sc[f];
+        // tap j lands on cell rc + j - H
+#pragma unroll
+        for (int jx = 0; jx < NTAP; ++jx) {
+          const int gx = rc[0] + jx - H;
+          if (gx < 0 || gx >= TS) continue;
+#pragma unroll
+          for (int jy = 0; jy < NTAP; ++jy) {
+            const int gy = rc[1] + jy - H;
+            if (gy < 0 || gy >= TS) continue;
+            const float wxy = wx[jx] * wy[jy];
+            const int row = (gx * TS + gy) * TS;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              const float wlo = wxy * qs[2 * k], whi = wxy * qs[2 * k + 1];
+#pragma unroll
+              for (int jz = 0; jz < NTAP; ++jz) {
+                const int gz = rc[2] + jz - H;
+                if (gz >= 0 && gz < TS) atomicAdd(acc2 + k * CV + row + gz, deposit_pair(wlo, whi, wz[jz]));
+              }
+            }
+          }
+        }
+      };
+      int head = 0, queued = 0;  // uniform within the wave
+      for (int b = wave * 64; b < total; b += NT) {
+        const int i = b + lane;
+        float4 a;
+        uint32_t rec;
+        int rc[3];
+        double fr[3];
+        const bool in = i < total && candidate(i, &a, &rec, rc, fr);
+        const unsigned long long mask = __ballot(in);
+        if (in) {
+          const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+          ring[wave][(head + queued + rank) & (kRing - 1)] = i;
+        }
+        queued += __popcll(mask);
+        __builtin_amdgcn_wave_barrier();
+        if (queued >= 64) {
+          deposit(head, 64);
+          head = (head + 64) & (kRing - 1);
+          queued -= 64;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (queued > 0) deposit(head, queued);
+      __syncthreads();
+    }
+    // write the tile's cells with plain stores, clearing the block
+    float inv[kNumFields];
+#pragma unroll
+    for (int f = 0; f < kNumFields; ++f) inv[f] = total > 0 ? inv_s[f] : 0.f;
+    for (int i = t; i < CV; i += NT) {
+      const int ez = i % TS, ey = (i / TS) % TS, ex = i / (TS * TS);
+      const int64_t gi = (static_cast<int64_t>(ox + ex) * n + oy + ey) * n + oz + ez;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const unsigned long long sum = acc2[k * CV + i];
+        acc2[k * CV + i] = 0ull;
+        int lo, hi;
+        unpack_pair(sum, &lo, &hi);
+        grid[(2 * k) * n3 + gi] = static_cast<float>(lo) * inv[2 * k];
+        grid[(2 * k + 1) * n3 + gi] = static_cast<float>(hi) * inv[2 * k + 1];
+      }
+    }
+    item = next_item<NT, kMulti>(tq, n_items, starts, n_cats, &s_tile);
+  }
+}
+
+// The halo form's fix-up.  A cell receives the halo cells of the
+// neighbouring tiles' blocks that cover it when it lies within 3 cells of
+// its tile's low face or 2 of its high face along some axis (the band: 2765
+// of a tile's 4096 cells); the fix-up adds them to the value the cell's own
+// tile stored, in a fixed order (neighbour offsets ascending), skipping
+// neighbours without particles.  One workgroup per tile.
+template <bool kMulti>
+__global__ __launch_bounds__(256) void halo_fixup_kernel(ScatterCat one, const ScatterCat* __restrict__ cats,
+                                                         const int64_t* __restrict__ starts, int n_cats) {
+  constexpr int TS = 16, H = 2, B = 5, IN = TS - B;
+  constexpr int kBand = TS * TS * TS - IN * IN * IN;
+  __shared__ int nb_full[27];
+  const int t = threadIdx.x;
+  int64_t tile = blockIdx.x;
+  int c = 0;
+  if constexpr (kMulti) {
+    int lo = 0, hi = n_cats;  // starts[lo] <= item < starts[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (starts[mid] <= tile) lo = mid; else hi = mid;
+    }
+    c = lo;
+    tile -= starts[c];
+  }
+  const ScatterCat& cat = kMulti ? cats[c] : one;
+  const uint32_t* offset = cat.offset;
+  float* grid = cat.grid;
+  const float* halo = cat.halo;
+  const int nt = cat.kp.nt, n = cat.kp.n;
+  const int64_t n3 = static_cast<int64_t>(n) * n * n;
+  const int tz = static_cast<int>(tile % nt);
+  const int ty = static_cast<int>((tile / nt) % nt);
+  const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
+  auto neighbour = [&](int dx, int dy, int dz) -> int64_t {
+    return (static_cast<int64_t>((tx + dx + nt) % nt) * nt + (ty + dy + nt) % nt) * nt + (tz + dz + nt) % nt;
+  };
+  bool full = false;
+  if (t < 27 && t != 13) {
+    const int64_t tn = neighbour(t / 9 - 1, (t / 3) % 3 - 1, t % 3 - 1);
+    full = offset[tn + 1] > offset[tn];
+  }
+  if (t < 27) nb_full[t] = full ? 1 : 0;
+  if (!__syncthreads_or(full)) return;  // uniform: no neighbour halo reaches this tile
+  auto band_cell = [](int i) { return i < 3 ? i : i + IN; };  // 0..4 -> 0, 1, 2, 14, 15
+  for (int b = t; b < kBand; b += 256) {
+    int l[3];
+    if (b < B * TS * TS) {
+      l[0] = band_cell(b / (TS * TS));
+      l[1] = (b / TS) % TS;
+      l[2] = b % TS;
+    } else if (b < B * TS * TS + IN * B * TS) {
+      const int r = b - B * TS * TS;
+      l[0] = 3 + r / (B * TS);
+      l[1] = band_cell((r / TS) % B);
+      l[2] = r % TS;
+    } else {
+      const int r = b - B * TS * TS - IN * B * TS;
+      l[0] = 3 + r / (IN * B);
+      l[1] = 3 + (r / B) % IN;
+      l[2] = band_cell(r % B);
+    }
+    int dlo[3], dhi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      dlo[a] = l[a] < 3 ? -1 : 0;
+      dhi[a] = l[a] >= TS - 2 ? 1 : 0;
+    }
+    const int64_t gi = (static_cast<int64_t>(tx * TS + l[0]) * n + ty * TS + l[1]) * n + tz * TS + l[2];
+    float v[kNumFields];
+    bool touched = false;
+    for (int dx = dlo[0]; dx <= dhi[0]; ++dx)
+      for (int dy = dlo[1]; dy <= dhi[1]; ++dy)
+        for (int dz = dlo[2]; dz <= dhi[2]; ++dz) {
+          if ((dx | dy | dz) == 0 || !nb_full[(dx + 1) * 9 + (dy + 1) * 3 + dz + 1]) continue;
+          if (!touched) {
+#pragma unroll
+            for (int f = 0; f < kNumFields; ++f) v[f] = grid[f * n3 + gi];
+            touched = true;
+          }
+          const float* hb = halo + neighbour(dx, dy, dz) * (static_cast<int64_t>(kNumFields) * kHaloCells) +
+                            halo_index(l[0] - TS * dx + H, l[1] - TS * dy + H, l[2] - TS * dz + H);
+#pragma unroll
+          for (int f = 0; f < kNumFields; ++f) v[f] += hb[f * kHaloCells];
+        }
+    if (touched) {
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) grid[f * n3 + gi] = v[f];
+    }
   }
 }
 
@@ -1429,6 +1848,39 @@ hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int
   const int k = kernel_id(c->flags);
   const TapPoly& tp = p->taps[k];
   const TapBound& tb = p->tap_bound[k];
+  const int form = scatter_form(p, c);
+  if (form != kFormAtomic) {
+    TileQueues tq;
+    const int64_t xcd_chunk = (p->n_tiles % 8 == 0) ? p->n_tiles / 8 : 0;
+    tq.counter = p->tile_queue;
+    tq.nq = xcd_chunk > 0 ? 8 : 1;
+    tq.per_queue = xcd_chunk > 0 ? xcd_chunk : p->n_tiles;
+    clear_kernel<uint32_t><<<1, 64, 0, s>>>(p->tile_queue, 8);
+    ScatterCat one = scatter_cat(p, c);
+    one.bulk = bulk;
+    if (form == kFormGather) {
+      // persistent, two workgroups per CU (the LDS holds two), over every
+      // tile: each writes its own cells, zeros included
+      const int64_t cap = 2 * static_cast<int64_t>(p->num_cus);
+      const unsigned blocks = static_cast<unsigned>(p->n_tiles < cap ? p->n_tiles : cap);
+      if (c->weight)
+        scatter_gather_kernel<kGatherThreads, true, false><<<blocks, kGatherThreads, 0, s>>>(
+            one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb);
+      else
+        scatter_gather_kernel<kGatherThreads, false, false><<<blocks, kGatherThreads, 0, s>>>(
+            one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb);
+    } else {
+      const unsigned blocks = static_cast<unsigned>(p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus);
+      if (c->weight)
+        scatter_fixed_kernel<16, 1024, 6, 3, true, false, true><<<blocks, 1024, 0, s>>>(
+            one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb);
+      else
+        scatter_fixed_kernel<16, 1024, 6, 3, false, false, true><<<blocks, 1024, 0, s>>>(
+            one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb);
+      halo_fixup_kernel<false><<<static_cast<unsigned>(p->n_tiles), 256, 0, s>>>(one, nullptr, nullptr, 1);
+    }
+    return hipGetLastError();
+  }
   // the record layout the permute wrote for this catalog
   return c->weight ? launch_scatter_kernel<true>(p, c, s, bulk, k, tp, tb)
                    : launch_scatter_kernel<false>(p, c, s, bulk, k, tp, tb);
@@ -1439,15 +1891,39 @@ hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s) {
 }
 
 ScatterCat scatter_cat(Plan* p, const mps_catalog* c) {
-  return ScatterCat{p->sorted, p->tile_offset, static_cast<float*>(p->grid), key_params(p, c), &p->d_header->d, 0};
+  return ScatterCat{p->sorted, p->tile_offset, static_cast<float*>(p->grid), key_params(p, c), &p->d_header->d, 0,
+                    p->halo};
 }
 
-bool scatter_multi_eligible(const Plan* p, const mps_catalog* c) {
-  return p->prec == MPS_F32 && p->tile == 16 && kernel_id(c->flags) == 0;
+int scatter_form_for(int n_grid, mps_precision prec, int64_t np) {
+  // on fewer than 8^3 tiles the atomic form's few workgroups are the fastest
+  if (prec != MPS_F32 || n_grid < MPS_SCATTER_MIN_GRID || np >= (static_cast<int64_t>(1) << 31)) return kFormAtomic;
+  const int64_t nt = n_grid / 16;
+  const int64_t tiles = nt * nt * nt;
+  if (np <= kGatherMaxMean * tiles) return kFormGather;
+  if (np <= kHaloMaxMean * tiles) return kFormHalo;
+  return kFormAtomic;
+}
+
+size_t halo_bytes(int n_grid, mps_precision prec) {
+  if (prec != MPS_F32 || n_grid < MPS_SCATTER_MIN_GRID) return 0;
+  const size_t nt = static_cast<size_t>(n_grid / 16);
+  return nt * nt * nt * kNumFields * kHaloCells * sizeof(float);
+}
+
+int scatter_form(const Plan* p, const mps_catalog* c) {
+  if (kernel_id(c->flags) != 0) return kFormAtomic;
+  const int f = scatter_form_for(p->n, p->prec, c->n_particles);
+  return f == kFormHalo && !p->halo ? kFormAtomic : f;
+}
+
+int scatter_group(const Plan* p, const mps_catalog* c) {
+  if (p->prec != MPS_F32 || p->tile != 16 || kernel_id(c->flags) != 0) return -1;
+  return 2 * scatter_form(p, c) + (c->weight ? 1 : 0);
 }
 
 hipError_t launch_scatter_multi(const ScatterCat* d_cats, const int64_t* d_starts, int n_cats, int64_t n_items,
-                                bool has_w, const TapPoly& tp, const TapBound& tb, uint32_t* d_queue, int num_cus,
+                                int group, const TapPoly& tp, const TapBound& tb, uint32_t* d_queue, int num_cus,
                                 hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   TileQueues tq;
@@ -1455,13 +1931,36 @@ hipError_t launch_scatter_multi(const ScatterCat* d_cats, const int64_t* d_start
   tq.nq = 8;
   tq.per_queue = (n_items + 7) / 8;
   clear_kernel<uint32_t><<<1, 64, 0, s>>>(d_queue, 8);
-  const int64_t blocks = n_items < num_cus ? n_items : num_cus;
   const ScatterCat none{};
+  const bool has_w = (group & 1) != 0;
+  const int form = group >> 1;
+  if (form == kFormGather) {
+    const int64_t cap = 2 * static_cast<int64_t>(num_cus);
+    const unsigned blocks = static_cast<unsigned>(n_items < cap ? n_items : cap);
+    if (has_w)
+      scatter_gather_kernel<kGatherThreads, true, true><<<blocks, kGatherThreads, 0, s>>>(
+          none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
+    else
+      scatter_gather_kernel<kGatherThreads, false, true><<<blocks, kGatherThreads, 0, s>>>(
+          none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
+    return hipGetLastError();
+  }
+  const unsigned blocks = static_cast<unsigned>(n_items < num_cus ? n_items : num_cus);
+  if (form == kFormHalo) {
+    if (has_w)
+      scatter_fixed_kernel<16, 1024, 6, 3, true, true, true><<<blocks, 1024, 0, s>>>(
+          none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
+    else
+      scatter_fixed_kernel<16, 1024, 6, 3, false, true, true><<<blocks, 1024, 0, s>>>(
+          none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
+    halo_fixup_kernel<true><<<static_cast<unsigned>(n_items), 256, 0, s>>>(none, d_cats, d_starts, n_cats);
+    return hipGetLastError();
+  }
   if (has_w)
-    scatter_fixed_kernel<16, 1024, 6, 3, true, true><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+    scatter_fixed_kernel<16, 1024, 6, 3, true, true><<<blocks, 1024, 0, s>>>(
         none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
   else
-    scatter_fixed_kernel<16, 1024, 6, 3, false, true><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+    scatter_fixed_kernel<16, 1024, 6, 3, false, true><<<blocks, 1024, 0, s>>>(
         none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
   return hipGetLastError();
 }

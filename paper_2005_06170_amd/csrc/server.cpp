@@ -54,6 +54,7 @@ struct PooledPlan {
   mps_precision prec = MPS_F32;
   int64_t cap = 0;            // particles reserved
   int64_t host_cap = 0;       // particles of host-catalog staging reserved
+  bool halo = false;          // holds the halo scatter's buffer
   size_t bytes = 0;
   bool busy = false;
   uint64_t last_use = 0;
@@ -66,6 +67,7 @@ struct Admission {
   PooledPlan* pp = nullptr;
   enum { kReady, kGrow, kCreate } action = kReady;
   int64_t cap = 0, host_cap = 0;          // reservation to make (grow, create)
+  bool halo = false;                      // the plan must hold the halo buffer
   std::vector<std::pair<mps_plan*, size_t>> victims;
 };
 
@@ -118,19 +120,30 @@ bool make_room(Server* s, size_t need, const PooledPlan* keep, Admission* adm) {
   return true;
 }
 
-size_t plan_bytes(int n_grid, mps_precision prec, int64_t cap, int64_t host_cap) {
-  return mps_footprint(n_grid, prec, cap) + kHostStageBytes * static_cast<size_t>(host_cap);
+// Device bytes of a pooled plan: grids and tables, cap particles' records,
+// host_cap particles' staging, and the halo buffer if it holds one.
+size_t plan_bytes(int n_grid, mps_precision prec, int64_t cap, int64_t host_cap, bool halo) {
+  size_t b = mps_footprint(n_grid, prec, cap);
+  if (scatter_form_for(n_grid, prec, cap) == kFormHalo) b -= halo_bytes(n_grid, prec);  // counted by the footprint
+  if (halo) b += halo_bytes(n_grid, prec);
+  return b + kHostStageBytes * static_cast<size_t>(host_cap);
+}
+
+// The request's scatter takes the halo form (its plan needs the buffer).
+bool needs_halo(const mps_catalog& c, int n_grid, mps_precision prec) {
+  return kernel_id(c.flags) == 0 && scatter_form_for(n_grid, prec, c.n_particles) == kFormHalo;
 }
 
 // Under the lock: choose an idle pooled plan of this shape with room for np
-// particles (and, for a host-resident catalog, np particles of staging),
-// else one to grow, else a new one, and reserve its bytes.  Returns false if
-// the budget cannot host it right now (*status stays MPS_OK) or never can
-// (*status = MPS_E_TOOBIG).
-bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host, Admission* adm, int* status) {
+// particles (and, for a host-resident catalog, np particles of staging; and
+// the halo buffer if `halo`), else one to grow, else a new one, and reserve
+// its bytes.  Returns false if the budget cannot host it right now (*status
+// stays MPS_OK) or never can (*status = MPS_E_TOOBIG).
+bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host, bool halo, Admission* adm,
+                int* status) {
   *status = MPS_OK;
   const int64_t hp = host ? np : 0;
-  if (plan_bytes(n_grid, prec, np, hp) > s->budget) {
+  if (plan_bytes(n_grid, prec, np, hp, halo) > s->budget) {
     *status = MPS_E_TOOBIG;
     return false;
   }
@@ -138,7 +151,7 @@ bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host
   PooledPlan* grow = nullptr;
   for (auto& pp : s->pool) {
     if (pp.busy || pp.n_grid != n_grid || pp.prec != prec) continue;
-    if (pp.cap >= np && pp.host_cap >= hp) {
+    if (pp.cap >= np && pp.host_cap >= hp && (pp.halo || !halo)) {
       if (!fit || pp.cap < fit->cap) fit = &pp;
     } else if (!grow || pp.cap > grow->cap) {
       grow = &pp;
@@ -153,19 +166,21 @@ bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host
   }
   if (grow) {
     const int64_t cap = std::max(grow->cap, np), hcap = std::max(grow->host_cap, hp);
-    const size_t need = plan_bytes(n_grid, prec, cap, hcap);
+    const bool h = grow->halo || halo;
+    const size_t need = plan_bytes(n_grid, prec, cap, hcap, h);
     if (!make_room(s, need - grow->bytes, grow, adm)) return false;
     adm->pp = grow;
     adm->action = Admission::kGrow;
     adm->cap = cap;
     adm->host_cap = hcap;
+    adm->halo = h;
     s->used += need - grow->bytes;
     grow->bytes = need;
     grow->busy = true;
     grow->last_use = ++s->clock;
     return true;
   }
-  const size_t need = plan_bytes(n_grid, prec, np, hp);
+  const size_t need = plan_bytes(n_grid, prec, np, hp, halo);
   if (!make_room(s, need, nullptr, adm)) return false;
   PooledPlan pp;
   pp.n_grid = n_grid;
@@ -179,6 +194,7 @@ bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host
   adm->action = Admission::kCreate;
   adm->cap = np;
   adm->host_cap = hp;
+  adm->halo = halo;
   return true;
 }
 
@@ -198,6 +214,7 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
     st = mps_plan_create(&created, pp->n_grid, pp->prec);
     if (st == MPS_OK && adm->cap > 0) st = mps_plan_reserve(created, adm->cap);
     if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(created), adm->host_cap);
+    if (st == MPS_OK && adm->halo) st = ensure_halo(reinterpret_cast<Plan*>(created));
     if (st != MPS_OK && created) {
       mps_plan_destroy(created);
       created = nullptr;
@@ -205,6 +222,7 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
   } else if (adm->action == Admission::kGrow) {
     if (adm->cap > 0) st = mps_plan_reserve(pp->plan, adm->cap);
     if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(pp->plan), adm->host_cap);
+    if (st == MPS_OK && adm->halo) st = ensure_halo(reinterpret_cast<Plan*>(pp->plan));
   }
   lk.lock();
   s->used -= freed;
@@ -213,6 +231,7 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
       pp->plan = created;
       pp->cap = adm->cap;
       pp->host_cap = adm->host_cap;
+      pp->halo = adm->halo;
     } else {
       s->used -= pp->bytes;
       for (auto it = s->pool.begin(); it != s->pool.end(); ++it)
@@ -226,6 +245,7 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
     if (st == MPS_OK) {
       pp->cap = adm->cap;
       pp->host_cap = adm->host_cap;
+      pp->halo = adm->halo;
     } else {  // a failed reservation may have dropped part of the old one
       mps_plan* dead = pp->plan;
       s->used -= pp->bytes;
@@ -319,11 +339,12 @@ void worker_main(Server* s) {
         Admission adm;
         const bool large = r->cat.n_particles > s->small;
         const bool host = (r->cat.flags & MPS_CATALOG_HOST) != 0;
+        const bool halo = needs_halo(r->cat, r->n_grid, r->prec);
         if (large) {
           // the plan holds its grids only; the records live in this worker's
           // workspace, reserved (and grown if needed) first
           const int64_t np = r->cat.n_particles;
-          if (plan_bytes(r->n_grid, r->prec, 0, 0) + ParticleSpace::size_of(np, host ? np : 0) > s->budget) {
+          if (plan_bytes(r->n_grid, r->prec, 0, 0, halo) + ParticleSpace::size_of(np, host ? np : 0) > s->budget) {
             it = s->queue.erase(it);
             finish(s, r, MPS_E_TOOBIG);
             s->cv_done.notify_all();
@@ -333,7 +354,7 @@ void worker_main(Server* s) {
           const int64_t hcap = host ? grown(np, wp.want_host > wp.host_cap ? wp.want_host : wp.host_cap)
                                     : (wp.want_host > wp.host_cap ? wp.want_host : wp.host_cap);
           size_t need = ParticleSpace::size_of(cap, hcap);
-          if (need + plan_bytes(r->n_grid, r->prec, 0, 0) > s->budget)
+          if (need + plan_bytes(r->n_grid, r->prec, 0, 0, halo) > s->budget)
             need = ParticleSpace::size_of(np, host ? np : 0);  // no headroom: exactly what it needs
           if (need > wp.reserved) {
             Admission wadm;
@@ -350,7 +371,7 @@ void worker_main(Server* s) {
           }
         }
         Admission padm;
-        if (!admit_plan(s, r->n_grid, r->prec, large ? 0 : r->cat.n_particles, !large && host, &padm, &st)) {
+        if (!admit_plan(s, r->n_grid, r->prec, large ? 0 : r->cat.n_particles, !large && host, halo, &padm, &st)) {
           // plans a workspace reservation evicted are freed before this
           // worker waits (their bytes stay counted until then)
           for (auto& v : adm.victims) dead.push_back(v);
@@ -382,7 +403,7 @@ void worker_main(Server* s) {
             int st2 = MPS_OK;
             Admission a2;
             if (!admit_plan(s, q->n_grid, q->prec, q->cat.n_particles, (q->cat.flags & MPS_CATALOG_HOST) != 0,
-                            &a2, &st2))
+                            needs_halo(q->cat, q->n_grid, q->prec), &a2, &st2))
               break;
             batch.push_back(q);
             adms.push_back(std::move(a2));
@@ -476,7 +497,7 @@ void worker_main(Server* s) {
       int st = MPS_OK;
       if (batch[i]->ready && hipStreamWaitEvent(stream, batch[i]->ready, 0) != hipSuccess) st = MPS_E_HIP;
       if (st == MPS_OK) st = ensure_bins(p, &batch[i]->cat);
-      if (st == MPS_OK) st = ensure_particles(p, batch[i]->cat.n_particles);
+      if (st == MPS_OK) st = ensure_scatter_space(p, &batch[i]->cat);
       status[i] = st;
       if (st == MPS_OK) {
         run_plans.push_back(p);

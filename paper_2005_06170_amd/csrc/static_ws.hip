@@ -25,11 +25,13 @@ constexpr int kStaticMaxGrid = MPS_STATIC_MAX_GRID;
 constexpr int64_t kStaticMaxParticles = MPS_STATIC_MAX_PARTICLES;
 constexpr int kStaticMaxDevices = 16;
 constexpr int kStaticCus = 256;  // bound on the x pass's workgroups
+static_assert(kStaticMaxGrid < MPS_SCATTER_MIN_GRID, "the workspace holds no halo buffer");
 
 constexpr size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
 // Byte offsets of the plan's buffers in `scratch`, sized for the largest
-// grid (FP64) and catalog the entry point accepts.
+// grid (FP64) and catalog the entry point accepts.  Grids this small take
+// the atomic scatter (which needs no halo buffer).
 struct Layout {
   static constexpr int64_t kN3 = static_cast<int64_t>(kStaticMaxGrid) * kStaticMaxGrid * kStaticMaxGrid;
   static constexpr int kHalf = kStaticMaxGrid / 2;

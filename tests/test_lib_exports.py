@@ -23,3 +23,12 @@ def test_library_exports_every_declared_symbol():
     L = _lib.lib()
     missing = [n for n in _declared() if not hasattr(L, n)]
     assert not missing, missing
+
+
+def test_python_constants_match_the_header():
+    from paper_2005_06170_amd import _lib
+    text = open(os.path.join(ROOT, "include", "mps.h")).read()
+    defs = dict(re.findall(r"^#define\s+(MPS_\w+)\s+(.+?)\s*(?:/\*.*)?$", text, re.M))
+    for name in ("STATIC_MAX_GRID", "STATIC_MAX_PARTICLES", "SCATTER_MIN_GRID", "SCATTER_GATHER_MAX_MEAN",
+                 "SCATTER_HALO_MAX_MEAN"):
+        assert getattr(_lib, name) == eval(defs["MPS_" + name]), name
