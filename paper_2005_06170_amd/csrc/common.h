@@ -125,6 +125,8 @@ struct ResultHeader {
   double sums[kMomentSums];
   Derived d;
   uint32_t flags;        // bit 0: non-finite position seen
+  uint32_t order_same;   // sampled neighbouring particles in one tile (the sort's order probe)
+  uint32_t order_pairs;  // sampled neighbouring pairs
   uint32_t pad;
 };
 

@@ -120,7 +120,22 @@ constexpr int kUnroll = 4;
 // LDS and adds its non-zero counts to the global histogram once at the end,
 // so that catalogs in random order over few tiles do not serialise on a few
 // global counters; larger grids count with wave-aggregated global atomics.
+// Up to kLdsTilesRandom tiles (a 512^3 grid of 16^3 tiles) a catalog in
+// random order still takes the LDS histograms (128 KB, one workgroup per
+// CU), since one global atomic per particle would bound the sort; a catalog
+// in spatial order, whose waves hold long runs of one tile, keeps the
+// global form, which runs at full occupancy.  order_probe_kernel decides on
+// the device, and the count and permute launch both forms, of which one
+// returns at once.
 constexpr int kLdsTiles = 16384;
+constexpr int kLdsTilesRandom = 32768;
+constexpr int kProbeChunks = 64;  // chunks of kCountThreads consecutive particles sampled
+
+// A catalog is in random order when at most a quarter of its sampled
+// neighbouring pairs fall in one tile.
+__device__ __forceinline__ bool random_order(const ResultHeader* hdr) {
+  return 4ull * hdr->order_same <= static_cast<unsigned long long>(hdr->order_pairs);
+}
 
 // Catalog records of particles i0 .. i0+kUnroll-1 (one lane's group): with
 // 16-byte aligned arrays and a whole group, three 16-byte loads per array
@@ -160,12 +175,36 @@ __device__ __forceinline__ void load_group(const float* __restrict__ pos, const 
   }
 }
 
+// The sort's order probe: kProbeChunks chunks of kCountThreads consecutive
+// particles spread over the catalog; counts the neighbouring pairs of a
+// chunk and those whose two particles share a tile.
+__global__ __launch_bounds__(kCountThreads) void order_probe_kernel(const float* __restrict__ pos, int64_t np,
+                                                                   KeyParams kp, ResultHeader* hdr) {
+  __shared__ uint32_t keys[kCountThreads];
+  const int64_t span = np > kCountThreads ? np - kCountThreads : 0;
+  const int64_t start = span * blockIdx.x / kProbeChunks;
+  const int64_t i = start + threadIdx.x;
+  bool ok;
+  keys[threadIdx.x] = i < np ? tile_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], kp, &ok) : 0xffffffffu;
+  __syncthreads();
+  const bool pair = threadIdx.x > 0 && i < np;
+  const bool same = pair && keys[threadIdx.x] == keys[threadIdx.x - 1];
+  const unsigned long long sm = __ballot(same), pm = __ballot(pair);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&hdr->order_same, static_cast<uint32_t>(__popcll(sm)));
+    atomicAdd(&hdr->order_pairs, static_cast<uint32_t>(__popcll(pm)));
+  }
+}
+
+// order_mode: -1 runs always; 0 only for a catalog in spatial order, 1 only
+// for one in random order (random_order()).
 template <bool kHasW, bool kLds>
 __global__ __launch_bounds__(kCountThreads) void count_kernel(
     const float* __restrict__ pos, const float* __restrict__ vel, const float* __restrict__ wgt,
     int64_t np, KeyParams kp, int64_t n_tiles, uint32_t* __restrict__ tile_count,
-    double* __restrict__ partials, ResultHeader* hdr, bool vec) {
+    double* __restrict__ partials, ResultHeader* hdr, bool vec, int order_mode) {
   extern __shared__ uint32_t hist[];  // n_tiles counters when kLds
+  if (order_mode >= 0 && random_order(hdr) != (order_mode == 1)) return;  // uniform
   if (kLds) {
     for (int64_t i = threadIdx.x; i < n_tiles; i += kCountThreads) hist[i] = 0u;
     __syncthreads();
@@ -389,8 +428,9 @@ template <bool kHasW, bool kLds>
 __global__ __launch_bounds__(kCountThreads) void permute_kernel(
     const float* __restrict__ pos, const float* __restrict__ vel, const float* __restrict__ wgt,
     int64_t np, KeyParams kp, int64_t n_tiles, uint32_t* __restrict__ cursor, float4* __restrict__ sorted,
-    bool vec) {
+    bool vec, const ResultHeader* __restrict__ hdr, int order_mode) {
   extern __shared__ uint32_t hist[];  // n_tiles counters when kLds
+  if (order_mode >= 0 && random_order(hdr) != (order_mode == 1)) return;  // uniform
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kCountThreads * kUnroll;
   const int64_t first = static_cast<int64_t>(blockIdx.x) * kCountThreads * kUnroll;
   if (kLds) {
@@ -1569,20 +1609,31 @@ hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
   // the grid depends only on the particle count, so the moment sums of a
   // catalog are added in one order whatever else runs
   const int nb = count_blocks(c->n_particles);
-  const bool lds = p->n_tiles <= kLdsTiles;
-  auto go = [&](auto has_w, auto use_lds) {
-    const size_t dyn = decltype(use_lds)::value ? sizeof(uint32_t) * static_cast<size_t>(p->n_tiles) : 0;
-    count_kernel<decltype(has_w)::value, decltype(use_lds)::value><<<nb, kCountThreads, dyn, s>>>(
-        c->pos, c->vel, c->weight, c->n_particles, kp, p->n_tiles, p->tile_count, p->moment_partials,
-        p->d_header, vec_aligned(c));
+  auto go = [&](auto has_w, auto use_lds, int mode) {
+    constexpr bool kW = decltype(has_w)::value, kL = decltype(use_lds)::value;
+    const size_t dyn = kL ? sizeof(uint32_t) * static_cast<size_t>(p->n_tiles) : 0;
+    if (dyn > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&count_kernel<kW, kL>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn));
+    count_kernel<kW, kL><<<nb, kCountThreads, dyn, s>>>(c->pos, c->vel, c->weight, c->n_particles, kp, p->n_tiles,
+                                                        p->tile_count, p->moment_partials, p->d_header,
+                                                        vec_aligned(c), mode);
   };
-  using T_ = std::true_type;
-  using F_ = std::false_type;
-  if (c->weight) {
-    if (lds) go(T_{}, T_{}); else go(T_{}, F_{});
-  } else {
-    if (lds) go(F_{}, T_{}); else go(F_{}, F_{});
-  }
+  auto both = [&](auto has_w) {
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    if (p->n_tiles <= kLdsTiles) {
+      go(has_w, T_{}, -1);
+    } else if (p->n_tiles <= kLdsTilesRandom) {
+      order_probe_kernel<<<kProbeChunks, kCountThreads, 0, s>>>(c->pos, c->n_particles, kp, p->d_header);
+      go(has_w, F_{}, 0);
+      go(has_w, T_{}, 1);
+    } else {
+      go(has_w, F_{}, -1);
+    }
+  };
+  if (c->weight) both(std::true_type{});
+  else both(std::false_type{});
   return hipGetLastError();
 }
 
@@ -1600,19 +1651,30 @@ hipError_t launch_scan(Plan* p, hipStream_t s) {
 hipError_t launch_permute(Plan* p, const mps_catalog* c, hipStream_t s) {
   const KeyParams kp = key_params(p, c);
   const int nb = count_blocks(c->n_particles);
-  const bool lds = p->n_tiles <= kLdsTiles;
-  auto go = [&](auto has_w, auto use_lds) {
-    const size_t dyn = decltype(use_lds)::value ? sizeof(uint32_t) * static_cast<size_t>(p->n_tiles) : 0;
-    permute_kernel<decltype(has_w)::value, decltype(use_lds)::value><<<nb, kCountThreads, dyn, s>>>(
-        c->pos, c->vel, c->weight, c->n_particles, kp, p->n_tiles, p->tile_cursor, p->sorted, vec_aligned(c));
+  auto go = [&](auto has_w, auto use_lds, int mode) {
+    constexpr bool kW = decltype(has_w)::value, kL = decltype(use_lds)::value;
+    const size_t dyn = kL ? sizeof(uint32_t) * static_cast<size_t>(p->n_tiles) : 0;
+    if (dyn > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&permute_kernel<kW, kL>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn));
+    permute_kernel<kW, kL><<<nb, kCountThreads, dyn, s>>>(c->pos, c->vel, c->weight, c->n_particles, kp,
+                                                          p->n_tiles, p->tile_cursor, p->sorted, vec_aligned(c),
+                                                          p->d_header, mode);
   };
-  using T_ = std::true_type;
-  using F_ = std::false_type;
-  if (c->weight) {
-    if (lds) go(T_{}, T_{}); else go(T_{}, F_{});
-  } else {
-    if (lds) go(F_{}, T_{}); else go(F_{}, F_{});
-  }
+  auto both = [&](auto has_w) {
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    if (p->n_tiles <= kLdsTiles) {
+      go(has_w, T_{}, -1);
+    } else if (p->n_tiles <= kLdsTilesRandom) {  // the order probe ran with the count
+      go(has_w, F_{}, 0);
+      go(has_w, T_{}, 1);
+    } else {
+      go(has_w, F_{}, -1);
+    }
+  };
+  if (c->weight) both(std::true_type{});
+  else both(std::false_type{});
   return hipGetLastError();
 }
 
