@@ -190,7 +190,7 @@ typedef struct {
  * bytes per tile, is allocated on first use and counted by mps_footprint);
  * else, and on smaller grids, the atomic scatter. */
 #define MPS_SCATTER_MIN_GRID 128
-#define MPS_SCATTER_GATHER_MAX_MEAN 256
+#define MPS_SCATTER_GATHER_MAX_MEAN 384
 #define MPS_SCATTER_HALO_MAX_MEAN 2048
 
 typedef struct mps_plan mps_plan;

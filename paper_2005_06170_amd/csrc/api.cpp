@@ -224,6 +224,8 @@ int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s, void* stage) 
 
 // ------------------------------------------------------------ batches
 int BatchWorkspace::ensure(int n) {
+  for (hipEvent_t& e : done)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return MPS_E_HIP;
   if (n <= cap) return MPS_OK;
   if (d_cats) (void)hipFree(d_cats);
   if (d_starts) (void)hipFree(d_starts);
@@ -242,21 +244,23 @@ int BatchWorkspace::ensure(int n) {
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&h_starts), sizeof(int64_t) * (c + kScatterGroups),
                            hipHostMallocDefault) ==
                  hipSuccess;
-  if (!d_queue) ok = ok && hipMalloc(reinterpret_cast<void**>(&d_queue), sizeof(uint32_t) * 8) == hipSuccess;
+  if (!d_queue)
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&d_queue), sizeof(uint32_t) * 8 * kScatterGroups) == hipSuccess;
   if (!ok) return MPS_E_NOMEM;
   cap = c;
   return MPS_OK;
 }
 
-// Several catalogs, each with its own plan, on n_lanes streams (lanes[0]
-// joins the others for the scatter):
+// Several catalogs, each with its own plan, on n_lanes streams:
 //   1. per catalog, round robin on the lanes: moments, sort, clear;
-//   2. on lanes[0]: one persistent multi-catalog scatter launch over the
-//      tiles of every catalog it serves (FP32 grids, 16^3 tiles, truncated
-//      BL3; with and without weights separately), so that catalogs with few
-//      tiles fill the GPU together; the others' own scatter launches;
-//   3. per catalog, round robin: FFTs, estimator, finalize, copy back to
-//      stages[i] (the plan's own staging buffer when NULL).
+//   2. once every lane has got there: on lanes[0] the own scatter launches
+//      of the catalogs no multi-catalog group takes (FP64 grids, the other
+//      kernels), then one persistent multi-catalog scatter launch per group
+//      (scatter_group: form and record layout), the groups round robin on
+//      the lanes so that they overlap each other and the later stages;
+//   3. per catalog, round robin, after its group's scatter: FFTs,
+//      estimator, finalize, copy back to stages[i] (the plan's own staging
+//      buffer when NULL).
 // lanes[1..] must be ordered after earlier work by the caller.
 int enqueue_batch(Plan* const* plans, const mps_catalog* cats, int n, hipStream_t* lanes, int n_lanes,
                   hipEvent_t* events, BatchWorkspace* ws, void* const* stages) {
@@ -264,23 +268,24 @@ int enqueue_batch(Plan* const* plans, const mps_catalog* cats, int n, hipStream_
   int st = MPS_OK;
   for (int i = 0; i < n && st == MPS_OK; ++i) st = enqueue_prescatter(plans[i], &cats[i], lanes[i % n_lanes], &used[i]);
   if (st != MPS_OK) return st;
+  if ((st = ws->ensure(n)) != MPS_OK) return st;
   for (int l = 1; l < n_lanes; ++l) {
     MPS_TRY(hipEventRecord(events[l], lanes[l]));
     MPS_TRY(hipStreamWaitEvent(lanes[0], events[l], 0));
   }
-  // the multi-catalog groups (see scatter_group); the others' own launches
   constexpr int kGroups = kScatterGroups;
+  std::vector<int> group(n);
   std::vector<int> multi[kGroups];
   for (int i = 0; i < n; ++i) {
-    const int g = scatter_group(plans[i], &used[i]);
-    if (g >= 0) multi[g].push_back(i);
+    group[i] = scatter_group(plans[i], &used[i]);
+    if (group[i] >= 0) multi[group[i]].push_back(i);
     else MPS_TRY(launch_scatter_impl(plans[i], &used[i], lanes[0], 0));
   }
+  MPS_TRY(hipEventRecord(ws->done[kGroups], lanes[0]));
   int nm = 0;
   for (int g = 0; g < kGroups; ++g) nm += static_cast<int>(multi[g].size());
   if (nm > 0) {
     // descriptors of group g at [k_g, k_g + m_g), its prefix sums at [k_g + g, k_g + g + m_g]
-    if ((st = ws->ensure(nm)) != MPS_OK) return st;
     int k = 0;
     for (int g = 0; g < kGroups; ++g) {
       int64_t* starts = ws->h_starts + k + g;
@@ -295,21 +300,27 @@ int enqueue_batch(Plan* const* plans, const mps_catalog* cats, int n, hipStream_
     MPS_TRY(hipMemcpyAsync(ws->d_cats, ws->h_cats, sizeof(ScatterCat) * nm, hipMemcpyHostToDevice, lanes[0]));
     MPS_TRY(hipMemcpyAsync(ws->d_starts, ws->h_starts, sizeof(int64_t) * (nm + kGroups), hipMemcpyHostToDevice,
                            lanes[0]));
+    MPS_TRY(hipEventRecord(events[0], lanes[0]));  // descriptors in place, every catalog sorted
     k = 0;
+    int launched = 0;
     for (int g = 0; g < kGroups; ++g) {
       const int m = static_cast<int>(multi[g].size());
       if (m > 0) {
+        hipStream_t lane = lanes[launched++ % n_lanes];
+        if (lane != lanes[0]) MPS_TRY(hipStreamWaitEvent(lane, events[0], 0));
         Plan* p0 = plans[multi[g][0]];
         MPS_TRY(launch_scatter_multi(ws->d_cats + k, ws->d_starts + k + g, m, ws->h_starts[k + g + m], g,
-                                     p0->taps[0], p0->tap_bound[0], ws->d_queue, p0->num_cus, lanes[0]));
+                                     p0->taps[0], p0->tap_bound[0], ws->d_queue + 8 * g, p0->num_cus, lane));
+        MPS_TRY(hipEventRecord(ws->done[g], lane));
       }
       k += m;
     }
   }
-  MPS_TRY(hipEventRecord(events[0], lanes[0]));
-  for (int l = 1; l < n_lanes; ++l) MPS_TRY(hipStreamWaitEvent(lanes[l], events[0], 0));
-  for (int i = 0; i < n && st == MPS_OK; ++i)
-    st = enqueue_postscatter(plans[i], &cats[i], lanes[i % n_lanes], stages ? stages[i] : nullptr);
+  for (int i = 0; i < n && st == MPS_OK; ++i) {
+    hipStream_t lane = lanes[i % n_lanes];
+    MPS_TRY(hipStreamWaitEvent(lane, ws->done[group[i] >= 0 ? group[i] : kGroups], 0));
+    st = enqueue_postscatter(plans[i], &cats[i], lane, stages ? stages[i] : nullptr);
+  }
   return st;
 }
 

@@ -258,11 +258,14 @@ int enqueue_estimate(Plan* p, const mps_catalog* c, hipStream_t s, void* stage =
 constexpr int kScatterGroups = 6;
 // Device and pinned buffers of the multi-catalog scatter launches: catalog
 // descriptors (cap of them), tile prefix sums (cap + kScatterGroups: one
-// array per group), queue counters.  Grown on demand, kept by their owner.
+// array per group), queue counters (8 per group), and one event per group
+// (and one for the catalogs scattered on their own) that the catalogs'
+// later stages wait for.  Grown on demand, kept by their owner.
 struct BatchWorkspace {
   ScatterCat* d_cats = nullptr;
   int64_t* d_starts = nullptr;
   uint32_t* d_queue = nullptr;
+  hipEvent_t done[kScatterGroups + 1] = {};
   ScatterCat* h_cats = nullptr;
   int64_t* h_starts = nullptr;
   int cap = 0;

@@ -1104,17 +1104,22 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
 // [o - 3, o + T + 1] per axis for the truncated BL3 taps j = -2..3 (the
 // source region, 21 cells), drawn from the tile and its 26 periodic
 // neighbours (at least 4 tiles per axis, so that the neighbours are
-// distinct).  Two passes over these candidates:
+// distinct and a cell's periodic offset from the tile is unambiguous).  Two
+// passes over these candidates:
 //   1. per-cell sums of the scaled |q| over the source region, whose largest
-//      value times (sum_j k_j)^3 bounds every cell of the tile, as in the
-//      atomic form;
+//      value (from the atomics' returns) times (sum_j k_j)^3 bounds every
+//      cell of the tile, as in the atomic form; the in-region candidates go
+//      to an LDS list;
 //   2. the deposits of the taps that land in the tile, in 32-bit fixed point,
-//      two fields per 64-bit LDS word.  Each wave queues its in-region
-//      candidates in a ring of 128 LDS slots and deposits 64 at a time, so
-//      that the many neighbour candidates outside the region do not leave
-//      lanes idle through the deposit loop.
-// The candidates' records are read from 27 tiles, twice: this pays while
-// tiles hold few particles and the atomic form's halo flush dominates.
+//      two fields per 64-bit LDS word: the listed records dealt to all
+//      lanes, or, when more than the list holds are in the region, each
+//      wave's in-region candidates found again and queued in a ring of 128
+//      LDS slots, deposited 64 at a time, so that the many neighbour
+//      candidates outside the region do not leave lanes idle through the
+//      deposit loop.
+// The candidates' records are read from 27 tiles (twice when the list
+// overflows): this pays while tiles hold few particles and the atomic
+// form's halo flush dominates.
 template <int NT, bool kW, bool kMulti>
 __global__ __launch_bounds__(NT) void scatter_gather_kernel(
     ScatterCat one, const ScatterCat* __restrict__ cats, const int64_t* __restrict__ starts, int n_cats,
@@ -1127,12 +1132,20 @@ __global__ __launch_bounds__(NT) void scatter_gather_kernel(
   constexpr int CV = TS * TS * TS;
   constexpr int kWaves = NT / 64;
   constexpr int kRing = 128;
+  constexpr int kList = 1152;
   static_assert(2 * CV * 2 <= 2 * RV, "the deposit pairs alias the cell sums");
+  static_assert(kWaves * kRing * 4 <= kList * 6, "the ring aliases the list");
   __shared__ __align__(16) unsigned blk[2 * RV];  // cell sums, then 2 x CV 64-bit pairs
-  __shared__ int ring[kWaves][kRing];             // each wave's queued candidates
+  // the in-region candidates' records and cells (pass 1 to pass 2), or,
+  // when they overflow the list, each wave's queue of candidates (pass 2)
+  __shared__ __align__(16) unsigned char lbuf[kList * 6];
+  __shared__ int list_n;
+  uint32_t* list_rec = reinterpret_cast<uint32_t*>(lbuf);
+  unsigned short* list_cell = reinterpret_cast<unsigned short*>(lbuf + 4 * kList);
+  int (*ring)[kRing] = reinterpret_cast<int (*)[kRing]>(lbuf);
   __shared__ int nb_first[28];                    // prefix sums of the 27 candidate ranges
   __shared__ uint32_t nb_start[27];
-  __shared__ float red[kWaves][2];
+  __shared__ unsigned red[kWaves][2];
   __shared__ float scale_s[kNumFields], inv_s[kNumFields];
   __shared__ long long s_tile;
   unsigned long long* acc2 = reinterpret_cast<unsigned long long*>(blk);
@@ -1174,20 +1187,13 @@ __global__ __launch_bounds__(NT) void scatter_gather_kernel(
   for (int j = 0; j < NTAP; ++j) ksum += static_cast<double>(kb.k[j]);
   const double ksum3 = ksum * ksum * ksum * 1.00001;
 
-  // Candidate i (0 <= i < total): its record, its tile's offset d from this
-  // tile, and its cell rc relative to this tile's origin (from its own
-  // tile's origin, so that the periodic wrap is never ambiguous) with the
-  // fractions fr.  False when the cell is outside the source region.
+  // A record's position, its cell rc relative to this tile's origin and its
+  // fractions fr; true when the cell lies in the source region.  The cells
+  // of the 27-tile neighbourhood lie within [-16, 32) of the origin, so on
+  // grids of N >= 64 the periodic offset taken in [-N/2, N/2) is the true one.
   int ox = 0, oy = 0, oz = 0;
-  auto candidate = [&](int i, float4* a, uint32_t* rec, int* rc, double* fr) -> bool {
-    int lo = 0, hi = 27;  // nb_first[lo] <= i < nb_first[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (nb_first[mid] <= i) lo = mid; else hi = mid;
-    }
-    *rec = nb_start[lo] + static_cast<uint32_t>(i - nb_first[lo]);
-    *a = rec_pos<kW>(sorted, static_cast<int64_t>(*rec));
-    const int d[3] = {lo / 9 - 1, (lo / 3) % 3 - 1, lo % 3 - 1};
+  auto record_cell = [&](uint32_t rec, float4* a, int* rc, double* fr) -> bool {
+    *a = rec_pos<kW>(sorted, static_cast<int64_t>(rec));
     const int o[3] = {ox, oy, oz};
     const float xs[3] = {a->x, a->y, a->z};
     bool in = true;
@@ -1195,10 +1201,20 @@ __global__ __launch_bounds__(NT) void scatter_gather_kernel(
     for (int ax = 0; ax < 3; ++ax) {
       bool ok;
       const int c = locate(xs[ax], kp.scale, kp.shift, kp.n, &fr[ax], &ok);
-      rc[ax] = c - ((o[ax] + TS * d[ax]) & (n - 1)) + TS * d[ax];
+      rc[ax] = ((c - o[ax] + n / 2) & (n - 1)) - n / 2;
       in = in && rc[ax] >= -HI && rc[ax] < TS + H;
     }
     return in;
+  };
+  // Candidate i (0 <= i < total) of the neighbourhood's 27 record ranges.
+  auto candidate = [&](int i, float4* a, uint32_t* rec, int* rc, double* fr) -> bool {
+    int lo = 0, hi = 27;  // nb_first[lo] <= i < nb_first[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (nb_first[mid] <= i) lo = mid; else hi = mid;
+    }
+    *rec = nb_start[lo] + static_cast<uint32_t>(i - nb_first[lo]);
+    return record_cell(*rec, a, rc, fr);
   };
 
   for (int i = t; i < 2 * RV; i += NT) blk[i] = 0u;
@@ -1227,6 +1243,7 @@ __global__ __launch_bounds__(NT) void scatter_gather_kernel(
     if (t == 0) {
       nb_first[0] = 0;
       for (int r = 0; r < 27; ++r) nb_first[r + 1] += nb_first[r];
+      list_n = 0;
     }
     __syncthreads();
     const int total = nb_first[27];
@@ -1240,65 +1257,75 @@ __global__ __launch_bounds__(NT) void scatter_gather_kernel(
                      ? static_cast<float>((4294967295.0 - total) * (1.0 - 1e-6) / (static_cast<double>(total) * qmax[f]))
                      : 0.f;
       // pass 1: cell sums over the source region (rho; the largest of the
-      // momentum fields' scaled charges)
-      for (int i = t; i < total; i += NT) {
+      // momentum fields' scaled charges), their maxima from the atomics'
+      // returns, and a list of the in-region candidates (up to kList)
+      unsigned m0 = 0, m1 = 0;
+      for (int b = wave * 64; b < total; b += NT) {  // uniform within the wave
+        const int i = b + lane;
         float4 a;
         uint32_t rec;
         int rc[3];
         double fr[3];
-        if (!candidate(i, &a, &rec, rc, fr)) continue;
-        const DepositQ<float> q = charges<float>(a, rec_vel<kW>(sorted, static_cast<int64_t>(rec)), bulk, vb0, vb1, vb2);
-        const unsigned u0 = static_cast<unsigned>(ceilf(fabsf(q.q[0]) * csc[0]));
-        unsigned u1 = 0;
+        const bool in = i < total && candidate(i, &a, &rec, rc, fr);
+        const unsigned long long mask = __ballot(in);
+        int base = 0;
+        if (lane == 0 && mask) base = atomicAdd(&list_n, __popcll(mask));
+        base = __shfl(base, 0);
+        if (in) {
+          const int cell = ((rc[0] + HI) * R + rc[1] + HI) * R + rc[2] + HI;
+          const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+          if (slot < kList) {
+            list_rec[slot] = rec;
+            list_cell[slot] = static_cast<unsigned short>(cell);
+          }
+          const DepositQ<float> q = charges<float>(a, rec_vel<kW>(sorted, static_cast<int64_t>(rec)), bulk, vb0, vb1, vb2);
+          const unsigned u0 = static_cast<unsigned>(ceilf(fabsf(q.q[0]) * csc[0]));
+          unsigned u1 = 0;
 #pragma unroll
-        for (int f = 1; f < kNumFields; ++f) u1 = max(u1, static_cast<unsigned>(ceilf(fabsf(q.q[f]) * csc[f])));
-        const int cell = ((rc[0] + HI) * R + rc[1] + HI) * R + rc[2] + HI;
-        if (u0) atomicAdd(&blk[cell], u0);
-        if (u1) atomicAdd(&blk[RV + cell], u1);
-      }
-      __syncthreads();
-      // the largest cell sums, clearing the block for the deposits
-      float amax0 = 0.f, amax1 = 0.f;
-      for (int i = t; i < RV; i += NT) {
-        amax0 = fmaxf(amax0, static_cast<float>(blk[i]));
-        amax1 = fmaxf(amax1, static_cast<float>(blk[RV + i]));
-        blk[i] = 0u;
-        blk[RV + i] = 0u;
+          for (int f = 1; f < kNumFields; ++f) u1 = max(u1, static_cast<unsigned>(ceilf(fabsf(q.q[f]) * csc[f])));
+          if (u0) m0 = max(m0, atomicAdd(&blk[cell], u0) + u0);
+          if (u1) m1 = max(m1, atomicAdd(&blk[RV + cell], u1) + u1);
+        }
       }
       for (int off = 32; off > 0; off >>= 1) {
-        amax0 = fmaxf(amax0, __shfl_xor(amax0, off));
-        amax1 = fmaxf(amax1, __shfl_xor(amax1, off));
+        m0 = max(m0, static_cast<unsigned>(__shfl_xor(static_cast<int>(m0), off)));
+        m1 = max(m1, static_cast<unsigned>(__shfl_xor(static_cast<int>(m1), off)));
       }
       if (lane == 0) {
-        red[wave][0] = amax0;
-        red[wave][1] = amax1;
+        red[wave][0] = m0;
+        red[wave][1] = m1;
       }
       __syncthreads();
+      const int listed = list_n;
+      const bool fits = listed <= kList;  // uniform
       if (t < kNumFields) {
-        float mx = 0.f;
+        unsigned mx = 0;
         const int bf = t == 0 ? 0 : 1;
-        for (int w = 0; w < kWaves; ++w) mx = fmaxf(mx, red[w][bf]);
+        for (int w = 0; w < kWaves; ++w) mx = max(mx, red[w][bf]);
         // bound in charge units; room for the rounding errors of up to
         // `total` deposits per cell
         const double bound = static_cast<double>(mx) * ksum3 / static_cast<double>(csc[t]);
         const double room = 0.99 * 2147483648.0 - 0.5 * static_cast<double>(total) - 64.0;
-        const double scl = (mx > 0.f && csc[t] > 0.f) ? fmin(room / bound, 1e30) : 0.0;
+        const double scl = (mx > 0 && csc[t] > 0.f) ? fmin(room / bound, 1e30) : 0.0;
         scale_s[t] = static_cast<float>(scl);
         inv_s[t] = scl > 0.0 ? static_cast<float>(1.0 / static_cast<double>(static_cast<float>(scl))) : 0.f;
+      }
+      // clear the cell sums for the deposits: the listed cells, or all
+      if (fits) {
+        for (int j = t; j < listed; j += NT) {
+          blk[list_cell[j]] = 0u;
+          blk[RV + list_cell[j]] = 0u;
+        }
+      } else {
+        for (int i = t; i < 2 * RV; i += NT) blk[i] = 0u;
       }
       __syncthreads();
       float sc[kNumFields];
 #pragma unroll
       for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
-      // pass 2: 64 queued candidates of this wave (slots head .. head + 63,
-      // lanes beyond `m` idle) deposit the taps that land in the tile
-      auto deposit = [&](int head, int m) {
-        if (lane >= m) return;
-        float4 a;
-        uint32_t rec;
-        int rc[3];
-        double fr[3];
-        (void)candidate(ring[wave][(head + lane) & (kRing - 1)], &a, &rec, rc, fr);
+      // pass 2: one in-region particle's deposits of the taps that land in
+      // the tile
+      auto deposit_one = [&](const float4& a, uint32_t rec, const int* rc, const double* fr) {
         float wx[NTAP], wy[NTAP], wz[NTAP];
 #pragma unroll
         for (int j = 0; j < NTAP; ++j) {
@@ -1333,29 +1360,52 @@ __global__ __launch_bounds__(NT) void scatter_gather_kernel(
           }
         }
       };
-      int head = 0, queued = 0;  // uniform within the wave
-      for (int b = wave * 64; b < total; b += NT) {
-        const int i = b + lane;
-        float4 a;
-        uint32_t rec;
-        int rc[3];
-        double fr[3];
-        const bool in = i < total && candidate(i, &a, &rec, rc, fr);
-        const unsigned long long mask = __ballot(in);
-        if (in) {
-          const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-          ring[wave][(head + queued + rank) & (kRing - 1)] = i;
+      if (fits) {  // the listed records, dealt to all lanes
+        for (int j = t; j < listed; j += NT) {
+          const uint32_t rec = list_rec[j];
+          float4 a;
+          int rc[3];
+          double fr[3];
+          (void)record_cell(rec, &a, rc, fr);
+          deposit_one(a, rec, rc, fr);
         }
-        queued += __popcll(mask);
+      } else {
+        // more in-region candidates than the list holds: each wave evaluates
+        // the candidates again and queues its in-region ones in a ring of
+        // kRing LDS slots, depositing 64 at a time (lanes beyond `m` idle)
+        auto deposit = [&](int head, int m) {
+          if (lane >= m) return;
+          float4 a;
+          uint32_t rec;
+          int rc[3];
+          double fr[3];
+          (void)candidate(ring[wave][(head + lane) & (kRing - 1)], &a, &rec, rc, fr);
+          deposit_one(a, rec, rc, fr);
+        };
+        int head = 0, queued = 0;  // uniform within the wave
+        for (int b = wave * 64; b < total; b += NT) {
+          const int i = b + lane;
+          float4 a;
+          uint32_t rec;
+          int rc[3];
+          double fr[3];
+          const bool in = i < total && candidate(i, &a, &rec, rc, fr);
+          const unsigned long long mask = __ballot(in);
+          if (in) {
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+            ring[wave][(head + queued + rank) & (kRing - 1)] = i;
+          }
+          queued += __popcll(mask);
+          __builtin_amdgcn_wave_barrier();
+          if (queued >= 64) {
+            deposit(head, 64);
+            head = (head + 64) & (kRing - 1);
+            queued -= 64;
+          }
+        }
         __builtin_amdgcn_wave_barrier();
-        if (queued >= 64) {
-          deposit(head, 64);
-          head = (head + 64) & (kRing - 1);
-          queued -= 64;
-        }
+        if (queued > 0) deposit(head, queued);
       }
-      __builtin_amdgcn_wave_barrier();
-      if (queued > 0) deposit(head, queued);
       __syncthreads();
     }
     // write the tile's cells with plain stores, clearing the block

@@ -326,6 +326,8 @@ void worker_main(Server* s) {
         if (ws.d_queue) (void)hipFree(ws.d_queue);
         if (ws.h_cats) (void)hipHostFree(ws.h_cats);
         if (ws.h_starts) (void)hipHostFree(ws.h_starts);
+        for (hipEvent_t e : ws.done)
+          if (e) (void)hipEventDestroy(e);
         if (wp.sorted) (void)hipFree(wp.sorted);
         if (wp.host) (void)hipFree(wp.host);
         lk.lock();

@@ -78,8 +78,8 @@ def _grid_err(g, want):
 
 # (N, particles, weights, form): each switch point from both sides
 ASSIGN_CASES = [
-    (128, 5_000, True, "owner-computes"), (128, 131_000, False, "owner-computes"),
-    (128, 132_000, True, "halo"), (128, 1_048_000, False, "halo"), (128, 1_049_000, True, "atomic"),
+    (128, 5_000, True, "owner-computes"), (128, 196_000, False, "owner-computes"),
+    (128, 197_500, True, "halo"), (128, 1_048_000, False, "halo"), (128, 1_049_000, True, "atomic"),
     (64, 3_000, False, "atomic"), (64, 60_000, True, "atomic"),
 ]
 
@@ -112,7 +112,7 @@ def test_assign_bulk_flow_grids(mps, npart):
     assert err < GRID_TOL, err
 
 
-@pytest.mark.parametrize("n_cluster,n_wrap,form", [(20_000, 5_000, "owner-computes"), (120_000, 30_000, "halo")])
+@pytest.mark.parametrize("n_cluster,n_wrap,form", [(20_000, 5_000, "owner-computes"), (200_000, 50_000, "halo")])
 def test_clustered_catalog_and_stale_grid(mps, n_cluster, n_wrap, form):
     """A few tiles hold all the particles (a Gaussian clump around one tile
     corner, a uniform block straddling the periodic wrap), most tiles and
