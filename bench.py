@@ -39,8 +39,8 @@ DEPOSITS_PER_PARTICLE = 216 * 4
 # (FETCH_SIZE and WRITE_SIZE, one counter per run, calibrated by a 1 GiB
 # device copy), with the SHA-256 (first 16 hex digits) of the kernel source
 # the counters were taken on.  Reported only while that source is unchanged.
-SCATTER_TRAFFIC = {"bytes": 3.335e9 + 7.876e9, "read_bytes": 3.335e9, "write_bytes": 7.876e9,
-                   "source": "paper_2005_06170_amd/csrc/particles.hip", "source_sha16": "5b133dd660559446",
+SCATTER_TRAFFIC = {"bytes": 3.340e9 + 7.876e9, "read_bytes": 3.340e9, "write_bytes": 7.876e9,
+                   "source": "paper_2005_06170_amd/csrc/particles.hip", "source_sha16": "633bd2253a460898",
                    "profile": "profiles/estimate_512_f32_hbm_traffic.md"}
 
 
@@ -154,13 +154,14 @@ def time_spt(mps, n_k=1024, n_table=256, reps=5):
     return {"n_k": n_k, "n_table": n_table, "ms_per_call": 1e3 * dt, "predictions_per_s": n_k / dt}
 
 
-def batch_workload(mps, torch, seed_config=4, n_cat=64):
+def batch_workload(mps, torch, seed_config=4, n_cat=64, reps=5, sequential=True):
     """The batched form: 64 catalogs of uneven sizes (particle counts
     log-uniform in [1e5, 4e6], grids from {64, 128, 256}^3, boxes from
     {250, 500, 1000} Mpc/h, half uniform with Gaussian velocities, half
     Zel'dovich power-law lattices with rms displacement 3 Mpc/h x L/1000),
-    FP32 grids.  Times one mps_estimate_batch call over all 64 against 64
-    mps_estimate calls in sequence (plans created beforehand in both)."""
+    FP32 grids.  Times one mps_estimate_batch call over all 64 (after a
+    warm-up call, mean of `reps`) against 64 mps_estimate calls in sequence
+    (plans created beforehand in both; sequential=False skips the latter)."""
     from synth import catalogs
     rng = np.random.default_rng(catalogs.seed_for(seed_config))
     cats = []
@@ -181,17 +182,18 @@ def batch_workload(mps, torch, seed_config=4, n_cat=64):
         p.reserve(c["pos"].shape[0])
     args = [dict(pos=c["pos"], vel=c["vel"], box=c["box"], haf=c["haf"]) for c in cats]
     mps.estimate_batch(plans, args)  # warm-up (tables, bins)
-    reps = 5
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         mps.estimate_batch(plans, args)
     t_batch = (time.perf_counter() - t0) / reps
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        for p, a in zip(plans, args):
-            p.estimate(a["pos"], a["vel"], box=a["box"], haf=a["haf"])
-    t_seq = (time.perf_counter() - t0) / reps
+    t_seq = float("nan")
+    if sequential:
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for p, a in zip(plans, args):
+                p.estimate(a["pos"], a["vel"], box=a["box"], haf=a["haf"])
+        t_seq = (time.perf_counter() - t0) / reps
     for p in plans:
         p.close()
     n_part = sum(int(c["pos"].shape[0]) for c in cats)
