@@ -302,9 +302,10 @@ def reference_errors(out, pos_np, vel_np):
 
 
 def serving_pool(torch, catalogs):
-    """Device-resident request pool: particle counts log-spaced over
-    [1e6, 5e8], alternately Zel'dovich lattices (host-generated, up to 311^3)
-    and uniform catalogs with Gaussian velocities (generated on the device)."""
+    """Device-resident request pool: eight particle counts log-spaced over
+    [1e6, 5e8]; the 1e6 and 1e7 ones are Zel'dovich lattices (100^3 and
+    215^3, host-generated, lattice order), the other six uniform catalogs
+    with Gaussian velocities (generated on the device, random order)."""
     sizes = [10 ** 6, 3 * 10 ** 6, 10 ** 7, 3 * 10 ** 7, 6 * 10 ** 7, 134217728, 2.5e8, 5e8]
     pool = []
     for i, n in enumerate(sizes):
@@ -387,8 +388,8 @@ def serving_section(mps, torch, args):
     keeps up (served rate >= 95 % of offered)."""
     from synth import catalogs
     pool = serving_pool(torch, catalogs)
-    out = {"pool": "8 device-resident catalogs, 1e6-5e8 particles (4 Zel'dovich lattices up to 311^3, "
-                   "4 uniform), grids uniform in {128,256,512,1024}^3",
+    out = {"pool": "8 device-resident catalogs, 1e6-5e8 particles (Zel'dovich lattices 100^3 and 215^3, "
+                   "6 uniform in random order), grids uniform in {128,256,512,1024}^3",
            "p99_bound_ms": P99_BOUND_MS}
     for prec in ("f32", "f64"):
         out[prec] = serve_stream(mps, torch, pool, prec, args.rate, args.duration, catalogs.seed_for(5, 90),
