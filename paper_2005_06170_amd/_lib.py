@@ -28,6 +28,7 @@ STATIC_MAX_PARTICLES = 1 << 20    # MPS_STATIC_MAX_PARTICLES
 SCATTER_MIN_GRID = 128            # MPS_SCATTER_MIN_GRID
 SCATTER_GATHER_MAX_MEAN = 384     # MPS_SCATTER_GATHER_MAX_MEAN
 SCATTER_HALO_MAX_MEAN = 2048      # MPS_SCATTER_HALO_MAX_MEAN
+SCATTER_GATHER64_MAX_MEAN = 384   # MPS_SCATTER_GATHER64_MAX_MEAN
 NUM_STAGES = 9
 STAGES = ("moments+count", "scan", "permute", "clear", "scatter",
           "fft_z", "fft_y", "fft_x+bin", "finalize")

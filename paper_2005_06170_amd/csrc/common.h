@@ -105,7 +105,8 @@ struct ScatterCat {
   float* halo;             // halo form: kHaloCells x 4 fields per tile
 };
 
-// The FP32 scatter's forms (16^3 tiles, truncated BL3).  Each tile
+// The scatter's forms (16^3 tiles, truncated BL3; FP64 grids only the atomic
+// and owner-computes forms).  Each tile
 // accumulates its particles' deposits over the tile and a halo (2 cells
 // below, 3 above per axis) in LDS, then
 //   kFormAtomic: adds the whole block to the (cleared) grid with FP32 atomics;
@@ -286,8 +287,8 @@ hipError_t launch_scan(Plan* p, hipStream_t s);
 hipError_t launch_permute(Plan* p, const mps_catalog* c, hipStream_t s);
 hipError_t launch_clear_grid(Plan* p, hipStream_t s);
 hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s);
-// The catalog's scatter form (ScatterForm; kFormAtomic for FP64 grids and
-// the kernels other than the truncated BL3).
+// The catalog's scatter form (ScatterForm; FP64 grids take kFormGather or
+// kFormAtomic, the kernels other than the truncated BL3 kFormAtomic).
 int scatter_form(const Plan* p, const mps_catalog* c);
 // The form a truncated-BL3 catalog of np particles takes on an N^3 grid of
 // this precision, and the halo buffer's bytes.

@@ -24,6 +24,7 @@ constexpr int kCountThreads = 256;
 constexpr int kGatherThreads = 512;
 constexpr int64_t kGatherMaxMean = MPS_SCATTER_GATHER_MAX_MEAN;
 constexpr int64_t kHaloMaxMean = MPS_SCATTER_HALO_MAX_MEAN;
+constexpr int64_t kGather64MaxMean = MPS_SCATTER_GATHER64_MAX_MEAN;
 
 // Grid coordinate of one float32 coordinate: u = x * (N / L) + shift in FP64
 // (shift = 1/2 for the odd-order B-splines, whose taps are centred on the
@@ -1899,6 +1900,225 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
   }
 }
 
+// FP64 grids of sparse catalogs, owner-computes form: the FP32 form's
+// candidate search and in-region list (see scatter_gather_kernel), with the
+// FP64 path's 64-bit fixed point (one field per ds_add_u64, all four fields
+// of the tile's 16^3 cells in LDS: 128 KB, one workgroup per CU).  The
+// scale of a field maps the largest possible deposit, max|q| K^3, to 2^50
+// and caps a cell's sum over the n_in in-region particles below 2^62, as the
+// atomic FP64 form does for a tile's particles; no per-cell bound is needed.
+template <int NT, bool kW>
+__global__ __launch_bounds__(NT) void scatter_gather64_kernel(
+    const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, double* __restrict__ grid, KeyParams kp,
+    int64_t n_tiles, TileQueues tq, TapPoly tp, TapBound kb, const Derived* dsrc, int bulk) {
+  constexpr int TS = 16, NTAP = 6, DEG = 3;
+  constexpr int H = kHaloLo<NTAP>;
+  constexpr int HI = NTAP - 1 - H;
+  constexpr int CV = TS * TS * TS;
+  constexpr int kWaves = NT / 64;
+  constexpr int kRing = 128;
+  constexpr int kList = kWaves * kRing;  // the ring aliases the list
+  __shared__ unsigned long long acc[kNumFields * CV];
+  __shared__ uint32_t lbuf[kList];
+  __shared__ int list_n;
+  __shared__ int nb_first[28];
+  __shared__ uint32_t nb_start[27];
+  __shared__ long long s_tile;
+  uint32_t* list_rec = lbuf;
+  int (*ring)[kRing] = reinterpret_cast<int (*)[kRing]>(lbuf);
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
+  if (bulk) {
+    vb0 = dsrc->vb[0];
+    vb1 = dsrc->vb[1];
+    vb2 = dsrc->vb[2];
+  }
+  double kmax = 0.0;
+#pragma unroll
+  for (int j = 0; j < NTAP; ++j) kmax = fmax(kmax, static_cast<double>(kb.k[j]));
+  const double kmax3 = kmax * kmax * kmax;
+  double dep[kNumFields];  // the largest possible deposit per field
+#pragma unroll
+  for (int f = 0; f < kNumFields; ++f) {
+    const double vbf = f == 1 ? vb0 : (f == 2 ? vb1 : vb2);
+    dep[f] = (dsrc->qmax[f] + (bulk && f > 0 ? dsrc->qmax[0] * fabs(vbf) : 0.0)) * kmax3 * 1.0001;
+  }
+  const int nt = kp.nt, n = kp.n;
+  const int64_t n3 = static_cast<int64_t>(n) * n * n;
+  int ox = 0, oy = 0, oz = 0;
+  // a record's position, cell relative to the tile origin (the periodic
+  // offset in [-N/2, N/2), unambiguous for N >= 64) and fractions; true in
+  // the source region
+  auto record_cell = [&](uint32_t rec, float4* a, int* rc, double* fr) -> bool {
+    *a = rec_pos<kW>(sorted, static_cast<int64_t>(rec));
+    const int o[3] = {ox, oy, oz};
+    const float xs[3] = {a->x, a->y, a->z};
+    bool in = true;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      bool ok;
+      const int c = locate(xs[ax], kp.scale, kp.shift, kp.n, &fr[ax], &ok);
+      rc[ax] = ((c - o[ax] + n / 2) & (n - 1)) - n / 2;
+      in = in && rc[ax] >= -HI && rc[ax] < TS + H;
+    }
+    return in;
+  };
+  auto candidate = [&](int i, float4* a, uint32_t* rec, int* rc, double* fr) -> bool {
+    int lo = 0, hi = 27;  // nb_first[lo] <= i < nb_first[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (nb_first[mid] <= i) lo = mid; else hi = mid;
+    }
+    *rec = nb_start[lo] + static_cast<uint32_t>(i - nb_first[lo]);
+    return record_cell(*rec, a, rc, fr);
+  };
+
+  for (int i = t; i < kNumFields * CV; i += NT) acc[i] = 0ull;
+  int64_t tile = next_tile<NT>(tq, n_tiles, &s_tile);
+  while (tile >= 0) {
+    const int tz = static_cast<int>(tile % nt);
+    const int ty = static_cast<int>((tile / nt) % nt);
+    const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
+    ox = tx * TS;
+    oy = ty * TS;
+    oz = tz * TS;
+    if (t < 27) {
+      const int dx = t / 9 - 1, dy = (t / 3) % 3 - 1, dz = t % 3 - 1;
+      const int64_t tn = (static_cast<int64_t>((tx + dx + nt) % nt) * nt + (ty + dy + nt) % nt) * nt +
+                         (tz + dz + nt) % nt;
+      nb_start[t] = offset[tn];
+      nb_first[t + 1] = static_cast<int>(offset[tn + 1] - offset[tn]);
+    }
+    __syncthreads();
+    if (t == 0) {
+      nb_first[0] = 0;
+      for (int r = 0; r < 27; ++r) nb_first[r + 1] += nb_first[r];
+      list_n = 0;
+    }
+    __syncthreads();
+    const int total = nb_first[27];
+    double inv[kNumFields] = {0.0, 0.0, 0.0, 0.0};
+    if (total > 0) {  // uniform; otherwise the tile is written with zeros
+      // pass 1: the in-region candidates (up to kList listed)
+      for (int b = wave * 64; b < total; b += NT) {  // uniform within the wave
+        const int i = b + lane;
+        float4 a;
+        uint32_t rec;
+        int rc[3];
+        double fr[3];
+        const bool in = i < total && candidate(i, &a, &rec, rc, fr);
+        const unsigned long long mask = __ballot(in);
+        int base = 0;
+        if (lane == 0 && mask) base = atomicAdd(&list_n, __popcll(mask));
+        base = __shfl(base, 0);
+        if (in) {
+          const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+          if (slot < kList) list_rec[slot] = rec;
+        }
+      }
+      __syncthreads();
+      const int n_in = list_n;
+      const bool fits = n_in <= kList;  // uniform
+      double scl[kNumFields];
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) {
+        scl[f] = dep[f] > 0.0 ? fmin(0x1p50 / dep[f], 0x1p62 / (static_cast<double>(n_in) * dep[f])) : 0.0;
+        inv[f] = dep[f] > 0.0 ? 1.0 / scl[f] : 0.0;
+      }
+      // pass 2: one in-region particle's deposits of the taps that land in
+      // the tile
+      auto deposit_one = [&](const float4& a, uint32_t rec, const int* rc, const double* fr) {
+        double wx[NTAP], wy[NTAP], wz[NTAP];
+#pragma unroll
+        for (int j = 0; j < NTAP; ++j) {
+          wx[j] = tap_weight<DEG>(tp, j, fr[0]);
+          wy[j] = tap_weight<DEG>(tp, j, fr[1]);
+          wz[j] = tap_weight<DEG>(tp, j, fr[2]);
+        }
+        const DepositQ<double> d = charges<double>(a, rec_vel<kW>(sorted, static_cast<int64_t>(rec)), bulk, vb0, vb1, vb2);
+        double qs[kNumFields];
+#pragma unroll
+        for (int f = 0; f < kNumFields; ++f) qs[f] = d.q[f] * scl[f];
+#pragma unroll
+        for (int jx = 0; jx < NTAP; ++jx) {
+          const int gx = rc[0] + jx - H;
+          if (gx < 0 || gx >= TS) continue;
+#pragma unroll
+          for (int jy = 0; jy < NTAP; ++jy) {
+            const int gy = rc[1] + jy - H;
+            if (gy < 0 || gy >= TS) continue;
+            const double wxy = wx[jx] * wy[jy];
+            const int row = (gx * TS + gy) * TS;
+#pragma unroll
+            for (int jz = 0; jz < NTAP; ++jz) {
+              const int gz = rc[2] + jz - H;
+              if (gz < 0 || gz >= TS) continue;
+              const double w = wxy * wz[jz];
+#pragma unroll
+              for (int f = 0; f < kNumFields; ++f) atomicAdd(acc + f * CV + row + gz, fixed64(w * qs[f]));
+            }
+          }
+        }
+      };
+      if (fits) {
+        for (int j = t; j < n_in; j += NT) {
+          const uint32_t rec = list_rec[j];
+          float4 a;
+          int rc[3];
+          double fr[3];
+          (void)record_cell(rec, &a, rc, fr);
+          deposit_one(a, rec, rc, fr);
+        }
+      } else {  // the list overflowed and is not read: the ring takes its place
+        auto deposit = [&](int head, int m) {
+          if (lane >= m) return;
+          float4 a;
+          uint32_t rec;
+          int rc[3];
+          double fr[3];
+          (void)candidate(ring[wave][(head + lane) & (kRing - 1)], &a, &rec, rc, fr);
+          deposit_one(a, rec, rc, fr);
+        };
+        int head = 0, queued = 0;  // uniform within the wave
+        for (int b = wave * 64; b < total; b += NT) {
+          const int i = b + lane;
+          float4 a;
+          uint32_t rec;
+          int rc[3];
+          double fr[3];
+          const bool in = i < total && candidate(i, &a, &rec, rc, fr);
+          const unsigned long long mask = __ballot(in);
+          if (in) {
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+            ring[wave][(head + queued + rank) & (kRing - 1)] = i;
+          }
+          queued += __popcll(mask);
+          __builtin_amdgcn_wave_barrier();
+          if (queued >= 64) {
+            deposit(head, 64);
+            head = (head + 64) & (kRing - 1);
+            queued -= 64;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (queued > 0) deposit(head, queued);
+      }
+      __syncthreads();
+    }
+    // store the tile's cells, clearing the block
+    for (int i = t; i < CV; i += NT) {
+      const int64_t gi = (static_cast<int64_t>(ox + i / (TS * TS)) * n + oy + (i / TS) % TS) * n + oz + i % TS;
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) {
+        const long long v = static_cast<long long>(acc[f * CV + i]);
+        acc[f * CV + i] = 0ull;
+        grid[f * n3 + gi] = static_cast<double>(v) * inv[f];
+      }
+    }
+    tile = next_tile<NT>(tq, n_tiles, &s_tile);
+  }
+}
+
 template <int NTAP, int DEG, bool kW>
 hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int bulk, const TapPoly& tp,
                                const TapBound& tb) {
@@ -1961,6 +2181,25 @@ hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int
   const TapPoly& tp = p->taps[k];
   const TapBound& tb = p->tap_bound[k];
   const int form = scatter_form(p, c);
+  if (form == kFormGather && p->prec == MPS_F64) {
+    // persistent, one workgroup per CU (the LDS holds one), over every tile
+    TileQueues tq;
+    const int64_t xcd_chunk = (p->n_tiles % 8 == 0) ? p->n_tiles / 8 : 0;
+    tq.counter = p->tile_queue;
+    tq.nq = xcd_chunk > 0 ? 8 : 1;
+    tq.per_queue = xcd_chunk > 0 ? xcd_chunk : p->n_tiles;
+    clear_kernel<uint32_t><<<1, 64, 0, s>>>(p->tile_queue, 8);
+    const KeyParams kp = key_params(p, c);
+    const unsigned blocks = static_cast<unsigned>(p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus);
+    double* g = static_cast<double*>(p->grid);
+    if (c->weight)
+      scatter_gather64_kernel<1024, true><<<blocks, 1024, 0, s>>>(p->sorted, p->tile_offset, g, kp, p->n_tiles, tq,
+                                                                   tp, tb, &p->d_header->d, bulk);
+    else
+      scatter_gather64_kernel<1024, false><<<blocks, 1024, 0, s>>>(p->sorted, p->tile_offset, g, kp, p->n_tiles, tq,
+                                                                    tp, tb, &p->d_header->d, bulk);
+    return hipGetLastError();
+  }
   if (form != kFormAtomic) {
     TileQueues tq;
     const int64_t xcd_chunk = (p->n_tiles % 8 == 0) ? p->n_tiles / 8 : 0;
@@ -2009,9 +2248,10 @@ ScatterCat scatter_cat(Plan* p, const mps_catalog* c) {
 
 int scatter_form_for(int n_grid, mps_precision prec, int64_t np) {
   // on fewer than 8^3 tiles the atomic form's few workgroups are the fastest
-  if (prec != MPS_F32 || n_grid < MPS_SCATTER_MIN_GRID || np >= (static_cast<int64_t>(1) << 31)) return kFormAtomic;
+  if (n_grid < MPS_SCATTER_MIN_GRID || np >= (static_cast<int64_t>(1) << 31)) return kFormAtomic;
   const int64_t nt = n_grid / 16;
   const int64_t tiles = nt * nt * nt;
+  if (prec == MPS_F64) return np <= kGather64MaxMean * tiles ? kFormGather : kFormAtomic;
   if (np <= kGatherMaxMean * tiles) return kFormGather;
   if (np <= kHaloMaxMean * tiles) return kFormHalo;
   return kFormAtomic;

@@ -212,3 +212,60 @@ def test_batch_of_many_catalogs_matches_single_estimates(mps):
             assert e.max() < (1e-4 if f == "atomic" else 1e-10), (i, f, key, e.max())
     for p in plans:
         p.close()
+
+
+# ------------------------------------------------------------------ FP64 grids
+def _form64(n, npart):
+    from paper_2005_06170_amd import _lib
+    if n < _lib.SCATTER_MIN_GRID:
+        return "atomic"
+    return "owner-computes" if npart <= _lib.SCATTER_GATHER64_MAX_MEAN * (n // 16) ** 3 else "atomic"
+
+
+@pytest.mark.parametrize("n,npart,weights,form", [(128, 3_000, True, "owner-computes"),
+                                                  (128, 196_000, False, "owner-computes"),
+                                                  (128, 197_500, True, "atomic")])
+def test_assign_fp64_each_side_of_the_switch(mps, n, npart, weights, form):
+    """FP64 grids: the owner-computes form's 64-bit fixed point (a unit of
+    2^-50 of the largest deposit) against oracle.assign to 1e-12 of the
+    largest |grid|, the FP64 assignment bound of test_gpu_parity."""
+    assert _form64(n, npart) == form
+    pos, vel, w = catalogs.uniform_gaussian(npart, BOX, 300.0, seed=catalogs.seed_for(5, 400 + npart),
+                                            with_weights=True)
+    pos = _edge_particles(pos, n)
+    w = w if weights else None
+    g = mps.Plan(n, "f64").assign(*_dev(pos, vel, w), box=BOX).cpu().numpy()
+    err = _grid_err(g, _assign_want(pos, vel, w, n, False))
+    print(f"f64 assign N={n} {npart} ({form}): {err:.2e}", flush=True)
+    assert err < 1e-12, (form, err)
+
+
+def test_fp64_clustered_stale_grid_and_estimate(mps):
+    """FP64 owner-computes form on a clustered catalog over a stale grid:
+    every cell written (exact zeros where the oracle has none), the grids
+    within 1e-11 of the largest |q| grid (the sum of ~10^4 roundings of 2^-51
+    of the largest deposit), and the spectra against oracle.estimate."""
+    n = 128
+    plan = mps.Plan(n, "f64")
+    dpos, dvel = catalogs.uniform_gaussian(1_200_000, BOX, 300.0, seed=catalogs.seed_for(5, 411))
+    assert _form64(n, dpos.shape[0]) == "atomic"
+    plan.assign(*_dev(dpos, dvel, None), box=BOX)
+    rng = np.random.default_rng(catalogs.seed_for(5, 412))
+    t = 16 * BOX / n
+    a = rng.normal(loc=[t, 2 * t, 3 * t], scale=0.15 * t, size=(20_000, 3))
+    b = rng.uniform(-0.5 * t, 0.5 * t, size=(5_000, 3))
+    pos = np.mod(np.concatenate([a, b]), BOX).astype(np.float32)
+    vel = rng.normal(0.0, 300.0, size=pos.shape).astype(np.float32)
+    assert _form64(n, pos.shape[0]) == "owner-computes"
+    g = plan.assign(*_dev(pos, vel, None), box=BOX).cpu().numpy()
+    want = _assign_want(pos, vel, None, n, False)
+    v64 = vel.astype(np.float64)
+    q_abs = np.stack([np.ones(len(pos)), np.abs(v64[:, 0]), np.abs(v64[:, 1]), np.abs(v64[:, 2])])
+    scale = np.abs(oracle.assign(pos, q_abs, BOX, n)).max(axis=(1, 2, 3), keepdims=True)
+    err = float(np.max(np.abs(g - want) / scale))
+    print(f"f64 clustered: {err:.2e}", flush=True)
+    assert err < 1e-11, err
+    assert np.all(g[:, want[0] == 0.0] == 0.0)
+    o = oracle.estimate(pos, vel, box=BOX, n_grid=n, haf=50.0, flags=oracle.FLAG_BULKFLOW_SUBTRACT)
+    got = plan.estimate(*_dev(pos, vel, None), box=BOX, haf=50.0, bulk_flow=True)
+    compare_spectra(got, o, 1e-5, "f64 clustered estimate (owner-computes)")

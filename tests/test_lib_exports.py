@@ -30,5 +30,5 @@ def test_python_constants_match_the_header():
     text = open(os.path.join(ROOT, "include", "mps.h")).read()
     defs = dict(re.findall(r"^#define\s+(MPS_\w+)\s+(.+?)\s*(?:/\*.*)?$", text, re.M))
     for name in ("STATIC_MAX_GRID", "STATIC_MAX_PARTICLES", "SCATTER_MIN_GRID", "SCATTER_GATHER_MAX_MEAN",
-                 "SCATTER_HALO_MAX_MEAN"):
+                 "SCATTER_HALO_MAX_MEAN", "SCATTER_GATHER64_MAX_MEAN"):
         assert getattr(_lib, name) == eval(defs["MPS_" + name]), name
