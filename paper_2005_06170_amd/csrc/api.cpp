@@ -178,7 +178,7 @@ int enqueue_prescatter(Plan* p, const mps_catalog* c0, hipStream_t s, mps_catalo
   MPS_TRY(launch_count(p, used, s));
   MPS_TRY(launch_derive(p, used, s));
   mark(p, 1, s);
-  MPS_TRY(launch_scan(p, s));
+  MPS_TRY(launch_scan(p, used, s));
   mark(p, 2, s);
   MPS_TRY(launch_permute(p, used, s));
   mark(p, 3, s);

@@ -283,7 +283,7 @@ int unpack(Plan* p, const mps_catalog* c, mps_result* out, const void* stage = n
 // Launchers (particles.hip).  All enqueue on `stream`.
 hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s);
 hipError_t launch_derive(Plan* p, const mps_catalog* c, hipStream_t s);
-hipError_t launch_scan(Plan* p, hipStream_t s);
+hipError_t launch_scan(Plan* p, const mps_catalog* c, hipStream_t s);
 hipError_t launch_permute(Plan* p, const mps_catalog* c, hipStream_t s);
 hipError_t launch_clear_grid(Plan* p, hipStream_t s);
 hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s);

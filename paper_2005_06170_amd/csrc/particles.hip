@@ -198,12 +198,14 @@ __global__ __launch_bounds__(kCountThreads) void order_probe_kernel(const float*
 }
 
 // order_mode: -1 runs always; 0 only for a catalog in spatial order, 1 only
-// for one in random order (random_order()).
+// for one in random order (random_order()).  key_shift: the histogram counts
+// tile >> key_shift (the two-level sort's buckets; n_tiles is then the
+// number of buckets).
 template <bool kHasW, bool kLds>
 __global__ __launch_bounds__(kCountThreads) void count_kernel(
     const float* __restrict__ pos, const float* __restrict__ vel, const float* __restrict__ wgt,
     int64_t np, KeyParams kp, int64_t n_tiles, uint32_t* __restrict__ tile_count,
-    double* __restrict__ partials, ResultHeader* hdr, bool vec, int order_mode) {
+    double* __restrict__ partials, ResultHeader* hdr, bool vec, int order_mode, int key_shift) {
   extern __shared__ uint32_t hist[];  // n_tiles counters when kLds
   if (order_mode >= 0 && random_order(hdr) != (order_mode == 1)) return;  // uniform
   if (kLds) {
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(kCountThreads) void count_kernel(
         mx[2] = fmax(mx[2], fabs(w * dvy));
         mx[3] = fmax(mx[3], fabs(w * dvz));
       }
-      wave_run_atomic(key, valid, counts);
+      wave_run_atomic(valid ? key >> key_shift : key, valid, counts);
     }
   }
   if (kLds) {
@@ -357,8 +359,10 @@ __global__ __launch_bounds__(kMomentBlocks) void derive_kernel(const double* __r
 
 // Exclusive scan of the tile counts (one workgroup); also resets the cursor.
 __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__ count, int64_t n_tiles,
-                                                    uint32_t* __restrict__ offset, uint32_t* __restrict__ cursor) {
+                                                    uint32_t* __restrict__ offset, uint32_t* __restrict__ cursor,
+                                                    const ResultHeader* __restrict__ hdr, int order_mode) {
   __shared__ uint32_t part[1024];
+  if (order_mode >= 0 && random_order(hdr) != (order_mode == 1)) return;  // uniform
   const int64_t per = (n_tiles + 1023) / 1024;
   const int64_t lo = threadIdx.x * per;
   const int64_t hi = lo + per < n_tiles ? lo + per : n_tiles;
@@ -496,6 +500,179 @@ __global__ __launch_bounds__(kCountThreads) void permute_kernel(
         rec_store<kHasW>(sorted, static_cast<int64_t>(slot), a[u], v[u]);
       }
     }
+  }
+}
+
+// Two-level counting sort of a catalog in random order on grids whose tile
+// histogram does not fit in LDS, where one global atomic per particle would
+// bound the count (1024^3, 5e8 particles: 18.5 ms against 2.2 with bucket
+// histograms).  The tiles form kSortBuckets or fewer buckets of
+// consecutive tiles; the count histograms buckets, pass A moves the records
+// bucket by bucket to a temporary array (the grid's memory, unused until
+// the scatter), and pass B, one workgroup per bucket, counts its tiles,
+// writes their offsets and moves the records to their tiles.  Both passes
+// sort chunks of kSortChunk particles in LDS first, so that the records of
+// one bucket (tile) leave a chunk as one contiguous run.
+constexpr int kSortThreads = 512;
+constexpr int kSortChunk = 8192;
+constexpr int kSortBuckets = 1024;  // also the largest number of tiles per bucket
+static_assert(kSortChunk <= 65536, "local indices are 16-bit");
+
+// Exclusive prefix sums of a[0..n) in LDS (n <= 2 kSortThreads), in place;
+// returns the total to every thread.  Ends with a barrier.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* wsum) {
+  constexpr int kWaves = kSortThreads / 64;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const uint32_t v0 = 2 * t < n ? a[2 * t] : 0u, v1 = 2 * t + 1 < n ? a[2 * t + 1] : 0u;
+  uint32_t incl = v0 + v1;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(incl, off);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    before += w < wave ? wsum[w] : 0u;
+    total += wsum[w];
+  }
+  const uint32_t excl = before + incl - (v0 + v1);
+  if (2 * t < n) a[2 * t] = excl;
+  if (2 * t + 1 < n) a[2 * t + 1] = excl + v0;
+  __syncthreads();
+  return total;
+}
+
+// A catalog particle's record fields (w = 1 without weights).
+template <bool kHasW>
+__device__ __forceinline__ void catalog_record(const float* __restrict__ pos, const float* __restrict__ vel,
+                                               const float* __restrict__ wgt, int64_t i, float4* a, float4* v) {
+  *a = make_float4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], kHasW ? wgt[i] : 1.f);
+  *v = make_float4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.f);
+}
+
+// Pass A: the catalog's particles to `temp`, grouped by bucket (tile >>
+// shift); bucket_cur[b] starts at bucket b's first slot.
+template <bool kHasW>
+__global__ __launch_bounds__(kSortThreads) void sort_pass_a_kernel(
+    const float* __restrict__ pos, const float* __restrict__ vel, const float* __restrict__ wgt, int64_t np,
+    KeyParams kp, int shift, int n_buckets, uint32_t* __restrict__ bucket_cur, float4* __restrict__ temp,
+    const ResultHeader* __restrict__ hdr) {
+  constexpr int NT = kSortThreads, K = kSortChunk, PER = K / NT;
+  __shared__ uint32_t lstart[kSortBuckets];
+  __shared__ uint32_t gbase[kSortBuckets];
+  __shared__ unsigned short bkey[K], rank[K], perm[K];
+  __shared__ uint32_t wsum[NT / 64];
+  if (!random_order(hdr)) return;  // uniform: the one-level sort runs instead
+  const int t = threadIdx.x;
+  for (int64_t c0 = static_cast<int64_t>(blockIdx.x) * K; c0 < np; c0 += static_cast<int64_t>(gridDim.x) * K) {
+    const int m = static_cast<int>(np - c0 < K ? np - c0 : K);
+    for (int b = t; b < n_buckets; b += NT) lstart[b] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int li = t + r * NT;
+      if (li < m) {
+        const int64_t i = c0 + li;
+        bool ok;
+        const uint32_t b = tile_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], kp, &ok) >> shift;
+        bkey[li] = static_cast<unsigned short>(b);
+        rank[li] = static_cast<unsigned short>(atomicAdd(&lstart[b], 1u));
+      }
+    }
+    __syncthreads();
+    // one global reservation per bucket present in the chunk
+    for (int b = t; b < n_buckets; b += NT)
+      if (lstart[b]) gbase[b] = atomicAdd(bucket_cur + b, lstart[b]);
+    (void)block_exclusive_scan(lstart, n_buckets, wsum);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int li = t + r * NT;
+      if (li < m) perm[lstart[bkey[li]] + rank[li]] = static_cast<unsigned short>(li);
+    }
+    __syncthreads();
+    // consecutive threads store consecutive slots of a bucket's run
+    for (int j = t; j < m; j += NT) {
+      const int li = perm[j];
+      const uint32_t b = bkey[li];
+      float4 a, v;
+      catalog_record<kHasW>(pos, vel, wgt, c0 + li, &a, &v);
+      rec_store<kHasW>(temp, static_cast<int64_t>(gbase[b]) + (j - static_cast<int>(lstart[b])), a, v);
+    }
+    __syncthreads();
+  }
+}
+
+// Pass B: workgroup b sorts bucket b (temp[bucket_start[b] ..
+// bucket_start[b + 1])) by tile into `sorted` and writes its tiles' offsets
+// (the last bucket also offset[n_tiles]).
+template <bool kHasW>
+__global__ __launch_bounds__(kSortThreads) void sort_pass_b_kernel(
+    const float4* __restrict__ temp, const uint32_t* __restrict__ bucket_start, KeyParams kp, int shift,
+    int n_buckets, int64_t n_tiles, uint32_t* __restrict__ tile_offset, float4* __restrict__ sorted,
+    const ResultHeader* __restrict__ hdr) {
+  constexpr int NT = kSortThreads, K = kSortChunk, PER = K / NT;
+  __shared__ uint32_t tcur[kSortBuckets];    // next free slot of each tile of the bucket
+  __shared__ uint32_t lstart[kSortBuckets];  // chunk counts, then starts
+  __shared__ uint32_t gbase[kSortBuckets];
+  __shared__ unsigned short tkey[K], rank[K], perm[K];
+  __shared__ uint32_t wsum[NT / 64];
+  if (!random_order(hdr)) return;  // uniform
+  const int t = threadIdx.x;
+  const int b = blockIdx.x;
+  const int tiles = 1 << shift;
+  const uint32_t tile0 = static_cast<uint32_t>(b) << shift;
+  const uint32_t start = bucket_start[b], end = bucket_start[b + 1];
+  auto local_tile = [&](int64_t rec) -> uint32_t {
+    const float4 a = rec_pos<kHasW>(temp, rec);
+    bool ok;
+    return tile_key(a.x, a.y, a.z, kp, &ok) - tile0;
+  };
+  // the bucket's tile counts and offsets
+  for (int k = t; k < tiles; k += NT) tcur[k] = 0u;
+  __syncthreads();
+  for (uint32_t i = start + t; i < end; i += NT) atomicAdd(&tcur[local_tile(i)], 1u);
+  __syncthreads();
+  (void)block_exclusive_scan(tcur, tiles, wsum);
+  for (int k = t; k < tiles; k += NT) {
+    tcur[k] += start;
+    tile_offset[tile0 + k] = tcur[k];
+  }
+  if (b == n_buckets - 1 && t == 0) tile_offset[n_tiles] = end;
+  __syncthreads();
+  for (uint32_t c0 = start; c0 < end; c0 += K) {
+    const int m = static_cast<int>(end - c0 < static_cast<uint32_t>(K) ? end - c0 : K);
+    for (int k = t; k < tiles; k += NT) lstart[k] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int li = t + r * NT;
+      if (li < m) {
+        const uint32_t lt = local_tile(c0 + li);
+        tkey[li] = static_cast<unsigned short>(lt);
+        rank[li] = static_cast<unsigned short>(atomicAdd(&lstart[lt], 1u));
+      }
+    }
+    __syncthreads();
+    for (int k = t; k < tiles; k += NT) {  // this workgroup owns the bucket: no global atomics
+      gbase[k] = tcur[k];
+      tcur[k] += lstart[k];
+    }
+    (void)block_exclusive_scan(lstart, tiles, wsum);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int li = t + r * NT;
+      if (li < m) perm[lstart[tkey[li]] + rank[li]] = static_cast<unsigned short>(li);
+    }
+    __syncthreads();
+    for (int j = t; j < m; j += NT) {
+      const int li = perm[j];
+      const uint32_t lt = tkey[li];
+      const int64_t src = static_cast<int64_t>(c0) + li;
+      rec_store<kHasW>(sorted, static_cast<int64_t>(gbase[lt]) + (j - static_cast<int>(lstart[lt])),
+                       rec_pos<kHasW>(temp, src), rec_vel<kHasW>(temp, src));
+    }
+    __syncthreads();
   }
 }
 
@@ -1647,6 +1824,24 @@ int count_blocks(int64_t np) {
   return static_cast<int>(b < kMomentBlocks ? (b < 1 ? 1 : b) : kMomentBlocks);
 }
 
+// The two-level sort (for a catalog in random order, decided on the device):
+// grids of more than kLdsTilesRandom tiles, whose tile histogram does not
+// fit in LDS, when their memory holds the temporary records.  (On 512^3 the
+// one-level LDS form is faster: with 6e7 particles count + permute take
+// 3.0 ms against 3.4.)  *shift: tiles per bucket = 2^shift, about the
+// square root of the tile count (buckets and tiles per bucket both at most
+// kSortBuckets).
+bool sort_two_level(const Plan* p, const mps_catalog* c, int* shift) {
+  if (p->n_tiles <= kLdsTilesRandom) return false;
+  int l = 0;
+  while ((static_cast<int64_t>(1) << l) < p->n_tiles) ++l;
+  *shift = l / 2;
+  if ((p->n_tiles >> *shift) > kSortBuckets || (1 << *shift) > kSortBuckets) return false;
+  const size_t rec = c->weight ? 2 * sizeof(float4) : 6 * sizeof(float);
+  const size_t grid = static_cast<size_t>(kNumFields) * p->n * p->n * p->n * p->real_size;
+  return rec * static_cast<size_t>(c->n_particles) <= grid;
+}
+
 }  // namespace
 
 hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
@@ -1668,13 +1863,23 @@ hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn));
     count_kernel<kW, kL><<<nb, kCountThreads, dyn, s>>>(c->pos, c->vel, c->weight, c->n_particles, kp, p->n_tiles,
                                                         p->tile_count, p->moment_partials, p->d_header,
-                                                        vec_aligned(c), mode);
+                                                        vec_aligned(c), mode, 0);
   };
+  int shift = 0;
+  const bool two = sort_two_level(p, c, &shift);
   auto both = [&](auto has_w) {
     using T_ = std::true_type;
     using F_ = std::false_type;
     if (p->n_tiles <= kLdsTiles) {
       go(has_w, T_{}, -1);
+    } else if (two) {  // random order: bucket histograms in LDS
+      order_probe_kernel<<<kProbeChunks, kCountThreads, 0, s>>>(c->pos, c->n_particles, kp, p->d_header);
+      go(has_w, F_{}, 0);
+      constexpr bool kW = decltype(has_w)::value;
+      const int64_t nbk = p->n_tiles >> shift;
+      count_kernel<kW, true><<<nb, kCountThreads, sizeof(uint32_t) * nbk, s>>>(
+          c->pos, c->vel, c->weight, c->n_particles, kp, nbk, p->tile_count, p->moment_partials, p->d_header,
+          vec_aligned(c), 1, shift);
     } else if (p->n_tiles <= kLdsTilesRandom) {
       order_probe_kernel<<<kProbeChunks, kCountThreads, 0, s>>>(c->pos, c->n_particles, kp, p->d_header);
       go(has_w, F_{}, 0);
@@ -1694,8 +1899,17 @@ hipError_t launch_derive(Plan* p, const mps_catalog* c, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan(Plan* p, hipStream_t s) {
-  scan_kernel<<<1, 1024, 0, s>>>(p->tile_count, p->n_tiles, p->tile_offset, p->tile_cursor);
+hipError_t launch_scan(Plan* p, const mps_catalog* c, hipStream_t s) {
+  int shift = 0;
+  if (sort_two_level(p, c, &shift)) {
+    // spatial order: the tiles; random order: the buckets (starts in
+    // tile_cursor[0 .. B], pass A's cursors in tile_count[B .. 2B))
+    const int64_t nbk = p->n_tiles >> shift;
+    scan_kernel<<<1, 1024, 0, s>>>(p->tile_count, p->n_tiles, p->tile_offset, p->tile_cursor, p->d_header, 0);
+    scan_kernel<<<1, 1024, 0, s>>>(p->tile_count, nbk, p->tile_cursor, p->tile_count + nbk, p->d_header, 1);
+  } else {
+    scan_kernel<<<1, 1024, 0, s>>>(p->tile_count, p->n_tiles, p->tile_offset, p->tile_cursor, p->d_header, -1);
+  }
   return hipGetLastError();
 }
 
@@ -1712,11 +1926,25 @@ hipError_t launch_permute(Plan* p, const mps_catalog* c, hipStream_t s) {
                                                           p->n_tiles, p->tile_cursor, p->sorted, vec_aligned(c),
                                                           p->d_header, mode);
   };
+  int shift = 0;
+  const bool two = sort_two_level(p, c, &shift);
   auto both = [&](auto has_w) {
     using T_ = std::true_type;
     using F_ = std::false_type;
+    constexpr bool kW = decltype(has_w)::value;
     if (p->n_tiles <= kLdsTiles) {
       go(has_w, T_{}, -1);
+    } else if (two) {  // the order probe ran with the count; temporary records in the grid
+      go(has_w, F_{}, 0);
+      const int nbk = static_cast<int>(p->n_tiles >> shift);
+      float4* temp = static_cast<float4*>(p->grid);
+      const int64_t chunks = (c->n_particles + kSortChunk - 1) / kSortChunk;
+      const int64_t cap = 2 * static_cast<int64_t>(p->num_cus);
+      sort_pass_a_kernel<kW><<<static_cast<unsigned>(chunks < cap ? (chunks < 1 ? 1 : chunks) : cap), kSortThreads, 0,
+                               s>>>(c->pos, c->vel, c->weight, c->n_particles, kp, shift, nbk, p->tile_count + nbk,
+                                    temp, p->d_header);
+      sort_pass_b_kernel<kW><<<static_cast<unsigned>(nbk), kSortThreads, 0, s>>>(
+          temp, p->tile_cursor, kp, shift, nbk, p->n_tiles, p->tile_offset, p->sorted, p->d_header);
     } else if (p->n_tiles <= kLdsTilesRandom) {  // the order probe ran with the count
       go(has_w, F_{}, 0);
       go(has_w, T_{}, 1);
