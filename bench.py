@@ -39,8 +39,8 @@ DEPOSITS_PER_PARTICLE = 216 * 4
 # (FETCH_SIZE and WRITE_SIZE, one counter per run, calibrated by a 1 GiB
 # device copy), with the SHA-256 (first 16 hex digits) of the kernel source
 # the counters were taken on.  Reported only while that source is unchanged.
-SCATTER_TRAFFIC = {"bytes": 3.340e9 + 7.876e9, "read_bytes": 3.340e9, "write_bytes": 7.876e9,
-                   "source": "paper_2005_06170_amd/csrc/particles.hip", "source_sha16": "633bd2253a460898",
+SCATTER_TRAFFIC = {"bytes": 3.338e9 + 7.876e9, "read_bytes": 3.338e9, "write_bytes": 7.876e9,
+                   "source": "paper_2005_06170_amd/csrc/particles.hip", "source_sha16": "5cebb5be3a5489db",
                    "profile": "profiles/estimate_512_f32_hbm_traffic.md"}
 
 
@@ -233,17 +233,24 @@ def resolution_study(mps, pos, vel, n_lo=N_GRID // 2):
 
 
 def cpu_baseline():
-    """The oracle on 1/64 of the workload, stage by stage: a 128^3-particle
-    Zel'dovich catalog of the same construction (rms 8 Mpc/h scaled with the
-    lattice spacing kept, i.e. the same catalog family) on a 128^3 grid, 64x
-    fewer particles and cells.  Every stage scales linearly with particles or
-    cells except the FFT (N log N: x1.29 more per cell at 512^3, applied)."""
+    """The oracle on 1/8 of the workload, stage by stage: a 256^3-particle
+    Zel'dovich catalog of the same construction on a 256^3 grid, 8x fewer
+    particles and cells.  The assignment runs the oracle's chunked form
+    (oracle/large.py) on a fork pool of one worker per host thread (at most
+    16, the host share of one GPU), the FFT on as many threads; the moments
+    and the per-mode and binning steps are single-threaded numpy.  Every
+    stage scales linearly with particles or cells except the FFT (N log N:
+    x8 x 9/8).  Runs before anything touches the GPU, so that the pool forks
+    a process without GPU state."""
+    import multiprocessing as mp
+
     import scipy.fft
 
-    import oracle
     from oracle import estimator as E
+    from oracle import large
     from synth import catalogs
-    n = 128
+    n = 256
+    threads = min(16, os.cpu_count() or 1)
     pos, vel = catalogs.zeldovich(n, BOX, RMS, haf=HAF, seed=catalogs.seed_for(3, 1))
     t = {}
     t0 = time.perf_counter()
@@ -253,25 +260,27 @@ def cpu_baseline():
     v = vel.astype(np.float64)
     charges = np.stack([w, v[:, 0], v[:, 1], v[:, 2]])
     t0 = time.perf_counter()
-    grids = E.assign(pos, charges, BOX, n)
+    chunk = 1 << 16  # particles per pool task (a few x planes each)
+    grids = large.assign_chunked(pos, charges, BOX, n, chunk=chunk, workers=threads)
     t["assign"] = time.perf_counter() - t0
+    del charges
     t0 = time.perf_counter()
-    F = scipy.fft.fftn(grids, axes=(1, 2, 3), workers=-1)
+    F = scipy.fft.fftn(grids, axes=(1, 2, 3), workers=threads)
     t["fft"] = time.perf_counter() - t0
+    del grids
     t0 = time.perf_counter()
     q = E.mode_quantities(F, mom, BOX, n, HAF)
     E.bin_modes(q, BOX, n, n_bins=32)
     t["per_mode_and_bin"] = time.perf_counter() - t0
-    fft_scale = 64.0 * math.log(512) / math.log(128)
-    scaled = {k: v * (fft_scale if k == "fft" else 64.0) for k, v in t.items()}
+    fft_scale = 8.0 * math.log(512) / math.log(256)
+    scaled = {k: val * (fft_scale if k == "fft" else 8.0) for k, val in t.items()}
     total = sum(scaled.values())
-    cores = os.cpu_count()
-    return {"value": 1.0 / total, "unit": "catalogs/s", "cores": cores, "kind": "oracle",
-            "sample": (f"oracle stages on a 128^3-particle Zel'dovich catalog on a 128^3 grid (1/64 of the "
-                       f"particles and cells), scaled x64 (FFT x{fft_scale:.1f}); the FFT uses all {cores} "
-                       f"host threads, the numpy moments, bincount assignment and per-mode steps one"),
-            "stage_s_sample": t, "stage_s_scaled": scaled, "threads_by_stage":
-                {"moments": 1, "assign": 1, "fft": cores, "per_mode_and_bin": 1}}
+    return {"value": 1.0 / total, "unit": "catalogs/s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle stages on a 256^3-particle Zel'dovich catalog on a 256^3 grid (1/8 of the "
+                       f"particles and cells), scaled x8 (FFT x{fft_scale:.1f}); the assignment on {threads} "
+                       f"fork-pool workers, the FFT on {threads} threads, the moments and per-mode steps on one"),
+            "stage_s_sample": t, "stage_s_scaled": scaled, "start_method": mp.get_start_method(allow_none=True),
+            "threads_by_stage": {"moments": 1, "assign": threads, "fft": threads, "per_mode_and_bin": 1}}
 
 
 def reference_errors(out, pos_np, vel_np):
@@ -476,6 +485,12 @@ def main():
         serving(args)
         return
 
+    cpu = None
+    if not args.no_cpu_baseline:
+        _log("timing the CPU oracle sample (before the GPU is touched)")
+        cpu = cpu_baseline()
+        _log(f"oracle: {cpu['value']:.5f} catalogs/s; stages {cpu['stage_s_sample']}")
+
     import torch
     import paper_2005_06170_amd as mps
     from synth import catalogs
@@ -585,11 +600,6 @@ def main():
         torch.cuda.empty_cache()
         _log("serving streams (config 5)")
         serving_out = serving_section(mps, torch, args)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        _log("timing the CPU oracle sample")
-        cpu = cpu_baseline()
 
     line = {
         "metric": "catalogs/sec (P_pp,P_\u03b8\u03b8,P_\u03b4\u03b8) at 512^3 grid, 134M particles; p50/p99 latency",
