@@ -212,7 +212,9 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
   mps_plan* created = nullptr;
   if (adm->action == Admission::kCreate) {
     st = mps_plan_create(&created, pp->n_grid, pp->prec);
-    if (st == MPS_OK && adm->cap > 0) st = mps_plan_reserve(created, adm->cap);
+    // the records only: the halo buffer is reserved when a request needs it
+    // (mps_plan_reserve would also allocate it for any plan that could)
+    if (st == MPS_OK && adm->cap > 0) st = ensure_particles(reinterpret_cast<Plan*>(created), adm->cap);
     if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(created), adm->host_cap);
     if (st == MPS_OK && adm->halo) st = ensure_halo(reinterpret_cast<Plan*>(created));
     if (st != MPS_OK && created) {
@@ -220,7 +222,7 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
       created = nullptr;
     }
   } else if (adm->action == Admission::kGrow) {
-    if (adm->cap > 0) st = mps_plan_reserve(pp->plan, adm->cap);
+    if (adm->cap > 0) st = ensure_particles(reinterpret_cast<Plan*>(pp->plan), adm->cap);
     if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(pp->plan), adm->host_cap);
     if (st == MPS_OK && adm->halo) st = ensure_halo(reinterpret_cast<Plan*>(pp->plan));
   }
