@@ -49,6 +49,7 @@ void release(Plan* p) {
   dfree(p->tile_cursor);
   dfree(p->tile_queue);
   dfree(p->halo);
+  dfree(p->pair_scratch);
   dfree(p->moment_partials);
   dfree(p->d_header);
   for (int k = 0; k < kNumKernels; ++k) {
@@ -130,9 +131,26 @@ int ensure_halo(Plan* p) {
   return dalloc(&p->halo, b) == hipSuccess ? MPS_OK : MPS_E_NOMEM;
 }
 
+// Whether the FP32 scatter of np particles can take paired deposits: 16^3
+// tiles in the atomic form.
+static bool pairs_reachable(int n, mps_precision prec, int64_t np) {
+  return prec == MPS_F32 && tile_for(n, prec) == 16 && scatter_form_for(n, prec, np) == kFormAtomic;
+}
+
+int ensure_pair_scratch(Plan* p) {
+  if (p->pair_scratch) return MPS_OK;
+  const size_t b = pair_scratch_bytes(p->n_tiles, p->num_cus);
+  if (dalloc(&p->pair_scratch, b) != hipSuccess) return MPS_E_NOMEM;
+  p->pair_blocks = static_cast<int>(b / (kPairCap * sizeof(uint32_t)));
+  return MPS_OK;
+}
+
 int ensure_scatter_space(Plan* p, const mps_catalog* c) {
-  const int st = ensure_particles(p, c->n_particles);
+  int st = ensure_particles(p, c->n_particles);
   if (st != MPS_OK) return st;
+  if (kernel_id(c->flags) == 0 && pairs_reachable(p->n, p->prec, c->n_particles) &&
+      (st = ensure_pair_scratch(p)) != MPS_OK)
+    return st;
   if (kernel_id(c->flags) == 0 && scatter_form_for(p->n, p->prec, c->n_particles) == kFormHalo) return ensure_halo(p);
   return MPS_OK;
 }
@@ -511,8 +529,11 @@ int mps_plan_destroy(mps_plan* plan) {
 int mps_plan_reserve(mps_plan* plan, int64_t max_particles) {
   if (!plan || max_particles < 1 || max_particles > 0x7fffffffll) return MPS_E_ARG;
   Plan* p = reinterpret_cast<Plan*>(plan);
-  const int st = ensure_particles(p, max_particles);
+  int st = ensure_particles(p, max_particles);
   if (st != MPS_OK) return st;
+  // the paired deposits' scratch, if such a catalog can take the atomic
+  // scatter
+  if (pairs_reachable(p->n, p->prec, max_particles) && (st = ensure_pair_scratch(p)) != MPS_OK) return st;
   // the halo buffer too, if a catalog of at most max_particles can take the
   // halo scatter (the catalogs just above the owner-computes range)
   const int64_t nt = p->n / 16;
@@ -536,6 +557,7 @@ size_t mps_footprint(int n_grid, mps_precision prec, int64_t n_particles) {
   b += sizeof(double) * (kMomentBlocks * (kMomentSums + kMomentMax) + 2 * kNumKernels * (half + 1)) +
        2 * rs * n_grid + sizeof(ResultHeader);
   if (scatter_form_for(n_grid, prec, n_particles) == kFormHalo) b += halo_bytes(n_grid, prec);
+  if (pairs_reachable(n_grid, prec, n_particles)) b += pair_scratch_bytes(tiles, kPairBlocks);
   return b;
 }
 
@@ -847,13 +869,17 @@ int mps_estimate_subcubes(mps_plan* plan, const mps_catalog* cat, int n_div, mps
   if ((st = ensure_sub_lanes(p)) != MPS_OK) return st;
   Plan* lane[Plan::kSubLanes];
   bool halo = false;  // a sub-catalog takes the halo scatter
-  for (uint32_t c : count)
+  bool pairs = false;  // or paired deposits
+  for (uint32_t c : count) {
     halo = halo || (c > 0 && kernel_id(sub.flags) == 0 && scatter_form_for(p->n, p->prec, c) == kFormHalo);
+    pairs = pairs || (c > 0 && kernel_id(sub.flags) == 0 && pairs_reachable(p->n, p->prec, c));
+  }
   for (int i = 0; i < Plan::kSubLanes; ++i) {
     lane[i] = i == 0 ? p : p->sub_plan[i - 1];
     if ((st = ensure_bins(lane[i], &sub)) != MPS_OK) return st;
     if ((st = ensure_particles(lane[i], largest)) != MPS_OK) return st;
     if (halo && (st = ensure_halo(lane[i])) != MPS_OK) return st;
+    if (pairs && (st = ensure_pair_scratch(lane[i])) != MPS_OK) return st;
   }
   std::vector<mps_catalog> cats(n_cubes, sub);
   int64_t off = 0;

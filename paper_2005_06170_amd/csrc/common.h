@@ -121,6 +121,21 @@ struct ScatterCat {
 enum ScatterForm { kFormAtomic = 0, kFormGather = 1, kFormHalo = 2 };
 constexpr int kHaloCells = 21 * 21 * 21 - 16 * 16 * 16;  // halo cells of a 16^3 tile's block
 
+// Paired deposits of the FP32 atomic form (16^3 tiles, truncated BL3, one
+// catalog per launch): a dense tile's particles are sorted by cell, and two
+// particles in one cell or in z-neighbouring cells of one (x, y) column
+// deposit together over 7 z cells instead of 2 x 6.  Each workgroup keeps
+// its tile's job list in its own slice of global scratch, kPairCap words;
+// tiles of more than kPairCap particles, and workgroups beyond `blocks`,
+// deposit unpaired.
+constexpr int kPairCap = 16384;
+constexpr int kPairBlocks = 256;  // most workgroups a plan's scratch covers
+struct PairWork {
+  uint32_t* base;  // blocks x kPairCap words, or null (unpaired only)
+  int blocks;
+};
+size_t pair_scratch_bytes(int64_t n_tiles, int num_cus);
+
 // Layout of the device result block copied back to the host.
 struct ResultHeader {
   double sums[kMomentSums];
@@ -174,6 +189,8 @@ struct Plan {
   uint32_t* tile_cursor = nullptr;   // n_tiles
   uint32_t* tile_queue = nullptr;    // 8 work-queue counters of the scatter
   float* halo = nullptr;             // halo form: n_tiles x 4 x kHaloCells (allocated on first use)
+  uint32_t* pair_scratch = nullptr;  // paired deposits (FP32, 16^3 tiles; allocated on first use)
+  int pair_blocks = 0;
   int num_cus = 256;
   double* moment_partials = nullptr; // kMomentBlocks x (kMomentSums + kMomentMax)
   ResultHeader* d_header = nullptr;
@@ -298,6 +315,7 @@ size_t halo_bytes(int n_grid, mps_precision prec);
 // halo form, the halo buffer (api.cpp).
 int ensure_scatter_space(Plan* p, const mps_catalog* c);
 int ensure_halo(Plan* p);
+int ensure_pair_scratch(Plan* p);
 // The multi-catalog scatter: one launch over the tiles of several catalogs
 // of one group (d_cats, d_starts: device arrays of n_cats descriptors and
 // n_cats + 1 tile prefix sums; d_queue: 8 counters), followed for the halo

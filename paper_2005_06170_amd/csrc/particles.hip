@@ -799,6 +799,35 @@ __device__ __forceinline__ void unpack_pair(unsigned long long s, int* lo, int* 
   *hi = static_cast<int>(static_cast<unsigned>(s >> 32) + (*lo < 0 ? 1u : 0u));
 }
 
+// Two particles' deposits into one cell, packed as deposit_pair: the low and
+// high words round wlo_a wz_a + wlo_b wz_b and whi_a wz_a + whi_b wz_b (each
+// an FP32 fused sum) once; the sign indicator is that of the low word.
+__device__ __forceinline__ unsigned long long deposit_pair2(float alo, float ahi, float wa, float blo, float bhi,
+                                                            float wb) {
+  const float x = fmaf(blo, wb, alo * wa);
+  const int lo = round_to_int(x);
+  const float neg = __builtin_amdgcn_fmed3f(fmaf(x, -0x1p40f, -0x1p39f), 0.f, 1.f);
+  const int hi = round_to_int(fmaf(ahi, wa, fmaf(bhi, wb, -neg)));
+  return (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) | static_cast<unsigned>(lo);
+}
+
+// Cell (x, y, z fastest) of a 16^3 tile holding a tap origin of its 21^3
+// block (6 taps: the origin is 2 cells below the particle's cell).
+__device__ __forceinline__ unsigned origin_cell(unsigned base) {
+  constexpr unsigned E = 21;
+  const unsigned cx = base / (E * E), cy = (base / E) % E, cz = base % E;
+  return (cx * 16u + cy) * 16u + cz;
+}
+
+// cell | rank << 12: the rank is the particle's place among its cell's
+// particles, from 16-bit counters packed two per word.
+__device__ __forceinline__ unsigned cell_rank(unsigned base, unsigned* ccnt) {
+  const unsigned cell = origin_cell(base);
+  const unsigned sh = (cell & 1u) << 4;
+  const unsigned rank = (atomicAdd(ccnt + (cell >> 1), 1u << sh) >> sh) & 0xffffu;
+  return cell | rank << 12;
+}
+
 // LDS word index of a particle's tap origin (cell relative to the tile
 // origin, halo offset included) without the tap weights.
 template <int TS, int NTAP>
@@ -948,10 +977,21 @@ __device__ __forceinline__ int64_t next_item(const TileQueues& tq, int64_t n_ite
 // kMulti: one launch over the tiles of several catalogs (ScatterCat array
 // `cats`, item prefix sums `starts`), so that catalogs with few tiles share
 // the GPU; otherwise the one catalog `one`.
+//
+// Paired deposits (atomic form, 16^3 tiles, truncated BL3, one catalog,
+// scratch in pw):
+// a dense tile's particles are counting-sorted by cell (16-bit counters in
+// LDS, the sorted order in the workgroup's global scratch); sorted positions
+// 2j and 2j + 1 form one job when their cells are equal or z-neighbours of
+// one (x, y) column, else two.  A pair job deposits both particles over the 7 z cells
+// they span with 7 atomics per (x, y) tap and field pair instead of 12, at
+// about the same VALU cost per particle; LDS atomics and VALU issue bound
+// the unpaired deposits about equally.  Jobs are bank-sorted like particles,
+// pairs and singles in separate wave slots.
 template <int TS, int NT, int NTAP, int DEG, bool kW, bool kMulti, bool kHalo = false>
 __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     ScatterCat one, const ScatterCat* __restrict__ cats, const int64_t* __restrict__ starts, int n_cats,
-    int64_t n_items, TileQueues tq, TapPoly tp, TapBound kb) {
+    int64_t n_items, TileQueues tq, TapPoly tp, TapBound kb, PairWork pw) {
   static_assert(!kHalo || (TS == 16 && NTAP == 6), "the halo layout is that of 16^3 tiles with taps -2..3");
   constexpr int H = kHaloLo<NTAP>;
   constexpr int E = TS + NTAP - 1;
@@ -963,6 +1003,14 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   constexpr int kBoundFields = 2;                 // rho, and the momentum fields together
   __shared__ __align__(16) int acc[kNumFields * VOL];
   __shared__ BankSort<NT, kPer> bs;
+  // paired deposits: the 16-bit cell counts, then cell starts, of a tile
+  // (two per word) in the bank sort's index array, which they do not use
+  constexpr bool kPairOK = TS == 16 && NT == 1024 && NTAP == 6 && DEG == 3 && !kMulti && !kHalo;
+  constexpr int kCellWords = TS * TS * TS / 2;
+  static_assert(!kPairOK || kCellWords * 4 <= NT * kPer * 2, "cell counts alias the bank-sort index array");
+  static_assert(!kPairOK || kCellWords == 2 * NT, "two count words per thread");
+  unsigned* ccnt = reinterpret_cast<unsigned*>(bs.idx);
+  __shared__ unsigned wsum[kWaves];
   __shared__ float red[kWaves][kNumFields];
   __shared__ float scale_s[kNumFields], inv_s[kNumFields];
   __shared__ long long s_tile;
@@ -1024,6 +1072,8 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   int64_t item = next_item<NT, kMulti>(tq, n_items, starts, n_cats, &s_tile);
   for (int i = t; i < kNumFields * VOL; i += NT) acc[i] = 0;
   if (t < 64) bs.cnt[t] = 0;
+  if constexpr (kPairOK)
+    for (int i = t; i < kCellWords; i += NT) ccnt[i] = 0u;
   __syncthreads();
 
   while (item >= 0) {
@@ -1077,6 +1127,9 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     // A sparse tile skips the per-cell bound: every cell holds at most
     // sum_p |q_p| K^3, and only the tap-origin bounding box is flushed.
     const bool sparse = cnt <= kSparse;  // uniform across the workgroup
+    const bool paired = kPairOK && !sparse && pw.base != nullptr && cnt <= static_cast<uint32_t>(kPairCap) &&
+                        static_cast<int>(blockIdx.x) < pw.blocks;
+    uint32_t* const pjobs = paired ? pw.base + static_cast<int64_t>(blockIdx.x) * kPairCap : nullptr;
     float qsum[kNumFields] = {0.f, 0.f, 0.f, 0.f};
     unsigned key0[kPer];
 #pragma unroll
@@ -1086,8 +1139,12 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         const int64_t p = static_cast<int64_t>(p0) + t + r * NT;
         const float4 a = rec_pos<kW>(sorted, p);
         const unsigned base = tap_origin<TS, NTAP>(a, kp, ox, oy, oz);
-        const unsigned b = base & 31u;
-        key0[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
+        if (paired) {
+          key0[r] = cell_rank(base, ccnt);
+        } else {
+          const unsigned b = base & 31u;
+          key0[r] = b | (static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6);
+        }
         if (sparse) {
           const DepositQ<float> d = charges<float>(a, rec_vel<kW>(sorted, p), bulk, vb0, vb1, vb2);
 #pragma unroll
@@ -1115,7 +1172,10 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     } else {
     for (uint32_t p = p0 + static_cast<uint32_t>(m0) + t; p < p1; p += NT) {
       const float4 a = rec_pos<kW>(sorted, static_cast<int64_t>(p));
-      add_cell_sums(a, rec_vel<kW>(sorted, static_cast<int64_t>(p)), tap_origin<TS, NTAP>(a, kp, ox, oy, oz) + kCellOff);
+      const unsigned base = tap_origin<TS, NTAP>(a, kp, ox, oy, oz);
+      add_cell_sums(a, rec_vel<kW>(sorted, static_cast<int64_t>(p)), base + kCellOff);
+      // the cell key in the (free) accumulator words of fields 2, 3
+      if (paired) reinterpret_cast<unsigned*>(acc)[2 * VOL + (p - p0)] = cell_rank(base, ccnt);
     }
     __syncthreads();
     // the largest cell sum of each bound field (only the tile's own cells
@@ -1138,24 +1198,85 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       if (lane == 0) red[wave][f] = m;
     }
     }  // dense tile
+    // The tile's fixed-point scale of each field (one thread per field).
+    auto set_scale = [&]() {
+      float mx = 0.f;
+      const int bf = t < kBoundFields ? t : kBoundFields - 1;  // dense: the field's bound field
+      for (int w = 0; w < kWaves; ++w) mx = sparse ? mx + red[w][t] : fmaxf(mx, red[w][bf]);
+      // A in charge units (with a margin for the FP32 convolution, or the
+      // sum bound of a sparse tile); room for the rounding errors of up to
+      // cnt deposits per cell
+      const double bound = sparse ? static_cast<double>(mx) * static_cast<double>(kmax3) * 1.0001
+                                  : static_cast<double>(mx) * ksum3 / static_cast<double>(csc[t]);
+      const double room = 0.99 * 2147483648.0 - 0.5 * static_cast<double>(cnt) - 64.0;
+      const double scl = (mx > 0.f && (sparse || csc[t] > 0.f)) ? fmin(room / bound, 1e30) : 0.0;
+      scale_s[t] = static_cast<float>(scl);
+      inv_s[t] = scl > 0.0 ? static_cast<float>(1.0 / static_cast<double>(static_cast<float>(scl))) : 0.f;
+    };
+    // Paired path, one field pair k (fields 2k, 2k + 1) per call, so that a
+    // tile's jobs fill twice as many wave slots.  One particle (record p):
+    auto deposit_one = [&](uint32_t p, int k, const float (&sc)[kNumFields]) {
+      const float4 a = rec_pos<kW>(sorted, static_cast<int64_t>(p));
+      const float4 v = rec_vel<kW>(sorted, static_cast<int64_t>(p));
+      float wx[NTAP], wy[NTAP], wz[NTAP];
+      const unsigned base = particle_taps<float, TS, NTAP, DEG>(a, kp, ox, oy, oz, tp, wx, wy, wz);
+      const DepositQ<float> d = charges<float>(a, v, bulk, vb0, vb1, vb2);
+      const float qlo = k ? d.q[2] * sc[2] : d.q[0] * sc[0];
+      const float qhi = k ? d.q[3] * sc[3] : d.q[1] * sc[1];
+      unsigned long long* const accp = acc2 + k * VOL + base;
+#pragma unroll
+      for (int jx = 0; jx < NTAP; ++jx) {
+#pragma unroll
+        for (int jy = 0; jy < NTAP; ++jy) {
+          const float wxy = wx[jx] * wy[jy];
+          const float wlo = wxy * qlo, whi = wxy * qhi;
+#pragma unroll
+          for (int jz = 0; jz < NTAP; ++jz) atomicAdd(accp + (jx * E + jy) * E + jz, deposit_pair(wlo, whi, wz[jz]));
+        }
+      }
+    };
+    // Two particles (records pa, pb; pb's cell is pa's or the one above it
+    // along z) over the NTAP + 1 z cells from pa's tap origin.
+    auto deposit_two = [&](uint32_t pa, uint32_t pb, int k, const float (&sc)[kNumFields]) {
+      const float4 a0 = rec_pos<kW>(sorted, static_cast<int64_t>(pa));
+      const float4 v0 = rec_vel<kW>(sorted, static_cast<int64_t>(pa));
+      const float4 a1 = rec_pos<kW>(sorted, static_cast<int64_t>(pb));
+      const float4 v1 = rec_vel<kW>(sorted, static_cast<int64_t>(pb));
+      float wx0[NTAP], wy0[NTAP], wz0[NTAP], wx1[NTAP], wy1[NTAP], wz1[NTAP];
+      const unsigned base = particle_taps<float, TS, NTAP, DEG>(a0, kp, ox, oy, oz, tp, wx0, wy0, wz0);
+      const unsigned base1 = particle_taps<float, TS, NTAP, DEG>(a1, kp, ox, oy, oz, tp, wx1, wy1, wz1);
+      const bool up = base1 != base;
+      float wzb[NTAP + 1];  // the second particle's z weights on the pair's cells
+      wzb[0] = up ? 0.f : wz1[0];
+#pragma unroll
+      for (int j = 1; j < NTAP; ++j) wzb[j] = up ? wz1[j - 1] : wz1[j];
+      wzb[NTAP] = up ? wz1[NTAP - 1] : 0.f;
+      const DepositQ<float> d0 = charges<float>(a0, v0, bulk, vb0, vb1, vb2);
+      const DepositQ<float> d1 = charges<float>(a1, v1, bulk, vb0, vb1, vb2);
+      const float qalo = k ? d0.q[2] * sc[2] : d0.q[0] * sc[0];
+      const float qahi = k ? d0.q[3] * sc[3] : d0.q[1] * sc[1];
+      const float qblo = k ? d1.q[2] * sc[2] : d1.q[0] * sc[0];
+      const float qbhi = k ? d1.q[3] * sc[3] : d1.q[1] * sc[1];
+      unsigned long long* const accp = acc2 + k * VOL + base;
+#pragma unroll
+      for (int jx = 0; jx < NTAP; ++jx) {
+#pragma unroll
+        for (int jy = 0; jy < NTAP; ++jy) {
+          const float wxa = wx0[jx] * wy0[jy], wxb = wx1[jx] * wy1[jy];
+          const float alo = wxa * qalo, ahi = wxa * qahi;
+          const float blo = wxb * qblo, bhi = wxb * qbhi;
+          unsigned long long* row = accp + (jx * E + jy) * E;
+#pragma unroll
+          for (int jz = 0; jz < NTAP; ++jz) atomicAdd(row + jz, deposit_pair2(alo, ahi, wz0[jz], blo, bhi, wzb[jz]));
+          if (up) atomicAdd(row + NTAP, deposit_pair(blo, bhi, wzb[NTAP]));
+        }
+      }
+    };
     // One super-chunk: scan the bank counters, place local indices in bank
     // order, deposit.  key[r] = bank | slot << 6 of local particle t + r NT.
     auto deposit_chunk = [&](uint32_t c0, int m, const unsigned (&key)[kPer], bool first) {
       __syncthreads();
-      if (first && t < kNumFields) {
-        float mx = 0.f;
-        const int bf = t < kBoundFields ? t : kBoundFields - 1;  // dense: the field's bound field
-        for (int w = 0; w < kWaves; ++w) mx = sparse ? mx + red[w][t] : fmaxf(mx, red[w][bf]);
-        // A in charge units (with a margin for the FP32 convolution, or the
-        // sum bound of a sparse tile); room for the rounding errors of up to
-        // cnt deposits per cell
-        const double bound = sparse ? static_cast<double>(mx) * static_cast<double>(kmax3) * 1.0001
-                                    : static_cast<double>(mx) * ksum3 / static_cast<double>(csc[t]);
-        const double room = 0.99 * 2147483648.0 - 0.5 * static_cast<double>(cnt) - 64.0;
-        const double scl = (mx > 0.f && (sparse || csc[t] > 0.f)) ? fmin(room / bound, 1e30) : 0.0;
-        scale_s[t] = static_cast<float>(scl);
-        inv_s[t] = scl > 0.0 ? static_cast<float>(1.0 / static_cast<double>(static_cast<float>(scl))) : 0.f;
-      }
+      if (first && t < kNumFields) set_scale();
       bank_scan<NT, kPer>(bs);
       __syncthreads();
 #pragma unroll
@@ -1173,6 +1294,8 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       for (int sl = wave; sl < slots; sl += kWaves) {
         const int q = lr * slots + sl;
         if (q >= m) continue;
+        // deposit_one's body, written out: as a call here it costs the other
+        // 6-tap kernels registers
         const uint32_t p = c0 + bs.idx[q];
         const float4 a = rec_pos<kW>(sorted, static_cast<int64_t>(p));
         const float4 v = rec_vel<kW>(sorted, static_cast<int64_t>(p));
@@ -1200,6 +1323,111 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       }
       __syncthreads();
     };
+    if (paired) {
+      __syncthreads();  // cell counts and bound maxima complete
+      if (t < kNumFields) set_scale();
+      // exclusive scan of the 4096 cell counts (4 per thread) into cell starts
+      {
+        const unsigned w0 = ccnt[2 * t], w1 = ccnt[2 * t + 1];
+        const unsigned a0 = w0 & 0xffffu, a1 = w0 >> 16, a2 = w1 & 0xffffu;
+        const unsigned sum = a0 + a1 + a2 + (w1 >> 16);
+        unsigned incl = sum;
+        for (int off = 1; off < 64; off <<= 1) {
+          const unsigned o = __shfl_up(incl, off);
+          if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        unsigned e0 = incl - sum;
+        for (int w = 0; w < wave; ++w) e0 += wsum[w];
+        const unsigned e1 = e0 + a0, e2 = e1 + a1, e3 = e2 + a2;
+        ccnt[2 * t] = e0 | e1 << 16;
+        ccnt[2 * t + 1] = e2 | e3 << 16;
+      }
+      __syncthreads();
+      // The accumulators are zero here and the sort runs in them: the cell
+      // keys of particles kSuper.. (written with the cell sums) in words
+      // 2 VOL.., the cell-sorted particles (local index | cell << 16) in words
+      // 0.., then the job keys in words 2 VOL..; both ranges are cleared again
+      // before the deposits.
+      unsigned* const lkey = reinterpret_cast<unsigned*>(acc) + 2 * VOL;
+      unsigned* const lsorted = reinterpret_cast<unsigned*>(acc);
+      auto place = [&](unsigned key, unsigned i) {
+        const unsigned cell = key & 4095u;
+        const unsigned st = (ccnt[cell >> 1] >> ((cell & 1u) << 4)) & 0xffffu;
+        lsorted[st + (key >> 12)] = i | cell << 16;
+      };
+#pragma unroll
+      for (int r = 0; r < kPer; ++r)
+        if (t + r * NT < m0) place(key0[r], static_cast<unsigned>(t + r * NT));
+      for (uint32_t i = static_cast<uint32_t>(m0) + t; i < cnt; i += NT) place(lkey[i], i);
+      __syncthreads();
+      // jobs of sorted positions 2j, 2j + 1: bucket = (pair ? 0 : 32) + bank
+      // pair of the first particle's tap origin; job keys bucket | slot << 6,
+      // ~0 for no second job
+      const uint32_t n2 = (cnt + 1) / 2;
+      auto bank_of = [&](unsigned cell) {
+        return (((cell >> 8) * E + ((cell >> 4) & 15u)) * E + (cell & 15u)) & 31u;
+      };
+      for (uint32_t j = t; j < n2; j += NT) {
+        const bool has1 = 2 * j + 1 < cnt;
+        const unsigned c0 = lsorted[2 * j] >> 16;
+        const unsigned c1 = has1 ? lsorted[2 * j + 1] >> 16 : 0u;
+        const bool pr = has1 && (c1 == c0 || (c1 == c0 + 1u && (c0 & 15u) != 15u));
+        const unsigned b0 = (pr ? 0u : 32u) + bank_of(c0);
+        lkey[2 * j] = b0 | static_cast<unsigned>(atomicAdd(&bs.cnt[b0], 1)) << 6;
+        unsigned k1 = ~0u;
+        if (has1 && !pr) {
+          const unsigned b1 = 32u + bank_of(c1);
+          k1 = b1 | static_cast<unsigned>(atomicAdd(&bs.cnt[b1], 1)) << 6;
+        }
+        lkey[2 * j + 1] = k1;
+      }
+      __syncthreads();
+      bank_scan<NT, kPer>(bs);
+      __syncthreads();
+      // bank-sorted jobs in the workgroup's scratch: a | b << 16 for a pair,
+      // a for a single
+      uint32_t* const pjob = pjobs;
+      for (uint32_t j = t; j < n2; j += NT) {
+        const unsigned k0 = lkey[2 * j], k1 = lkey[2 * j + 1];
+        const unsigned i0 = lsorted[2 * j] & 0xffffu;
+        const unsigned i1 = 2 * j + 1 < cnt ? lsorted[2 * j + 1] & 0xffffu : 0u;
+        pjob[bs.cnt[k0 & 63u] + (k0 >> 6)] = (k0 & 63u) < 32u ? (i0 | i1 << 16) : i0;
+        if (k1 != ~0u) pjob[bs.cnt[k1 & 63u] + (k1 >> 6)] = i1;
+      }
+      const int n_pair = bs.cnt[32];
+      float sc[kNumFields];
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
+      __syncthreads();
+      for (uint32_t i = t; i < cnt + 1; i += NT) {  // (2j + 1 may be cnt)
+        lsorted[i] = 0u;
+        lkey[i] = 0u;
+      }
+      __syncthreads();
+      // wave slots: pair jobs for fields 0, 1, then for fields 2, 3, then
+      // the single jobs likewise
+      const int n_single = static_cast<int>(cnt) - 2 * n_pair;
+      const int wp = (n_pair + 63) >> 6, ws = (n_single + 63) >> 6;
+      const int lr = ((lane & 31) << 1) | (lane >> 5);
+      for (int sl = wave; sl < 2 * (wp + ws); sl += kWaves) {
+        if (sl < 2 * wp) {
+          const int k = sl >= wp;
+          const int q = lr * wp + sl - k * wp;
+          if (q < n_pair) {
+            const unsigned jd = pjob[q];
+            deposit_two(p0 + (jd & 0xffffu), p0 + (jd >> 16), k, sc);
+          }
+        } else {
+          const int s2 = sl - 2 * wp;
+          const int k = s2 >= ws;
+          const int q = lr * ws + s2 - k * ws;
+          if (q < n_single) deposit_one(p0 + pjob[n_pair + q], k, sc);
+        }
+      }
+      __syncthreads();
+    } else {
     deposit_chunk(p0, m0, key0, true);
     for (uint32_t c0 = p0 + kSuper; c0 < p1; c0 += kSuper) {
       const int m = static_cast<int>(min(static_cast<uint32_t>(kSuper), p1 - c0));
@@ -1217,9 +1445,12 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       }
       deposit_chunk(c0, m, key, false);
     }
+    }  // unpaired
     // take the next tile, then flush this one (clearing it)
     item = next_item<NT, kMulti>(tq, n_items, starts, n_cats, &s_tile);
     if (t < 64) bs.cnt[t] = 0;
+    if constexpr (kPairOK)  // the deposits no longer read the bank-sort index array
+      for (int i = t; i < kCellWords; i += NT) ccnt[i] = 0u;
     float inv[kNumFields];
 #pragma unroll
     for (int f = 0; f < kNumFields; ++f) inv[f] = inv_s[f];
@@ -2364,12 +2595,12 @@ hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int
       // one workgroup per CU (the LDS holds one), never more than the tiles
       const int64_t blocks = p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus;
       scatter_fixed_kernel<16, 1024, NTAP, DEG, kW, false><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
-          one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb);
+          one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb, PairWork{p->pair_scratch, p->pair_blocks});
     } else {
       const int64_t cap = 4 * static_cast<int64_t>(p->num_cus);
       const int64_t blocks = p->n_tiles < cap ? p->n_tiles : cap;
       scatter_fixed_kernel<8, 512, NTAP, DEG, kW, false><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
-          one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb);
+          one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb, PairWork{nullptr, 0});
     }
   } else if (p->tile == 16) {
     TileQueues tq;
@@ -2452,10 +2683,10 @@ hipError_t launch_scatter_impl(Plan* p, const mps_catalog* c, hipStream_t s, int
       const unsigned blocks = static_cast<unsigned>(p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus);
       if (c->weight)
         scatter_fixed_kernel<16, 1024, 6, 3, true, false, true><<<blocks, 1024, 0, s>>>(
-            one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb);
+            one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb, PairWork{p->pair_scratch, p->pair_blocks});
       else
         scatter_fixed_kernel<16, 1024, 6, 3, false, false, true><<<blocks, 1024, 0, s>>>(
-            one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb);
+            one, nullptr, nullptr, 1, p->n_tiles, tq, tp, tb, PairWork{p->pair_scratch, p->pair_blocks});
       halo_fixup_kernel<false><<<static_cast<unsigned>(p->n_tiles), 256, 0, s>>>(one, nullptr, nullptr, 1);
     }
     return hipGetLastError();
@@ -2472,6 +2703,12 @@ hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s) {
 ScatterCat scatter_cat(Plan* p, const mps_catalog* c) {
   return ScatterCat{p->sorted, p->tile_offset, static_cast<float*>(p->grid), key_params(p, c), &p->d_header->d, 0,
                     p->halo};
+}
+
+size_t pair_scratch_bytes(int64_t n_tiles, int num_cus) {
+  int64_t b = n_tiles < num_cus ? n_tiles : num_cus;
+  if (b > kPairBlocks) b = kPairBlocks;
+  return static_cast<size_t>(b) * kPairCap * sizeof(uint32_t);
 }
 
 int scatter_form_for(int n_grid, mps_precision prec, int64_t np) {
@@ -2529,19 +2766,19 @@ hipError_t launch_scatter_multi(const ScatterCat* d_cats, const int64_t* d_start
   if (form == kFormHalo) {
     if (has_w)
       scatter_fixed_kernel<16, 1024, 6, 3, true, true, true><<<blocks, 1024, 0, s>>>(
-          none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
+          none, d_cats, d_starts, n_cats, n_items, tq, tp, tb, PairWork{nullptr, 0});
     else
       scatter_fixed_kernel<16, 1024, 6, 3, false, true, true><<<blocks, 1024, 0, s>>>(
-          none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
+          none, d_cats, d_starts, n_cats, n_items, tq, tp, tb, PairWork{nullptr, 0});
     halo_fixup_kernel<true><<<static_cast<unsigned>(n_items), 256, 0, s>>>(none, d_cats, d_starts, n_cats);
     return hipGetLastError();
   }
   if (has_w)
     scatter_fixed_kernel<16, 1024, 6, 3, true, true><<<blocks, 1024, 0, s>>>(
-        none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
+        none, d_cats, d_starts, n_cats, n_items, tq, tp, tb, PairWork{nullptr, 0});
   else
     scatter_fixed_kernel<16, 1024, 6, 3, false, true><<<blocks, 1024, 0, s>>>(
-        none, d_cats, d_starts, n_cats, n_items, tq, tp, tb);
+        none, d_cats, d_starts, n_cats, n_items, tq, tp, tb, PairWork{nullptr, 0});
   return hipGetLastError();
 }
 

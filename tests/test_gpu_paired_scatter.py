@@ -1,0 +1,103 @@
+"""The FP32 atomic form's paired deposits against the oracle.
+
+A dense 16^3 tile (more than 128 particles) of an FP32 grid in the atomic
+form sorts its particles by cell and deposits the particles at sorted
+positions 2j and 2j + 1 together when they share a cell or sit in
+z-neighbouring cells of one (x, y) column; tiles of more than 16384
+particles deposit unpaired.  The cases reach each branch of that path:
+tiles above and below the 6144 particles whose cell keys stay in registers,
+tiles above the paired path's limit, cells holding hundreds of particles
+(many same-cell pairs, large ranks), lattice-ordered and shuffled records,
+with and without weights.  Each assigned grid is compared with
+oracle.assign (max |error| / max |grid| per field < 2e-6, the FP32
+assignment bound of the other scatter tests; for the clump, against the
+grid of |q| as in the clustered scatter tests)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import catalogs
+
+pytestmark = pytest.mark.gpu
+
+BOX = 1000.0
+GRID_TOL = 2e-6
+
+
+@pytest.fixture(scope="module")
+def mps():
+    import paper_2005_06170_amd as m
+    return m
+
+
+def _dev(*arrays):
+    return [None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays]
+
+
+def _want(pos, vel, w, n):
+    w64 = np.ones(pos.shape[0]) if w is None else w.astype(np.float64)
+    v64 = vel.astype(np.float64)
+    q = np.stack([w64, w64 * v64[:, 0], w64 * v64[:, 1], w64 * v64[:, 2]])
+    return oracle.assign(pos, q, BOX, n)
+
+
+def _err(g, want, scale=None):
+    if scale is None:
+        scale = np.abs(want).max(axis=(1, 2, 3), keepdims=True)
+    return float(np.max(np.abs(g - want) / scale))
+
+
+# (particles per 16^3 tile on a 64^3 grid, weights): below and above the
+# 6144 keys held in registers, and above the 16384-particle pair limit
+@pytest.mark.parametrize("per_tile,weights", [(3_000, False), (7_000, True), (9_500, False), (20_000, True)])
+def test_uniform_tiles(mps, per_tile, weights):
+    n = 64
+    npart = per_tile * (n // 16) ** 3
+    print(f"paired scatter: N={n}, {npart} particles (~{per_tile} per tile), weights={weights}", flush=True)
+    pos, vel, w = catalogs.uniform_gaussian(npart, BOX, 300.0, seed=catalogs.seed_for(5, 900 + per_tile),
+                                            with_weights=True)
+    w = w if weights else None
+    g = mps.Plan(n, "f32").assign(*_dev(pos, vel, w), box=BOX).cpu().numpy().astype(np.float64)
+    err = _err(g, _want(pos, vel, w, n))
+    print(f"  max grid error / max |grid|: {err:.2e}", flush=True)
+    assert err < GRID_TOL, err
+
+
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_lattice_catalog(mps, shuffle):
+    """A Zel'dovich lattice (one particle per cell, 4096 per tile, rms
+    displacement 4 cells) in lattice order, where neighbouring records are
+    z-neighbours, and shuffled."""
+    n = 64
+    pos, vel = catalogs.zeldovich(n, BOX, 4.0 * BOX / n, haf=50.0, seed=catalogs.seed_for(5, 901))
+    if shuffle:
+        perm = np.random.default_rng(catalogs.seed_for(5, 902)).permutation(pos.shape[0])
+        pos, vel = pos[perm], vel[perm]
+    print(f"paired scatter: Zel'dovich 64^3 lattice, shuffled={shuffle}", flush=True)
+    g = mps.Plan(n, "f32").assign(*_dev(pos, vel, None), box=BOX).cpu().numpy().astype(np.float64)
+    err = _err(g, _want(pos, vel, None, n))
+    print(f"  max grid error / max |grid|: {err:.2e}", flush=True)
+    assert err < GRID_TOL, err
+
+
+def test_crowded_cells(mps):
+    """A tight clump (hundreds of particles per cell) on a tile corner at the
+    periodic wrap, over a uniform background: cells with many same-cell
+    pairs and ranks in the hundreds, columns crossing tile faces."""
+    n = 64
+    rng = np.random.default_rng(catalogs.seed_for(5, 903))
+    h = BOX / n
+    clump = rng.normal(loc=[16 * h, 32 * h, 0.0], scale=0.8 * h, size=(12_000, 3))
+    bg = rng.uniform(0.0, BOX, size=(150_000, 3))
+    pos = np.mod(np.concatenate([clump, bg]), BOX).astype(np.float32)
+    vel = rng.normal(0.0, 300.0, size=pos.shape).astype(np.float32)
+    print(f"paired scatter: N={n}, clump of 12000 + 150000 uniform", flush=True)
+    g = mps.Plan(n, "f32").assign(*_dev(pos, vel, None), box=BOX).cpu().numpy().astype(np.float64)
+    want = _want(pos, vel, None, n)
+    v64 = vel.astype(np.float64)
+    q_abs = np.stack([np.ones(len(pos)), np.abs(v64[:, 0]), np.abs(v64[:, 1]), np.abs(v64[:, 2])])
+    scale = np.abs(oracle.assign(pos, q_abs, BOX, n)).max(axis=(1, 2, 3), keepdims=True)
+    err = _err(g, want, scale)
+    print(f"  max grid error / max |q| grid: {err:.2e}", flush=True)
+    assert err < GRID_TOL, err
