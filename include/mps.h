@@ -188,7 +188,10 @@ typedef struct {
  * MPS_SCATTER_GATHER_MAX_MEAN, the owner-computes scatter; else m <=
  * MPS_SCATTER_HALO_MAX_MEAN, the halo scatter (its halo buffer, 5165 x 16
  * bytes per tile, is allocated on first use and counted by mps_footprint);
- * else, and on smaller grids, the atomic scatter. */
+ * else, and on smaller grids, the atomic scatter, whose dense tiles deposit
+ * pairs of particles in one cell or z-neighbouring cells together (its job
+ * scratch, 64 KB per workgroup for up to 256 workgroups, is likewise
+ * allocated on first use and counted by mps_footprint). */
 #define MPS_SCATTER_MIN_GRID 128
 #define MPS_SCATTER_GATHER_MAX_MEAN 384
 #define MPS_SCATTER_HALO_MAX_MEAN 2048
@@ -223,8 +226,9 @@ int mps_plan_destroy(mps_plan* plan);
 
 /* Pre-allocate workspace for catalogs of up to max_particles particles so
  * that later calls allocate nothing: the sorted records and, for MPS_F32
- * plans on which such a catalog can take the halo scatter, the halo buffer
- * (see MPS_SCATTER_GATHER_MAX_MEAN). */
+ * plans on which such a catalog can take the halo or the atomic scatter,
+ * the halo buffer or the paired deposits' job scratch (see
+ * MPS_SCATTER_GATHER_MAX_MEAN). */
 int mps_plan_reserve(mps_plan* plan, int64_t max_particles);
 
 /* Device bytes a plan of this shape holds when used for n_particles. */
