@@ -126,8 +126,9 @@ constexpr int kHaloCells = 21 * 21 * 21 - 16 * 16 * 16;  // halo cells of a 16^3
 // particles in one cell or in z-neighbouring cells of one (x, y) column
 // deposit together over 7 z cells instead of 2 x 6.  Each workgroup keeps
 // its tile's job list in its own slice of global scratch, kPairCap words;
-// tiles of more than kPairCap particles, and workgroups beyond `blocks`,
-// deposit unpaired.
+// tiles of more than kPairCap particles (the sort runs in the accumulator
+// block, 2 x 21^3 words per pair of fields), and workgroups beyond
+// `blocks`, deposit unpaired.
 constexpr int kPairCap = 16384;
 constexpr int kPairBlocks = 256;  // most workgroups a plan's scratch covers
 struct PairWork {

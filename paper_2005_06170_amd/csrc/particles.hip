@@ -1009,6 +1009,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   constexpr int kCellWords = TS * TS * TS / 2;
   static_assert(!kPairOK || kCellWords * 4 <= NT * kPer * 2, "cell counts alias the bank-sort index array");
   static_assert(!kPairOK || kCellWords == 2 * NT, "two count words per thread");
+  static_assert(!kPairOK || kPairCap <= 2 * VOL, "the paired sort's arrays fit the accumulator block");
   unsigned* ccnt = reinterpret_cast<unsigned*>(bs.idx);
   __shared__ unsigned wsum[kWaves];
   __shared__ float red[kWaves][kNumFields];
@@ -1130,6 +1131,9 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     const bool paired = kPairOK && !sparse && pw.base != nullptr && cnt <= static_cast<uint32_t>(kPairCap) &&
                         static_cast<int>(blockIdx.x) < pw.blocks;
     uint32_t* const pjobs = paired ? pw.base + static_cast<int64_t>(blockIdx.x) * kPairCap : nullptr;
+    // paired: the cell keys of particles kSuper.. go to the accumulator
+    // words of fields 2, 3 (2 VOL + i), zero and unused until the deposits
+    unsigned* const words = reinterpret_cast<unsigned*>(acc);
     float qsum[kNumFields] = {0.f, 0.f, 0.f, 0.f};
     unsigned key0[kPer];
 #pragma unroll
@@ -1173,9 +1177,9 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     for (uint32_t p = p0 + static_cast<uint32_t>(m0) + t; p < p1; p += NT) {
       const float4 a = rec_pos<kW>(sorted, static_cast<int64_t>(p));
       const unsigned base = tap_origin<TS, NTAP>(a, kp, ox, oy, oz);
-      add_cell_sums(a, rec_vel<kW>(sorted, static_cast<int64_t>(p)), base + kCellOff);
-      // the cell key in the (free) accumulator words of fields 2, 3
-      if (paired) reinterpret_cast<unsigned*>(acc)[2 * VOL + (p - p0)] = cell_rank(base, ccnt);
+      const float4 v = rec_vel<kW>(sorted, static_cast<int64_t>(p));
+      add_cell_sums(a, v, base + kCellOff);
+      if (paired) words[2 * VOL + (p - p0)] = cell_rank(base, ccnt);
     }
     __syncthreads();
     // the largest cell sum of each bound field (only the tile's own cells
@@ -1345,43 +1349,83 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
         ccnt[2 * t + 1] = e2 | e3 << 16;
       }
       __syncthreads();
-      // The accumulators are zero here and the sort runs in them: the cell
-      // keys of particles kSuper.. (written with the cell sums) in words
-      // 2 VOL.., the cell-sorted particles (local index | cell << 16) in words
-      // 0.., then the job keys in words 2 VOL..; both ranges are cleared again
-      // before the deposits.
-      unsigned* const lkey = reinterpret_cast<unsigned*>(acc) + 2 * VOL;
-      unsigned* const lsorted = reinterpret_cast<unsigned*>(acc);
+      // The accumulators are zero here and the sort runs in them (words of
+      // the u32 view; cnt <= 2 VOL): the cell-sorted entries (local index |
+      // cell << 16) at 0.., the cell keys of particles kSuper.. and then
+      // the job keys at 2 VOL..; both ranges are cleared again before the
+      // deposits.
+      unsigned* const fsorted = words;
       auto place = [&](unsigned key, unsigned i) {
         const unsigned cell = key & 4095u;
-        const unsigned st = (ccnt[cell >> 1] >> ((cell & 1u) << 4)) & 0xffffu;
-        lsorted[st + (key >> 12)] = i | cell << 16;
+        fsorted[((ccnt[cell >> 1] >> ((cell & 1u) << 4)) & 0xffffu) + (key >> 12)] = i | cell << 16;
       };
 #pragma unroll
       for (int r = 0; r < kPer; ++r)
         if (t + r * NT < m0) place(key0[r], static_cast<unsigned>(t + r * NT));
-      for (uint32_t i = static_cast<uint32_t>(m0) + t; i < cnt; i += NT) place(lkey[i], i);
+      for (uint32_t i = static_cast<uint32_t>(m0) + t; i < cnt; i += NT) place(words[2 * VOL + i], i);
       __syncthreads();
-      // jobs of sorted positions 2j, 2j + 1: bucket = (pair ? 0 : 32) + bank
-      // pair of the first particle's tap origin; job keys bucket | slot << 6,
-      // ~0 for no second job
-      const uint32_t n2 = (cnt + 1) / 2;
+      // Jobs: along each run of sorted positions whose neighbours are
+      // linked (cells equal or z-neighbours), positions
+      // pair greedily from the run's start; the others are single jobs.
+      // Each thread walks a contiguous segment of positions, marking the
+      // link of i and i + 1 in bit 28 of position i's entry and finding the
+      // segment's last run start; a block max-scan gives each segment the
+      // run it begins in; a second walk writes each job's bucket ((pair ? 0 :
+      // 32) + bank pair of the first particle's tap origin) at its first
+      // position, ~0 at a pair's second; the slots are claimed in a strided
+      // pass.
+      constexpr unsigned kLink = 1u << 28;
+      unsigned* const jkey = words + 2 * VOL;  // the job keys, by first position
       auto bank_of = [&](unsigned cell) {
         return (((cell >> 8) * E + ((cell >> 4) & 15u)) * E + (cell & 15u)) & 31u;
       };
-      for (uint32_t j = t; j < n2; j += NT) {
-        const bool has1 = 2 * j + 1 < cnt;
-        const unsigned c0 = lsorted[2 * j] >> 16;
-        const unsigned c1 = has1 ? lsorted[2 * j + 1] >> 16 : 0u;
-        const bool pr = has1 && (c1 == c0 || (c1 == c0 + 1u && (c0 & 15u) != 15u));
-        const unsigned b0 = (pr ? 0u : 32u) + bank_of(c0);
-        lkey[2 * j] = b0 | static_cast<unsigned>(atomicAdd(&bs.cnt[b0], 1)) << 6;
-        unsigned k1 = ~0u;
-        if (has1 && !pr) {
-          const unsigned b1 = 32u + bank_of(c1);
-          k1 = b1 | static_cast<unsigned>(atomicAdd(&bs.cnt[b1], 1)) << 6;
+      auto linkable = [&](unsigned e0, unsigned e1) {
+        const unsigned c0 = (e0 >> 16) & 4095u, c1 = (e1 >> 16) & 4095u;
+        return c1 == c0 || (c1 == c0 + 1u && (c0 & 15u) != 15u);
+      };
+      const int per = (static_cast<int>(cnt) + NT - 1) / NT;
+      const int s0 = min(t * per, static_cast<int>(cnt)), s1 = min(s0 + per, static_cast<int>(cnt));
+      // the segment's links (bit 28) and its last run start; whether s0 - 1
+      // links to s0 is kept for the second walk
+      const bool link_in = s0 > 0 && s0 < s1 && linkable(fsorted[s0 - 1], fsorted[s0]);
+      int last = -1;
+      {
+        bool prev = link_in;
+        for (int i = s0; i < s1; ++i) {
+          if (!prev) last = i;
+          const unsigned e0 = fsorted[i];
+          prev = i + 1 < static_cast<int>(cnt) && linkable(e0, fsorted[i + 1]);
+          if (prev) fsorted[i] = e0 | kLink;  // the cell bits that others read are unchanged
         }
-        lkey[2 * j + 1] = k1;
+      }
+      {
+        int incl = last;
+        for (int off = 1; off < 64; off <<= 1) {
+          const int o = __shfl_up(incl, off);
+          if (lane >= off) incl = max(incl, o);
+        }
+        if (lane == 63) wsum[wave] = static_cast<unsigned>(incl + 1);
+        int before = __shfl_up(incl, 1);
+        if (lane == 0) before = -1;
+        __syncthreads();
+        for (int w = 0; w < wave; ++w) before = max(before, static_cast<int>(wsum[w]) - 1);
+        int rs = before;  // run start entering the segment (position 0 starts one)
+        bool prev = link_in;
+        for (int i = s0; i < s1; ++i) {
+          const unsigned e = fsorted[i];
+          if (!prev) rs = i;
+          prev = (e & kLink) != 0u;
+          if (((i - rs) & 1) != 0) {
+            jkey[i] = ~0u;  // second of the pair that starts at i - 1
+          } else {
+            jkey[i] = (prev ? 0u : 32u) + bank_of((e >> 16) & 4095u);
+          }
+        }
+      }
+      __syncthreads();
+      for (int i = t; i < static_cast<int>(cnt); i += NT) {
+        const unsigned b = jkey[i];
+        if (b != ~0u) jkey[i] = b | static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6;
       }
       __syncthreads();
       bank_scan<NT, kPer>(bs);
@@ -1389,21 +1433,21 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       // bank-sorted jobs in the workgroup's scratch: a | b << 16 for a pair,
       // a for a single
       uint32_t* const pjob = pjobs;
-      for (uint32_t j = t; j < n2; j += NT) {
-        const unsigned k0 = lkey[2 * j], k1 = lkey[2 * j + 1];
-        const unsigned i0 = lsorted[2 * j] & 0xffffu;
-        const unsigned i1 = 2 * j + 1 < cnt ? lsorted[2 * j + 1] & 0xffffu : 0u;
-        pjob[bs.cnt[k0 & 63u] + (k0 >> 6)] = (k0 & 63u) < 32u ? (i0 | i1 << 16) : i0;
-        if (k1 != ~0u) pjob[bs.cnt[k1 & 63u] + (k1 >> 6)] = i1;
+      for (int i = t; i < static_cast<int>(cnt); i += NT) {
+        const unsigned k0 = jkey[i];
+        if (k0 == ~0u) continue;
+        const unsigned i0 = fsorted[i] & 0xffffu;
+        const bool pr = (k0 & 63u) < 32u;
+        pjob[bs.cnt[k0 & 63u] + (k0 >> 6)] = pr ? (i0 | (fsorted[i + 1] & 0xffffu) << 16) : i0;
       }
       const int n_pair = bs.cnt[32];
       float sc[kNumFields];
 #pragma unroll
       for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
       __syncthreads();
-      for (uint32_t i = t; i < cnt + 1; i += NT) {  // (2j + 1 may be cnt)
-        lsorted[i] = 0u;
-        lkey[i] = 0u;
+      for (uint32_t i = t; i < cnt; i += NT) {
+        words[i] = 0u;
+        words[2 * VOL + i] = 0u;
       }
       __syncthreads();
       // wave slots: pair jobs for fields 0, 1, then for fields 2, 3, then
@@ -1472,8 +1516,18 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     }
     const int fvol = fdx * fdy * fdz;
     float* hbase = kHalo ? halo + tile * (static_cast<int64_t>(kNumFields) * kHaloCells) : nullptr;
+    const bool whole = fdx == E && fdy == E && fdz == E;  // uniform: constant divisors
     for (int j = t; j < fvol; j += NT) {
-      const int ez = fz0 + j % fdz, ey = fy0 + (j / fdz) % fdy, ex = fx0 + j / (fdy * fdz);
+      int ex, ey, ez;
+      if (whole) {
+        ez = j % E;
+        ey = (j / E) % E;
+        ex = j / (E * E);
+      } else {
+        ez = fz0 + j % fdz;
+        ey = fy0 + (j / fdz) % fdy;
+        ex = fx0 + j / (fdy * fdz);
+      }
       const int i = (ex * E + ey) * E + ez;
       const int gx = (ox + ex - H) & (n - 1);
       const int gy = (oy + ey - H) & (n - 1);

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import guarded_rel
+from gpu_common import RUN_TOL_F32, guarded_rel
 from synth import catalogs
 
 pytestmark = pytest.mark.gpu
@@ -44,7 +44,7 @@ def test_estimate_from_host_memory(mps, prec, pinned):
     plan = mps.Plan(64, prec)
     dev = plan.estimate(*(torch.from_numpy(a).cuda() for a in (pos, vel, w)), box=BOX, haf=HAF, bulk_flow=True)
     host = plan.estimate(*_host(pos, vel, w, pinned=pinned), box=BOX, haf=HAF, bulk_flow=True)
-    _close(host, dev, 1e-12 if prec == "f64" else 1e-6)
+    _close(host, dev, 1e-12 if prec == "f64" else RUN_TOL_F32)
     np.testing.assert_allclose(host["v_bulk"], dev["v_bulk"], rtol=1e-12)
 
 
@@ -84,7 +84,7 @@ def test_server_with_host_catalogs(mps):
             t_dev = srv.submit(dp, dv, box=BOX, haf=HAF, n_grid=grid, precision=prec)
             jobs.append((t_host, t_dev, prec, (hp, hv, dp, dv)))
         for t_host, t_dev, prec, _keep in jobs:
-            _close(srv.wait(t_host, 300.0), srv.wait(t_dev, 300.0), 1e-12 if prec == "f64" else 1e-6)
+            _close(srv.wait(t_host, 300.0), srv.wait(t_dev, 300.0), 1e-12 if prec == "f64" else RUN_TOL_F32)
     finally:
         srv.close()
 

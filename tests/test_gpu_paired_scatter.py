@@ -5,10 +5,10 @@ form sorts its particles by cell and deposits the particles at sorted
 positions 2j and 2j + 1 together when they share a cell or sit in
 z-neighbouring cells of one (x, y) column; tiles of more than 16384
 particles deposit unpaired.  The cases reach each branch of that path:
-tiles above and below the 6144 particles whose cell keys stay in registers,
-tiles above the paired path's limit, cells holding hundreds of particles
-(many same-cell pairs, large ranks), lattice-ordered and shuffled records,
-with and without weights.  Each assigned grid is compared with
+tiles above and below the 6144 particles whose cell keys stay in
+registers, tiles above the paired path's limit, cells holding hundreds of
+particles (many same-cell pairs, large ranks), lattice-ordered and shuffled
+records, with and without weights.  Each assigned grid is compared with
 oracle.assign (max |error| / max |grid| per field < 2e-6, the FP32
 assignment bound of the other scatter tests; for the clump, against the
 grid of |q| as in the clustered scatter tests)."""
@@ -49,8 +49,8 @@ def _err(g, want, scale=None):
 
 
 # (particles per 16^3 tile on a 64^3 grid, weights): below and above the
-# 6144 keys held in registers, and above the 16384-particle pair limit
-@pytest.mark.parametrize("per_tile,weights", [(3_000, False), (7_000, True), (9_500, False), (20_000, True)])
+# 6144 keys held in registers, just under and above the 16384-particle limit
+@pytest.mark.parametrize("per_tile,weights", [(3_000, False), (7_000, True), (16_000, False), (20_000, True)])
 def test_uniform_tiles(mps, per_tile, weights):
     n = 64
     npart = per_tile * (n // 16) ** 3

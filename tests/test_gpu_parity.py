@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from synth import catalogs
-from gpu_common import compare_spectra
+from gpu_common import RUN_TOL_F32, compare_spectra
 
 pytestmark = pytest.mark.gpu
 
@@ -150,6 +150,12 @@ def test_ragged_many_tiles(mps, prec):
     compare_spectra(g, o, TOL[prec], f"ragged {prec}")
 
 
+# Run-to-run agreement of one catalog's spectra: the paired FP32 BL3
+# scatter's, RUN_TOL_F32 (see gpu_common); the other FP32 kernels' differ by
+# the flush's atomic order only.
+_RUN_TOL = {("f32", "bl3"): RUN_TOL_F32, ("f64", "bl3"): 1e-12, ("f32", "bl3_exact"): 1e-6, ("f32", "pqs"): 1e-6}
+
+
 @pytest.mark.parametrize("prec,kernel", [("f32", "bl3"), ("f64", "bl3"), ("f32", "bl3_exact"),
                                          ("f32", "pqs")])
 def test_unit_weights_match_no_weights(mps, prec, kernel):
@@ -165,9 +171,10 @@ def test_unit_weights_match_no_weights(mps, prec, kernel):
     b = plan.estimate(*_dev(pos, vel, w), box=box, haf=haf, n_bins=24, kernel=kernel, bulk_flow=True)
     for key, sn in (("p_pp", a["sn_pp"]), ("p_tt", a["sn_tt"]), ("p_dd", a["sn_dd"]),
                     ("p_dt", np.sqrt(a["sn_dd"] * a["sn_tt"]))):
-        # the two differ only by the order of the flush's atomic additions
+        # the two differ by the order of the flush's atomic additions and,
+        # for the FP32 BL3 scatter's paired deposits, by which particles pair
         e = np.abs(a[key] - b[key]) / (np.abs(b[key]) + np.abs(sn))
-        assert np.nanmax(e) < (1e-12 if prec == "f64" else 1e-6), (key, np.nanmax(e))
+        assert np.nanmax(e) < _RUN_TOL[(prec, kernel)], (key, np.nanmax(e))
     np.testing.assert_allclose(a["v_bulk"], b["v_bulk"], rtol=1e-12)
     o = oracle.estimate(pos, vel, box=box, n_grid=n, haf=haf, n_bins=24, kernel=kernel,
                         flags=oracle.FLAG_BULKFLOW_SUBTRACT)
@@ -178,8 +185,8 @@ def test_unit_weights_match_no_weights(mps, prec, kernel):
 def test_plan_reuse_across_entry_points(mps, prec):
     """A plan keeps its grid, sorted records and tables between calls.  One
     plan driven through the isotropic and (k, mu_b) estimates and the
-    assignment in turn must give each estimate exactly what a fresh plan
-    gives (up to the order of the flush's atomic additions)."""
+    assignment in turn must give each estimate what a fresh plan gives, up
+    to the run-to-run differences of the atomic scatter (_RUN_TOL)."""
     box, n, haf = 1000.0, 32, 50.0
     cats = [catalogs.uniform_gaussian(20_000 + 1000 * i, box, seed=catalogs.seed_for(1, 40 + i)) for i in range(3)]
     cats[2] = catalogs.zeldovich(24, box, 15.0, haf=haf, seed=catalogs.seed_for(1, 43))
@@ -196,7 +203,7 @@ def test_plan_reuse_across_entry_points(mps, prec):
     plan.assign(*_dev(*cats[1]), box=box)
     got.append(plan.estimate(*_dev(*cats[2]), box=box, haf=haf, n_bins=12))
     got.append(plan.estimate(*_dev(*cats[1]), box=box, haf=haf, n_bins=12))
-    tol = 1e-12 if prec == "f64" else 1e-6
+    tol = _RUN_TOL[(prec, "bl3")]
     for g, w in zip(got, [want[0], want[1], want[0], want[2], want[1]]):
         for key, sn in (("p_pp", w["sn_pp"]), ("p_tt", w["sn_tt"]), ("p_dd", w["sn_dd"]),
                         ("p_dt", np.sqrt(w["sn_dd"] * w["sn_tt"]))):

@@ -15,7 +15,7 @@ import torch
 
 import oracle
 from synth import catalogs
-from gpu_common import compare_spectra, guarded_rel
+from gpu_common import RUN_TOL_F32, compare_spectra, guarded_rel
 
 TOL = {"f64": 1e-5, "f32": 3e-4}
 # pool entries small enough for the oracle
@@ -79,7 +79,7 @@ def test_batch_equals_alone(mps, pool_oracle):
     cats = [dict(pos=c["pos"], vel=c["vel"], box=c["box"], haf=c["haf"], n_bins=c["n_bins"]) for c in pool]
     batch = mps.estimate_batch(plans, cats)
     for a, b, c in zip(batch, alone, pool):
-        _same(a, b, 1e-6 if c["prec"] == "f32" else 1e-12)
+        _same(a, b, RUN_TOL_F32 if c["prec"] == "f32" else 1e-12)
     for i in ORACLE_CHECKED:
         compare_spectra(batch[i], want[i], TOL[pool[i]["prec"]], f"batch catalog {i}")
 
@@ -112,7 +112,7 @@ def test_server_mix_equals_alone(mps, pool_oracle):
     for j, t in enumerate(tickets):
         got = srv.wait(t, timeout_s=120.0)
         c = pool[order[j]]
-        _same(got, alone[order[j]], 1e-6 if c["prec"] == "f32" else 1e-12)
+        _same(got, alone[order[j]], RUN_TOL_F32 if c["prec"] == "f32" else 1e-12)
         if order[j] in ORACLE_CHECKED:
             compare_spectra(got, want[order[j]], TOL[c["prec"]], f"served catalog {order[j]}")
     srv.close()
@@ -141,7 +141,7 @@ def test_server_waits_for_the_producing_stream(mps):
             t = srv.submit(dst_p, dst_v, box=500.0, haf=50.0, n_grid=64, n_bins=16, stream=side)
         got = srv.wait(t, timeout_s=120.0)
         torch.cuda.synchronize()
-        _same(got, want, 1e-6)
+        _same(got, want, RUN_TOL_F32)
     srv.close()
 
 
