@@ -131,10 +131,10 @@ int ensure_halo(Plan* p) {
   return dalloc(&p->halo, b) == hipSuccess ? MPS_OK : MPS_E_NOMEM;
 }
 
-// Whether the FP32 scatter of np particles can take paired deposits: 16^3
-// tiles in the atomic form.
+// Whether the scatter of np particles can take paired deposits: 16^3 tiles
+// in the atomic form (FP32 or FP64 grids).
 static bool pairs_reachable(int n, mps_precision prec, int64_t np) {
-  return prec == MPS_F32 && tile_for(n, prec) == 16 && scatter_form_for(n, prec, np) == kFormAtomic;
+  return tile_for(n, prec) == 16 && scatter_form_for(n, prec, np) == kFormAtomic;
 }
 
 int ensure_pair_scratch(Plan* p) {

@@ -887,6 +887,149 @@ __device__ __forceinline__ int halo_index(int ex, int ey, int ez) {
   return B * E * E + TS * B * E + ((ex - H) * TS + ey - H) * B + band(ez);
 }
 
+// The paired deposits' cell sort and job list of one dense tile of cnt
+// particles (cnt <= kPairCap), shared by the FP32 and FP64 atomic scatters:
+// on entry the 16-bit cell counts are in ccnt (the particles' cell | rank
+// keys in key0 for t + r NT < m0, in words[2 E^3 + i] beyond) and the
+// accumulator block, seen as words, is zero; on return the bank-sorted job
+// list (a | b << 16 for a pair, a for a single; pairs first) is in pjob and
+// the block is zero again.  Returns the number of pair jobs.  The bank
+// counters bs.cnt are cleared here (they size the jobs' slots in pjob).
+template <int NT, int kPer, int E>
+__device__ __forceinline__ int pair_jobs(unsigned* words, unsigned* ccnt, unsigned* wsum, BankSort<NT, kPer>& bs,
+                                         const unsigned (&key0)[kPer], int m0, uint32_t cnt,
+                                         uint32_t* __restrict__ pjob) {
+  constexpr int VOL = E * E * E;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  if (t < 64) bs.cnt[t] = 0;  // first read after the barriers below
+  // exclusive scan of the 4096 cell counts (2 CW per thread) into cell starts
+  {
+    constexpr int CW = 2048 / NT;  // count words per thread
+    static_assert(CW * NT == 2048, "the threads cover the 4096 counts");
+    unsigned cw[CW];
+    unsigned sum = 0;
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      cw[c] = ccnt[CW * t + c];
+      sum += (cw[c] & 0xffffu) + (cw[c] >> 16);
+    }
+    unsigned incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    unsigned e = incl - sum;
+    for (int w = 0; w < wave; ++w) e += wsum[w];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      const unsigned lo = e, hi = e + (cw[c] & 0xffffu);
+      e = hi + (cw[c] >> 16);
+      ccnt[CW * t + c] = lo | hi << 16;
+    }
+  }
+  __syncthreads();
+  // The accumulators are zero here and the sort runs in them (words of
+  // the u32 view; cnt <= 2 VOL): the cell-sorted entries (local index |
+  // cell << 16) at 0.., the cell keys of particles kSuper.. and then
+  // the job keys at 2 VOL..; both ranges are cleared again before the
+  // deposits.
+  unsigned* const fsorted = words;
+  auto place = [&](unsigned key, unsigned i) {
+    const unsigned cell = key & 4095u;
+    fsorted[((ccnt[cell >> 1] >> ((cell & 1u) << 4)) & 0xffffu) + (key >> 12)] = i | cell << 16;
+  };
+#pragma unroll
+  for (int r = 0; r < kPer; ++r)
+    if (t + r * NT < m0) place(key0[r], static_cast<unsigned>(t + r * NT));
+  for (uint32_t i = static_cast<uint32_t>(m0) + t; i < cnt; i += NT) place(words[2 * VOL + i], i);
+  __syncthreads();
+  // Jobs: along each run of sorted positions whose neighbours are
+  // linked (cells equal or z-neighbours), positions
+  // pair greedily from the run's start; the others are single jobs.
+  // Each thread walks a contiguous segment of positions, marking the
+  // link of i and i + 1 in bit 28 of position i's entry and finding the
+  // segment's last run start; a block max-scan gives each segment the
+  // run it begins in; a second walk writes each job's bucket ((pair ? 0 :
+  // 32) + bank pair of the first particle's tap origin) at its first
+  // position, ~0 at a pair's second; the slots are claimed in a strided
+  // pass.
+  constexpr unsigned kLink = 1u << 28;
+  unsigned* const jkey = words + 2 * VOL;  // the job keys, by first position
+  auto bank_of = [&](unsigned cell) {
+    return (((cell >> 8) * E + ((cell >> 4) & 15u)) * E + (cell & 15u)) & 31u;
+  };
+  auto linkable = [&](unsigned e0, unsigned e1) {
+    const unsigned c0 = (e0 >> 16) & 4095u, c1 = (e1 >> 16) & 4095u;
+    return c1 == c0 || (c1 == c0 + 1u && (c0 & 15u) != 15u);
+  };
+  const int per = (static_cast<int>(cnt) + NT - 1) / NT;
+  const int s0 = min(t * per, static_cast<int>(cnt)), s1 = min(s0 + per, static_cast<int>(cnt));
+  // the segment's links (bit 28) and its last run start; whether s0 - 1
+  // links to s0 is kept for the second walk
+  const bool link_in = s0 > 0 && s0 < s1 && linkable(fsorted[s0 - 1], fsorted[s0]);
+  int last = -1;
+  {
+    bool prev = link_in;
+    for (int i = s0; i < s1; ++i) {
+      if (!prev) last = i;
+      const unsigned e0 = fsorted[i];
+      prev = i + 1 < static_cast<int>(cnt) && linkable(e0, fsorted[i + 1]);
+      if (prev) fsorted[i] = e0 | kLink;  // the cell bits that others read are unchanged
+    }
+  }
+  {
+    int incl = last;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(incl, off);
+      if (lane >= off) incl = max(incl, o);
+    }
+    if (lane == 63) wsum[wave] = static_cast<unsigned>(incl + 1);
+    int before = __shfl_up(incl, 1);
+    if (lane == 0) before = -1;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) before = max(before, static_cast<int>(wsum[w]) - 1);
+    int rs = before;  // run start entering the segment (position 0 starts one)
+    bool prev = link_in;
+    for (int i = s0; i < s1; ++i) {
+      const unsigned e = fsorted[i];
+      if (!prev) rs = i;
+      prev = (e & kLink) != 0u;
+      if (((i - rs) & 1) != 0) {
+        jkey[i] = ~0u;  // second of the pair that starts at i - 1
+      } else {
+        jkey[i] = (prev ? 0u : 32u) + bank_of((e >> 16) & 4095u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < static_cast<int>(cnt); i += NT) {
+    const unsigned b = jkey[i];
+    if (b != ~0u) jkey[i] = b | static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6;
+  }
+  __syncthreads();
+  bank_scan<NT, kPer>(bs);
+  __syncthreads();
+  // bank-sorted jobs in the workgroup's scratch: a | b << 16 for a pair,
+  // a for a single
+  for (int i = t; i < static_cast<int>(cnt); i += NT) {
+    const unsigned k0 = jkey[i];
+    if (k0 == ~0u) continue;
+    const unsigned i0 = fsorted[i] & 0xffffu;
+    const bool pr = (k0 & 63u) < 32u;
+    pjob[bs.cnt[k0 & 63u] + (k0 >> 6)] = pr ? (i0 | (fsorted[i + 1] & 0xffffu) << 16) : i0;
+  }
+  const int n_pair = bs.cnt[32];
+  __syncthreads();
+  for (uint32_t i = t; i < cnt; i += NT) {
+    words[i] = 0u;
+    words[2 * VOL + i] = 0u;
+  }
+  __syncthreads();
+  return n_pair;
+}
+
 // Work queues of the persistent scatter: 8 (one per XCD, each over a
 // contiguous range of tiles, so that halo lines shared by neighbouring tiles
 // stay in one L2) or 1.  A block takes tiles from its own queue, then from
@@ -1330,126 +1473,11 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     if (paired) {
       __syncthreads();  // cell counts and bound maxima complete
       if (t < kNumFields) set_scale();
-      // exclusive scan of the 4096 cell counts (4 per thread) into cell starts
-      {
-        const unsigned w0 = ccnt[2 * t], w1 = ccnt[2 * t + 1];
-        const unsigned a0 = w0 & 0xffffu, a1 = w0 >> 16, a2 = w1 & 0xffffu;
-        const unsigned sum = a0 + a1 + a2 + (w1 >> 16);
-        unsigned incl = sum;
-        for (int off = 1; off < 64; off <<= 1) {
-          const unsigned o = __shfl_up(incl, off);
-          if (lane >= off) incl += o;
-        }
-        if (lane == 63) wsum[wave] = incl;
-        __syncthreads();
-        unsigned e0 = incl - sum;
-        for (int w = 0; w < wave; ++w) e0 += wsum[w];
-        const unsigned e1 = e0 + a0, e2 = e1 + a1, e3 = e2 + a2;
-        ccnt[2 * t] = e0 | e1 << 16;
-        ccnt[2 * t + 1] = e2 | e3 << 16;
-      }
-      __syncthreads();
-      // The accumulators are zero here and the sort runs in them (words of
-      // the u32 view; cnt <= 2 VOL): the cell-sorted entries (local index |
-      // cell << 16) at 0.., the cell keys of particles kSuper.. and then
-      // the job keys at 2 VOL..; both ranges are cleared again before the
-      // deposits.
-      unsigned* const fsorted = words;
-      auto place = [&](unsigned key, unsigned i) {
-        const unsigned cell = key & 4095u;
-        fsorted[((ccnt[cell >> 1] >> ((cell & 1u) << 4)) & 0xffffu) + (key >> 12)] = i | cell << 16;
-      };
-#pragma unroll
-      for (int r = 0; r < kPer; ++r)
-        if (t + r * NT < m0) place(key0[r], static_cast<unsigned>(t + r * NT));
-      for (uint32_t i = static_cast<uint32_t>(m0) + t; i < cnt; i += NT) place(words[2 * VOL + i], i);
-      __syncthreads();
-      // Jobs: along each run of sorted positions whose neighbours are
-      // linked (cells equal or z-neighbours), positions
-      // pair greedily from the run's start; the others are single jobs.
-      // Each thread walks a contiguous segment of positions, marking the
-      // link of i and i + 1 in bit 28 of position i's entry and finding the
-      // segment's last run start; a block max-scan gives each segment the
-      // run it begins in; a second walk writes each job's bucket ((pair ? 0 :
-      // 32) + bank pair of the first particle's tap origin) at its first
-      // position, ~0 at a pair's second; the slots are claimed in a strided
-      // pass.
-      constexpr unsigned kLink = 1u << 28;
-      unsigned* const jkey = words + 2 * VOL;  // the job keys, by first position
-      auto bank_of = [&](unsigned cell) {
-        return (((cell >> 8) * E + ((cell >> 4) & 15u)) * E + (cell & 15u)) & 31u;
-      };
-      auto linkable = [&](unsigned e0, unsigned e1) {
-        const unsigned c0 = (e0 >> 16) & 4095u, c1 = (e1 >> 16) & 4095u;
-        return c1 == c0 || (c1 == c0 + 1u && (c0 & 15u) != 15u);
-      };
-      const int per = (static_cast<int>(cnt) + NT - 1) / NT;
-      const int s0 = min(t * per, static_cast<int>(cnt)), s1 = min(s0 + per, static_cast<int>(cnt));
-      // the segment's links (bit 28) and its last run start; whether s0 - 1
-      // links to s0 is kept for the second walk
-      const bool link_in = s0 > 0 && s0 < s1 && linkable(fsorted[s0 - 1], fsorted[s0]);
-      int last = -1;
-      {
-        bool prev = link_in;
-        for (int i = s0; i < s1; ++i) {
-          if (!prev) last = i;
-          const unsigned e0 = fsorted[i];
-          prev = i + 1 < static_cast<int>(cnt) && linkable(e0, fsorted[i + 1]);
-          if (prev) fsorted[i] = e0 | kLink;  // the cell bits that others read are unchanged
-        }
-      }
-      {
-        int incl = last;
-        for (int off = 1; off < 64; off <<= 1) {
-          const int o = __shfl_up(incl, off);
-          if (lane >= off) incl = max(incl, o);
-        }
-        if (lane == 63) wsum[wave] = static_cast<unsigned>(incl + 1);
-        int before = __shfl_up(incl, 1);
-        if (lane == 0) before = -1;
-        __syncthreads();
-        for (int w = 0; w < wave; ++w) before = max(before, static_cast<int>(wsum[w]) - 1);
-        int rs = before;  // run start entering the segment (position 0 starts one)
-        bool prev = link_in;
-        for (int i = s0; i < s1; ++i) {
-          const unsigned e = fsorted[i];
-          if (!prev) rs = i;
-          prev = (e & kLink) != 0u;
-          if (((i - rs) & 1) != 0) {
-            jkey[i] = ~0u;  // second of the pair that starts at i - 1
-          } else {
-            jkey[i] = (prev ? 0u : 32u) + bank_of((e >> 16) & 4095u);
-          }
-        }
-      }
-      __syncthreads();
-      for (int i = t; i < static_cast<int>(cnt); i += NT) {
-        const unsigned b = jkey[i];
-        if (b != ~0u) jkey[i] = b | static_cast<unsigned>(atomicAdd(&bs.cnt[b], 1)) << 6;
-      }
-      __syncthreads();
-      bank_scan<NT, kPer>(bs);
-      __syncthreads();
-      // bank-sorted jobs in the workgroup's scratch: a | b << 16 for a pair,
-      // a for a single
+      const int n_pair = pair_jobs<NT, kPer, E>(words, ccnt, wsum, bs, key0, m0, cnt, pjobs);
       uint32_t* const pjob = pjobs;
-      for (int i = t; i < static_cast<int>(cnt); i += NT) {
-        const unsigned k0 = jkey[i];
-        if (k0 == ~0u) continue;
-        const unsigned i0 = fsorted[i] & 0xffffu;
-        const bool pr = (k0 & 63u) < 32u;
-        pjob[bs.cnt[k0 & 63u] + (k0 >> 6)] = pr ? (i0 | (fsorted[i + 1] & 0xffffu) << 16) : i0;
-      }
-      const int n_pair = bs.cnt[32];
       float sc[kNumFields];
 #pragma unroll
       for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
-      __syncthreads();
-      for (uint32_t i = t; i < cnt; i += NT) {
-        words[i] = 0u;
-        words[2 * VOL + i] = 0u;
-      }
-      __syncthreads();
       // wave slots: pair jobs for fields 0, 1, then for fields 2, 3, then
       // the single jobs likewise
       const int n_single = static_cast<int>(cnt) - 2 * n_pair;
@@ -2276,19 +2304,35 @@ __device__ __forceinline__ unsigned long long fixed64(double x) {
 // nearest to it as the bits of x + 1.5 * 2^52 minus those of 1.5 * 2^52.
 // For tiles of up to 4096 particles the unit is 2^-50 of the largest
 // possible deposit, the resolution of the FP64 products themselves.
+//
+// Dense tiles (truncated BL3, scratch in pw) take the FP32 atomic form's
+// paired deposits (see scatter_fixed_kernel): one cell sort and job list per
+// tile serve both passes.  The FP64 pair sum rounds at 2^-53 of the pair,
+// below the fixed-point unit of the largest deposit, so which particles pair
+// moves a cell's integer sum by at most a unit here and there.
 template <int TS, int NT, int NTAP, int DEG, bool kW>
 __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
     const float4* __restrict__ sorted, const uint32_t* __restrict__ offset, double* __restrict__ grid,
-    KeyParams kp, int64_t n_tiles, TileQueues tq, TapPoly tp, TapBound kb, const Derived* dsrc, int bulk) {
+    KeyParams kp, int64_t n_tiles, TileQueues tq, TapPoly tp, TapBound kb, const Derived* dsrc, int bulk,
+    PairWork pw) {
   constexpr int H = kHaloLo<NTAP>;
   constexpr int E = TS + NTAP - 1;
   constexpr int VOL = E * E * E;
-  constexpr int kPer = 6;
+  constexpr int kPer = NT == 512 ? 8 : 6;
   constexpr int kSuper = kPer * NT;
   constexpr int kWaves = NT / 64;
   __shared__ unsigned long long acc[2 * VOL];
   __shared__ BankSort<NT, kPer> bs;
   __shared__ long long s_tile;
+  // 512 threads (256 registers per lane) for the paired path's two
+  // particles' FP64 weights
+  constexpr bool kPairOK = TS == 16 && NT == 512 && NTAP == 6 && DEG == 3;
+  constexpr int kCellWords = TS * TS * TS / 2;
+  static_assert(!kPairOK || kCellWords * 4 <= NT * kPer * 2, "cell counts alias the bank-sort index array");
+  static_assert(!kPairOK || kPairCap <= 2 * VOL, "the paired sort's arrays fit the accumulator block");
+  unsigned* ccnt = reinterpret_cast<unsigned*>(bs.idx);
+  unsigned* const words = reinterpret_cast<unsigned*>(acc);
+  __shared__ unsigned wsum[kWaves];
   double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
   if (bulk) {
     vb0 = dsrc->vb[0];
@@ -2305,6 +2349,8 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
   const int n = kp.n;
   const int64_t n3 = static_cast<int64_t>(n) * n * n;
   for (int i = t; i < 2 * VOL; i += NT) acc[i] = 0ull;
+  if constexpr (kPairOK)
+    for (int i = t; i < kCellWords; i += NT) ccnt[i] = 0u;
   int64_t tile = next_tile<NT>(tq, n_tiles, &s_tile);
   while (tile >= 0) {
     const uint32_t p0 = offset[tile], p1 = offset[tile + 1];
@@ -2316,6 +2362,29 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
     const int ty = static_cast<int>((tile / nt) % nt);
     const int tx = static_cast<int>(tile / (static_cast<int64_t>(nt) * nt));
     const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
+    const uint32_t cnt = p1 - p0;
+    const bool paired = kPairOK && cnt > 128u && pw.base != nullptr && cnt <= static_cast<uint32_t>(kPairCap) &&
+                        static_cast<int>(blockIdx.x) < pw.blocks;
+    uint32_t* const pjob = paired ? pw.base + static_cast<int64_t>(blockIdx.x) * kPairCap : nullptr;
+    int n_pair = 0;
+    if (paired) {  // cell keys (registers, then the accumulator words of the second pair), sort, jobs
+      const int m0 = static_cast<int>(min(static_cast<uint32_t>(kSuper), cnt));
+      unsigned key0[kPer];
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        key0[r] = 0u;
+        if (t + r * NT < m0)
+          key0[r] = cell_rank(tap_origin<TS, NTAP>(rec_pos<kW>(sorted, static_cast<int64_t>(p0 + t + r * NT)), kp,
+                                                   ox, oy, oz),
+                              ccnt);
+      }
+      for (uint32_t i = static_cast<uint32_t>(m0) + t; i < cnt; i += NT)
+        words[2 * VOL + i] = cell_rank(tap_origin<TS, NTAP>(rec_pos<kW>(sorted, static_cast<int64_t>(p0 + i)), kp,
+                                                            ox, oy, oz),
+                                       ccnt);
+      __syncthreads();
+      n_pair = pair_jobs<NT, kPer, E>(words, ccnt, wsum, bs, key0, m0, cnt, pjob);
+    }
     for (int pass = 0; pass < 2; ++pass) {
       // fixed-point scales of this pass's two fields (uniform): one deposit
       // at most 2^50 (the rounding below needs |x| < 2^51), a cell's sum of
@@ -2333,6 +2402,74 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
         scl[k] = dep > 0.0 ? fmin(0x1p50 / dep, 0x1p62 / cell) : 0.0;
         inv[k] = dep > 0.0 ? 1.0 / scl[k] : 0.0;
       }
+      // paired: the job list's wave slots, pairs then singles
+      if (paired) {
+        const int n_single = static_cast<int>(cnt) - 2 * n_pair;
+        const int wp = (n_pair + 63) >> 6, ws = (n_single + 63) >> 6;
+        const int lr = ((lane & 31) << 1) | (lane >> 5);
+        for (int sl = wave; sl < wp + ws; sl += kWaves) {
+          const bool two = sl < wp;
+          const int q = two ? lr * wp + sl : lr * ws + (sl - wp);
+          if (q >= (two ? n_pair : n_single)) continue;
+          const unsigned jd = pjob[two ? q : n_pair + q];
+          const uint32_t pa = p0 + (jd & 0xffffu);
+          const float4 a0 = rec_pos<kW>(sorted, static_cast<int64_t>(pa));
+          const float4 v0 = rec_vel<kW>(sorted, static_cast<int64_t>(pa));
+          double wx0[NTAP], wy0[NTAP], wz0[NTAP];
+          const unsigned base = particle_taps<double, TS, NTAP, DEG>(a0, kp, ox, oy, oz, tp, wx0, wy0, wz0);
+          const DepositQ<double> d0 = charges<double>(a0, v0, bulk, vb0, vb1, vb2);
+          const double qa0 = (pass ? d0.q[2] : d0.q[0]) * scl[0];
+          const double qa1 = (pass ? d0.q[3] : d0.q[1]) * scl[1];
+          unsigned long long* accf[2] = {acc + base, acc + VOL + base};
+          if (two) {
+            const uint32_t pb = p0 + (jd >> 16);
+            const float4 a1 = rec_pos<kW>(sorted, static_cast<int64_t>(pb));
+            const float4 v1 = rec_vel<kW>(sorted, static_cast<int64_t>(pb));
+            double wx1[NTAP], wy1[NTAP], wz1[NTAP];
+            const unsigned base1 = particle_taps<double, TS, NTAP, DEG>(a1, kp, ox, oy, oz, tp, wx1, wy1, wz1);
+            const bool up = base1 != base;  // else one cell
+            double wzb[NTAP + 1];  // the second particle's z weights on the pair's cells
+            wzb[0] = up ? 0.0 : wz1[0];
+#pragma unroll
+            for (int j = 1; j < NTAP; ++j) wzb[j] = up ? wz1[j - 1] : wz1[j];
+            wzb[NTAP] = up ? wz1[NTAP - 1] : 0.0;
+            const DepositQ<double> d1 = charges<double>(a1, v1, bulk, vb0, vb1, vb2);
+            const double qb0 = (pass ? d1.q[2] : d1.q[0]) * scl[0];
+            const double qb1 = (pass ? d1.q[3] : d1.q[1]) * scl[1];
+#pragma unroll
+            for (int jx = 0; jx < NTAP; ++jx) {
+#pragma unroll
+              for (int jy = 0; jy < NTAP; ++jy) {
+                const double wa = wx0[jx] * wy0[jy], wb = wx1[jx] * wy1[jy];
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                  const double ta = wa * (k ? qa1 : qa0), tb = wb * (k ? qb1 : qb0);
+                  unsigned long long* row = accf[k] + (jx * E + jy) * E;
+#pragma unroll
+                  for (int jz = 0; jz < NTAP; ++jz) atomicAdd(row + jz, fixed64(fma(tb, wzb[jz], ta * wz0[jz])));
+                  if (up) atomicAdd(row + NTAP, fixed64(tb * wzb[NTAP]));
+                }
+              }
+            }
+          } else {
+#pragma unroll
+            for (int jx = 0; jx < NTAP; ++jx) {
+#pragma unroll
+              for (int jy = 0; jy < NTAP; ++jy) {
+                const double wa = wx0[jx] * wy0[jy];
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                  const double ta = wa * (k ? qa1 : qa0);
+#pragma unroll
+                  for (int jz = 0; jz < NTAP; ++jz)
+                    atomicAdd(accf[k] + (jx * E + jy) * E + jz, fixed64(ta * wz0[jz]));
+                }
+              }
+            }
+          }
+        }
+        __syncthreads();
+      } else {
       // a tile of one super-chunk keeps its bank order for the second pass
       const bool resort = pass == 0 || p1 - p0 > static_cast<uint32_t>(kSuper);
       for (uint32_t c0 = p0; c0 < p1; c0 += kSuper) {
@@ -2393,6 +2530,7 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
         }
         __syncthreads();
       }
+      }  // unpaired
       // flush this pass's two fields, clearing the block for the next
       for (int i = t; i < VOL; i += NT) {
         const int ez = i % E, ey = (i / E) % E, ex = i / (E * E);
@@ -2409,6 +2547,8 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
       }
       __syncthreads();
     }
+    if constexpr (kPairOK)  // the unpaired path's bank sort wrote over the counts
+      for (int i = t; i < kCellWords; i += NT) ccnt[i] = 0u;
     tile = next_tile<NT>(tq, n_tiles, &s_tile);
   }
 }
@@ -2663,8 +2803,14 @@ hipError_t launch_scatter_taps(Plan* p, const mps_catalog* c, hipStream_t s, int
     tq.per_queue = xcd_chunk > 0 ? xcd_chunk : p->n_tiles;
     clear_kernel<uint32_t><<<1, 64, 0, s>>>(p->tile_queue, 8);
     const int64_t blocks = p->n_tiles < p->num_cus ? p->n_tiles : p->num_cus;
-    scatter_f64_pair_kernel<16, 1024, NTAP, DEG, kW><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
-        p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk);
+    if constexpr (NTAP == 6 && DEG == 3)  // paired deposits: 512 threads
+      scatter_f64_pair_kernel<16, 512, NTAP, DEG, kW><<<static_cast<unsigned>(blocks), 512, 0, s>>>(
+          p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk,
+          PairWork{p->pair_scratch, p->pair_blocks});
+    else
+      scatter_f64_pair_kernel<16, 1024, NTAP, DEG, kW><<<static_cast<unsigned>(blocks), 1024, 0, s>>>(
+          p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, tq, tp, tb, dsrc, bulk,
+          PairWork{nullptr, 0});
   } else {
     scatter_f64_kernel<8, 512, NTAP, DEG, kW><<<static_cast<unsigned>(p->n_tiles), 512, 0, s>>>(
         p->sorted, p->tile_offset, static_cast<double*>(p->grid), kp, p->n_tiles, xcd_chunk, tp, dsrc, bulk);

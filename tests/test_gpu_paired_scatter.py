@@ -8,8 +8,8 @@ particles deposit unpaired.  The cases reach each branch of that path:
 tiles above and below the 6144 particles whose cell keys stay in
 registers, tiles above the paired path's limit, cells holding hundreds of
 particles (many same-cell pairs, large ranks), lattice-ordered and shuffled
-records, with and without weights.  Each assigned grid is compared with
-oracle.assign (max |error| / max |grid| per field < 2e-6, the FP32
+records, with and without weights; FP64 grids (64-bit fixed point) take the same
+pairing.  Each assigned grid is compared with oracle.assign (max |error| / max |grid| per field < 2e-6, the FP32
 assignment bound of the other scatter tests; for the clump, against the
 grid of |q| as in the clustered scatter tests)."""
 import numpy as np
@@ -22,7 +22,7 @@ from synth import catalogs
 pytestmark = pytest.mark.gpu
 
 BOX = 1000.0
-GRID_TOL = 2e-6
+GRID_TOL = {"f32": 2e-6, "f64": 1e-12}
 
 
 @pytest.fixture(scope="module")
@@ -48,24 +48,28 @@ def _err(g, want, scale=None):
     return float(np.max(np.abs(g - want) / scale))
 
 
-# (particles per 16^3 tile on a 64^3 grid, weights): below and above the
-# 6144 keys held in registers, just under and above the 16384-particle limit
-@pytest.mark.parametrize("per_tile,weights", [(3_000, False), (7_000, True), (16_000, False), (20_000, True)])
-def test_uniform_tiles(mps, per_tile, weights):
+# (particles per 16^3 tile on a 64^3 grid, weights, precision): below and
+# above the 6144 (FP32) or 4096 (FP64) keys held in registers, just under
+# and above the 16384-particle limit
+@pytest.mark.parametrize("per_tile,weights,prec", [(3_000, False, "f32"), (7_000, True, "f32"),
+                                                   (16_000, False, "f32"), (20_000, True, "f32"),
+                                                   (3_000, True, "f64"), (5_000, False, "f64"),
+                                                   (16_000, True, "f64"), (20_000, False, "f64")])
+def test_uniform_tiles(mps, per_tile, weights, prec):
     n = 64
     npart = per_tile * (n // 16) ** 3
-    print(f"paired scatter: N={n}, {npart} particles (~{per_tile} per tile), weights={weights}", flush=True)
+    print(f"paired scatter: N={n} {prec}, {npart} particles (~{per_tile} per tile), weights={weights}", flush=True)
     pos, vel, w = catalogs.uniform_gaussian(npart, BOX, 300.0, seed=catalogs.seed_for(5, 900 + per_tile),
                                             with_weights=True)
     w = w if weights else None
-    g = mps.Plan(n, "f32").assign(*_dev(pos, vel, w), box=BOX).cpu().numpy().astype(np.float64)
+    g = mps.Plan(n, prec).assign(*_dev(pos, vel, w), box=BOX).cpu().numpy().astype(np.float64)
     err = _err(g, _want(pos, vel, w, n))
     print(f"  max grid error / max |grid|: {err:.2e}", flush=True)
-    assert err < GRID_TOL, err
+    assert err < GRID_TOL[prec], err
 
 
-@pytest.mark.parametrize("shuffle", [False, True])
-def test_lattice_catalog(mps, shuffle):
+@pytest.mark.parametrize("shuffle,prec", [(False, "f32"), (True, "f32"), (False, "f64")])
+def test_lattice_catalog(mps, shuffle, prec):
     """A Zel'dovich lattice (one particle per cell, 4096 per tile, rms
     displacement 4 cells) in lattice order, where neighbouring records are
     z-neighbours, and shuffled."""
@@ -74,14 +78,15 @@ def test_lattice_catalog(mps, shuffle):
     if shuffle:
         perm = np.random.default_rng(catalogs.seed_for(5, 902)).permutation(pos.shape[0])
         pos, vel = pos[perm], vel[perm]
-    print(f"paired scatter: Zel'dovich 64^3 lattice, shuffled={shuffle}", flush=True)
-    g = mps.Plan(n, "f32").assign(*_dev(pos, vel, None), box=BOX).cpu().numpy().astype(np.float64)
+    print(f"paired scatter: Zel'dovich 64^3 lattice {prec}, shuffled={shuffle}", flush=True)
+    g = mps.Plan(n, prec).assign(*_dev(pos, vel, None), box=BOX).cpu().numpy().astype(np.float64)
     err = _err(g, _want(pos, vel, None, n))
     print(f"  max grid error / max |grid|: {err:.2e}", flush=True)
-    assert err < GRID_TOL, err
+    assert err < GRID_TOL[prec], err
 
 
-def test_crowded_cells(mps):
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_crowded_cells(mps, prec):
     """A tight clump (hundreds of particles per cell) on a tile corner at the
     periodic wrap, over a uniform background: cells with many same-cell
     pairs and ranks in the hundreds, columns crossing tile faces."""
@@ -92,12 +97,12 @@ def test_crowded_cells(mps):
     bg = rng.uniform(0.0, BOX, size=(150_000, 3))
     pos = np.mod(np.concatenate([clump, bg]), BOX).astype(np.float32)
     vel = rng.normal(0.0, 300.0, size=pos.shape).astype(np.float32)
-    print(f"paired scatter: N={n}, clump of 12000 + 150000 uniform", flush=True)
-    g = mps.Plan(n, "f32").assign(*_dev(pos, vel, None), box=BOX).cpu().numpy().astype(np.float64)
+    print(f"paired scatter: N={n} {prec}, clump of 12000 + 150000 uniform", flush=True)
+    g = mps.Plan(n, prec).assign(*_dev(pos, vel, None), box=BOX).cpu().numpy().astype(np.float64)
     want = _want(pos, vel, None, n)
     v64 = vel.astype(np.float64)
     q_abs = np.stack([np.ones(len(pos)), np.abs(v64[:, 0]), np.abs(v64[:, 1]), np.abs(v64[:, 2])])
     scale = np.abs(oracle.assign(pos, q_abs, BOX, n)).max(axis=(1, 2, 3), keepdims=True)
     err = _err(g, want, scale)
     print(f"  max grid error / max |q| grid: {err:.2e}", flush=True)
-    assert err < GRID_TOL, err
+    assert err < GRID_TOL[prec], err
