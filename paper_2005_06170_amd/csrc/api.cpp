@@ -133,7 +133,7 @@ int ensure_halo(Plan* p) {
 
 // Whether the scatter of np particles can take paired deposits: 16^3 tiles
 // in the atomic form (FP32 or FP64 grids).
-static bool pairs_reachable(int n, mps_precision prec, int64_t np) {
+bool pairs_reachable(int n, mps_precision prec, int64_t np) {
   return tile_for(n, prec) == 16 && scatter_form_for(n, prec, np) == kFormAtomic;
 }
 

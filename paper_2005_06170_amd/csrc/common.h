@@ -317,6 +317,9 @@ size_t halo_bytes(int n_grid, mps_precision prec);
 int ensure_scatter_space(Plan* p, const mps_catalog* c);
 int ensure_halo(Plan* p);
 int ensure_pair_scratch(Plan* p);
+// Whether a catalog of np particles on this grid can take paired deposits
+// (its plan then needs the job scratch).
+bool pairs_reachable(int n, mps_precision prec, int64_t np);
 // The multi-catalog scatter: one launch over the tiles of several catalogs
 // of one group (d_cats, d_starts: device arrays of n_cats descriptors and
 // n_cats + 1 tile prefix sums; d_queue: 8 counters), followed for the halo

@@ -1155,6 +1155,7 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
   static_assert(!kPairOK || kPairCap <= 2 * VOL, "the paired sort's arrays fit the accumulator block");
   unsigned* ccnt = reinterpret_cast<unsigned*>(bs.idx);
   __shared__ unsigned wsum[kWaves];
+  __shared__ int s_slot;  // paired deposits: the next wave slot to claim
   __shared__ float red[kWaves][kNumFields];
   __shared__ float scale_s[kNumFields], inv_s[kNumFields];
   __shared__ long long s_tile;
@@ -1478,12 +1479,16 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       float sc[kNumFields];
 #pragma unroll
       for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
+      if (t == 0) s_slot = kWaves;
+      __syncthreads();
       // wave slots: pair jobs for fields 0, 1, then for fields 2, 3, then
       // the single jobs likewise
       const int n_single = static_cast<int>(cnt) - 2 * n_pair;
       const int wp = (n_pair + 63) >> 6, ws = (n_single + 63) >> 6;
       const int lr = ((lane & 31) << 1) | (lane >> 5);
-      for (int sl = wave; sl < 2 * (wp + ws); sl += kWaves) {
+      // each wave claims its next slot when it is done with one, so that
+      // the waves leave the loop together however the LDS unit serves them
+      for (int sl = wave; sl < 2 * (wp + ws);) {
         if (sl < 2 * wp) {
           const int k = sl >= wp;
           const int q = lr * wp + sl - k * wp;
@@ -1497,6 +1502,9 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
           const int q = lr * ws + s2 - k * ws;
           if (q < n_single) deposit_one(p0 + pjob[n_pair + q], k, sc);
         }
+        int next = 0;
+        if (lane == 0) next = atomicAdd(&s_slot, 1);
+        sl = __shfl(next, 0);
       }
       __syncthreads();
     } else {
@@ -2333,6 +2341,7 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
   unsigned* ccnt = reinterpret_cast<unsigned*>(bs.idx);
   unsigned* const words = reinterpret_cast<unsigned*>(acc);
   __shared__ unsigned wsum[kWaves];
+  __shared__ int s_slot;  // paired deposits: the next wave slot to claim
   double vb0 = 0.0, vb1 = 0.0, vb2 = 0.0;
   if (bulk) {
     vb0 = dsrc->vb[0];
@@ -2407,66 +2416,73 @@ __global__ __launch_bounds__(NT) void scatter_f64_pair_kernel(
         const int n_single = static_cast<int>(cnt) - 2 * n_pair;
         const int wp = (n_pair + 63) >> 6, ws = (n_single + 63) >> 6;
         const int lr = ((lane & 31) << 1) | (lane >> 5);
-        for (int sl = wave; sl < wp + ws; sl += kWaves) {
+        if (t == 0) s_slot = kWaves;
+        __syncthreads();
+        // each wave claims its next slot when it is done with one
+        for (int sl = wave; sl < wp + ws;) {
           const bool two = sl < wp;
           const int q = two ? lr * wp + sl : lr * ws + (sl - wp);
-          if (q >= (two ? n_pair : n_single)) continue;
-          const unsigned jd = pjob[two ? q : n_pair + q];
-          const uint32_t pa = p0 + (jd & 0xffffu);
-          const float4 a0 = rec_pos<kW>(sorted, static_cast<int64_t>(pa));
-          const float4 v0 = rec_vel<kW>(sorted, static_cast<int64_t>(pa));
-          double wx0[NTAP], wy0[NTAP], wz0[NTAP];
-          const unsigned base = particle_taps<double, TS, NTAP, DEG>(a0, kp, ox, oy, oz, tp, wx0, wy0, wz0);
-          const DepositQ<double> d0 = charges<double>(a0, v0, bulk, vb0, vb1, vb2);
-          const double qa0 = (pass ? d0.q[2] : d0.q[0]) * scl[0];
-          const double qa1 = (pass ? d0.q[3] : d0.q[1]) * scl[1];
-          unsigned long long* accf[2] = {acc + base, acc + VOL + base};
-          if (two) {
-            const uint32_t pb = p0 + (jd >> 16);
-            const float4 a1 = rec_pos<kW>(sorted, static_cast<int64_t>(pb));
-            const float4 v1 = rec_vel<kW>(sorted, static_cast<int64_t>(pb));
-            double wx1[NTAP], wy1[NTAP], wz1[NTAP];
-            const unsigned base1 = particle_taps<double, TS, NTAP, DEG>(a1, kp, ox, oy, oz, tp, wx1, wy1, wz1);
-            const bool up = base1 != base;  // else one cell
-            double wzb[NTAP + 1];  // the second particle's z weights on the pair's cells
-            wzb[0] = up ? 0.0 : wz1[0];
+          if (q < (two ? n_pair : n_single)) {
+            const unsigned jd = pjob[two ? q : n_pair + q];
+            const uint32_t pa = p0 + (jd & 0xffffu);
+            const float4 a0 = rec_pos<kW>(sorted, static_cast<int64_t>(pa));
+            const float4 v0 = rec_vel<kW>(sorted, static_cast<int64_t>(pa));
+            double wx0[NTAP], wy0[NTAP], wz0[NTAP];
+            const unsigned base = particle_taps<double, TS, NTAP, DEG>(a0, kp, ox, oy, oz, tp, wx0, wy0, wz0);
+            const DepositQ<double> d0 = charges<double>(a0, v0, bulk, vb0, vb1, vb2);
+            const double qa0 = (pass ? d0.q[2] : d0.q[0]) * scl[0];
+            const double qa1 = (pass ? d0.q[3] : d0.q[1]) * scl[1];
+            unsigned long long* accf[2] = {acc + base, acc + VOL + base};
+            if (two) {
+              const uint32_t pb = p0 + (jd >> 16);
+              const float4 a1 = rec_pos<kW>(sorted, static_cast<int64_t>(pb));
+              const float4 v1 = rec_vel<kW>(sorted, static_cast<int64_t>(pb));
+              double wx1[NTAP], wy1[NTAP], wz1[NTAP];
+              const unsigned base1 = particle_taps<double, TS, NTAP, DEG>(a1, kp, ox, oy, oz, tp, wx1, wy1, wz1);
+              const bool up = base1 != base;  // else one cell
+              double wzb[NTAP + 1];  // the second particle's z weights on the pair's cells
+              wzb[0] = up ? 0.0 : wz1[0];
 #pragma unroll
-            for (int j = 1; j < NTAP; ++j) wzb[j] = up ? wz1[j - 1] : wz1[j];
-            wzb[NTAP] = up ? wz1[NTAP - 1] : 0.0;
-            const DepositQ<double> d1 = charges<double>(a1, v1, bulk, vb0, vb1, vb2);
-            const double qb0 = (pass ? d1.q[2] : d1.q[0]) * scl[0];
-            const double qb1 = (pass ? d1.q[3] : d1.q[1]) * scl[1];
+              for (int j = 1; j < NTAP; ++j) wzb[j] = up ? wz1[j - 1] : wz1[j];
+              wzb[NTAP] = up ? wz1[NTAP - 1] : 0.0;
+              const DepositQ<double> d1 = charges<double>(a1, v1, bulk, vb0, vb1, vb2);
+              const double qb0 = (pass ? d1.q[2] : d1.q[0]) * scl[0];
+              const double qb1 = (pass ? d1.q[3] : d1.q[1]) * scl[1];
 #pragma unroll
-            for (int jx = 0; jx < NTAP; ++jx) {
+              for (int jx = 0; jx < NTAP; ++jx) {
 #pragma unroll
-              for (int jy = 0; jy < NTAP; ++jy) {
-                const double wa = wx0[jx] * wy0[jy], wb = wx1[jx] * wy1[jy];
+                for (int jy = 0; jy < NTAP; ++jy) {
+                  const double wa = wx0[jx] * wy0[jy], wb = wx1[jx] * wy1[jy];
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                  const double ta = wa * (k ? qa1 : qa0), tb = wb * (k ? qb1 : qb0);
-                  unsigned long long* row = accf[k] + (jx * E + jy) * E;
+                  for (int k = 0; k < 2; ++k) {
+                    const double ta = wa * (k ? qa1 : qa0), tb = wb * (k ? qb1 : qb0);
+                    unsigned long long* row = accf[k] + (jx * E + jy) * E;
 #pragma unroll
-                  for (int jz = 0; jz < NTAP; ++jz) atomicAdd(row + jz, fixed64(fma(tb, wzb[jz], ta * wz0[jz])));
-                  if (up) atomicAdd(row + NTAP, fixed64(tb * wzb[NTAP]));
+                    for (int jz = 0; jz < NTAP; ++jz) atomicAdd(row + jz, fixed64(fma(tb, wzb[jz], ta * wz0[jz])));
+                    if (up) atomicAdd(row + NTAP, fixed64(tb * wzb[NTAP]));
+                  }
                 }
               }
-            }
-          } else {
+            } else {
 #pragma unroll
-            for (int jx = 0; jx < NTAP; ++jx) {
+              for (int jx = 0; jx < NTAP; ++jx) {
 #pragma unroll
-              for (int jy = 0; jy < NTAP; ++jy) {
-                const double wa = wx0[jx] * wy0[jy];
+                for (int jy = 0; jy < NTAP; ++jy) {
+                  const double wa = wx0[jx] * wy0[jy];
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                  const double ta = wa * (k ? qa1 : qa0);
+                  for (int k = 0; k < 2; ++k) {
+                    const double ta = wa * (k ? qa1 : qa0);
 #pragma unroll
-                  for (int jz = 0; jz < NTAP; ++jz)
-                    atomicAdd(accf[k] + (jx * E + jy) * E + jz, fixed64(ta * wz0[jz]));
+                    for (int jz = 0; jz < NTAP; ++jz)
+                      atomicAdd(accf[k] + (jx * E + jy) * E + jz, fixed64(ta * wz0[jz]));
+                  }
                 }
               }
             }
           }
+          int next = 0;
+          if (lane == 0) next = atomicAdd(&s_slot, 1);
+          sl = __shfl(next, 0);
         }
         __syncthreads();
       } else {

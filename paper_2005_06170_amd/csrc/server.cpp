@@ -217,6 +217,10 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
     if (st == MPS_OK && adm->cap > 0) st = ensure_particles(reinterpret_cast<Plan*>(created), adm->cap);
     if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(created), adm->host_cap);
     if (st == MPS_OK && adm->halo) st = ensure_halo(reinterpret_cast<Plan*>(created));
+    // the paired deposits' job scratch (counted by the footprint), here
+    // rather than in the worker's first estimate
+    if (st == MPS_OK && pairs_reachable(pp->n_grid, pp->prec, adm->cap))
+      st = ensure_pair_scratch(reinterpret_cast<Plan*>(created));
     if (st != MPS_OK && created) {
       mps_plan_destroy(created);
       created = nullptr;
@@ -225,6 +229,8 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
     if (adm->cap > 0) st = ensure_particles(reinterpret_cast<Plan*>(pp->plan), adm->cap);
     if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(pp->plan), adm->host_cap);
     if (st == MPS_OK && adm->halo) st = ensure_halo(reinterpret_cast<Plan*>(pp->plan));
+    if (st == MPS_OK && pairs_reachable(pp->n_grid, pp->prec, adm->cap))
+      st = ensure_pair_scratch(reinterpret_cast<Plan*>(pp->plan));
   }
   lk.lock();
   s->used -= freed;
