@@ -1361,31 +1361,34 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       scale_s[t] = static_cast<float>(scl);
       inv_s[t] = scl > 0.0 ? static_cast<float>(1.0 / static_cast<double>(static_cast<float>(scl))) : 0.f;
     };
-    // Paired path, one field pair k (fields 2k, 2k + 1) per call, so that a
-    // tile's jobs fill twice as many wave slots.  One particle (record p):
-    auto deposit_one = [&](uint32_t p, int k, const float (&sc)[kNumFields]) {
+    // Paired path, one particle (record p):
+    auto deposit_one = [&](uint32_t p, const float (&sc)[kNumFields]) {
       const float4 a = rec_pos<kW>(sorted, static_cast<int64_t>(p));
       const float4 v = rec_vel<kW>(sorted, static_cast<int64_t>(p));
       float wx[NTAP], wy[NTAP], wz[NTAP];
       const unsigned base = particle_taps<float, TS, NTAP, DEG>(a, kp, ox, oy, oz, tp, wx, wy, wz);
       const DepositQ<float> d = charges<float>(a, v, bulk, vb0, vb1, vb2);
-      const float qlo = k ? d.q[2] * sc[2] : d.q[0] * sc[0];
-      const float qhi = k ? d.q[3] * sc[3] : d.q[1] * sc[1];
-      unsigned long long* const accp = acc2 + k * VOL + base;
+      float qs[kNumFields];
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) qs[f] = d.q[f] * sc[f];
 #pragma unroll
       for (int jx = 0; jx < NTAP; ++jx) {
 #pragma unroll
         for (int jy = 0; jy < NTAP; ++jy) {
           const float wxy = wx[jx] * wy[jy];
-          const float wlo = wxy * qlo, whi = wxy * qhi;
 #pragma unroll
-          for (int jz = 0; jz < NTAP; ++jz) atomicAdd(accp + (jx * E + jy) * E + jz, deposit_pair(wlo, whi, wz[jz]));
+          for (int k = 0; k < 2; ++k) {
+            const float wlo = wxy * qs[2 * k], whi = wxy * qs[2 * k + 1];
+            unsigned long long* row = acc2 + k * VOL + base + (jx * E + jy) * E;
+#pragma unroll
+            for (int jz = 0; jz < NTAP; ++jz) atomicAdd(row + jz, deposit_pair(wlo, whi, wz[jz]));
+          }
         }
       }
     };
     // Two particles (records pa, pb; pb's cell is pa's or the one above it
     // along z) over the NTAP + 1 z cells from pa's tap origin.
-    auto deposit_two = [&](uint32_t pa, uint32_t pb, int k, const float (&sc)[kNumFields]) {
+    auto deposit_two = [&](uint32_t pa, uint32_t pb, const float (&sc)[kNumFields]) {
       const float4 a0 = rec_pos<kW>(sorted, static_cast<int64_t>(pa));
       const float4 v0 = rec_vel<kW>(sorted, static_cast<int64_t>(pa));
       const float4 a1 = rec_pos<kW>(sorted, static_cast<int64_t>(pb));
@@ -1401,22 +1404,27 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       wzb[NTAP] = up ? wz1[NTAP - 1] : 0.f;
       const DepositQ<float> d0 = charges<float>(a0, v0, bulk, vb0, vb1, vb2);
       const DepositQ<float> d1 = charges<float>(a1, v1, bulk, vb0, vb1, vb2);
-      const float qalo = k ? d0.q[2] * sc[2] : d0.q[0] * sc[0];
-      const float qahi = k ? d0.q[3] * sc[3] : d0.q[1] * sc[1];
-      const float qblo = k ? d1.q[2] * sc[2] : d1.q[0] * sc[0];
-      const float qbhi = k ? d1.q[3] * sc[3] : d1.q[1] * sc[1];
-      unsigned long long* const accp = acc2 + k * VOL + base;
+      float qa[kNumFields], qb[kNumFields];
+#pragma unroll
+      for (int f = 0; f < kNumFields; ++f) {
+        qa[f] = d0.q[f] * sc[f];
+        qb[f] = d1.q[f] * sc[f];
+      }
 #pragma unroll
       for (int jx = 0; jx < NTAP; ++jx) {
 #pragma unroll
         for (int jy = 0; jy < NTAP; ++jy) {
           const float wxa = wx0[jx] * wy0[jy], wxb = wx1[jx] * wy1[jy];
-          const float alo = wxa * qalo, ahi = wxa * qahi;
-          const float blo = wxb * qblo, bhi = wxb * qbhi;
-          unsigned long long* row = accp + (jx * E + jy) * E;
 #pragma unroll
-          for (int jz = 0; jz < NTAP; ++jz) atomicAdd(row + jz, deposit_pair2(alo, ahi, wz0[jz], blo, bhi, wzb[jz]));
-          if (up) atomicAdd(row + NTAP, deposit_pair(blo, bhi, wzb[NTAP]));
+          for (int k = 0; k < 2; ++k) {
+            const float alo = wxa * qa[2 * k], ahi = wxa * qa[2 * k + 1];
+            const float blo = wxb * qb[2 * k], bhi = wxb * qb[2 * k + 1];
+            unsigned long long* row = acc2 + k * VOL + base + (jx * E + jy) * E;
+#pragma unroll
+            for (int jz = 0; jz < NTAP; ++jz)
+              atomicAdd(row + jz, deposit_pair2(alo, ahi, wz0[jz], blo, bhi, wzb[jz]));
+            if (up) atomicAdd(row + NTAP, deposit_pair(blo, bhi, wzb[NTAP]));
+          }
         }
       }
     };
@@ -1481,26 +1489,22 @@ __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
       for (int f = 0; f < kNumFields; ++f) sc[f] = scale_s[f];
       if (t == 0) s_slot = kWaves;
       __syncthreads();
-      // wave slots: pair jobs for fields 0, 1, then for fields 2, 3, then
-      // the single jobs likewise
+      // wave slots: the pair jobs, then the single jobs
       const int n_single = static_cast<int>(cnt) - 2 * n_pair;
       const int wp = (n_pair + 63) >> 6, ws = (n_single + 63) >> 6;
       const int lr = ((lane & 31) << 1) | (lane >> 5);
       // each wave claims its next slot when it is done with one, so that
       // the waves leave the loop together however the LDS unit serves them
-      for (int sl = wave; sl < 2 * (wp + ws);) {
-        if (sl < 2 * wp) {
-          const int k = sl >= wp;
-          const int q = lr * wp + sl - k * wp;
+      for (int sl = wave; sl < wp + ws;) {
+        if (sl < wp) {
+          const int q = lr * wp + sl;
           if (q < n_pair) {
             const unsigned jd = pjob[q];
-            deposit_two(p0 + (jd & 0xffffu), p0 + (jd >> 16), k, sc);
+            deposit_two(p0 + (jd & 0xffffu), p0 + (jd >> 16), sc);
           }
         } else {
-          const int s2 = sl - 2 * wp;
-          const int k = s2 >= ws;
-          const int q = lr * ws + s2 - k * ws;
-          if (q < n_single) deposit_one(p0 + pjob[n_pair + q], k, sc);
+          const int q = lr * ws + (sl - wp);
+          if (q < n_single) deposit_one(p0 + pjob[n_pair + q], sc);
         }
         int next = 0;
         if (lane == 0) next = atomicAdd(&s_slot, 1);
