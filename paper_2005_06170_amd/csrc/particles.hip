@@ -945,16 +945,15 @@ __device__ __forceinline__ int pair_jobs(unsigned* words, unsigned* ccnt, unsign
     if (t + r * NT < m0) place(key0[r], static_cast<unsigned>(t + r * NT));
   for (uint32_t i = static_cast<uint32_t>(m0) + t; i < cnt; i += NT) place(words[2 * VOL + i], i);
   __syncthreads();
-  // Jobs: along each run of sorted positions whose neighbours are
-  // linked (cells equal or z-neighbours), positions
-  // pair greedily from the run's start; the others are single jobs.
-  // Each thread walks a contiguous segment of positions, marking the
-  // link of i and i + 1 in bit 28 of position i's entry and finding the
-  // segment's last run start; a block max-scan gives each segment the
-  // run it begins in; a second walk writes each job's bucket ((pair ? 0 :
-  // 32) + bank pair of the first particle's tap origin) at its first
-  // position, ~0 at a pair's second; the slots are claimed in a strided
-  // pass.
+  // Jobs: along each run of sorted positions whose neighbours are linked
+  // (cells equal or z-neighbours), positions pair greedily from the run's
+  // start; the others are single jobs.  Each thread walks a contiguous
+  // segment of positions, marking the link of i and i + 1 in bit 28 of
+  // position i's entry and finding the segment's last run start; a block
+  // max-scan gives each segment the run it begins in; a second walk writes
+  // each job's bucket ((pair ? 0 : 32) + bank pair of the first particle's
+  // tap origin) at its first position, ~0 at a pair's second; the slots
+  // are claimed in a strided pass.
   constexpr unsigned kLink = 1u << 28;
   unsigned* const jkey = words + 2 * VOL;  // the job keys, by first position
   auto bank_of = [&](unsigned cell) {
@@ -1122,15 +1121,17 @@ __device__ __forceinline__ int64_t next_item(const TileQueues& tq, int64_t n_ite
 // the GPU; otherwise the one catalog `one`.
 //
 // Paired deposits (atomic form, 16^3 tiles, truncated BL3, one catalog,
-// scratch in pw):
-// a dense tile's particles are counting-sorted by cell (16-bit counters in
-// LDS, the sorted order in the workgroup's global scratch); sorted positions
-// 2j and 2j + 1 form one job when their cells are equal or z-neighbours of
-// one (x, y) column, else two.  A pair job deposits both particles over the 7 z cells
-// they span with 7 atomics per (x, y) tap and field pair instead of 12, at
-// about the same VALU cost per particle; LDS atomics and VALU issue bound
-// the unpaired deposits about equally.  Jobs are bank-sorted like particles,
-// pairs and singles in separate wave slots.
+// scratch in pw): a dense tile's particles are counting-sorted by cell in
+// LDS (pair_jobs), and along each run of sorted particles whose cells are
+// equal or z-neighbours of one (x, y) column they pair greedily.  A pair
+// deposits both particles over the 7 z cells they span with 7 atomics per
+// (x, y) tap and field pair instead of 12, and fewer VALU operations than
+// the two alone (the two products are summed in FP32, then rounded and
+// packed once).  Jobs are bank-sorted like particles, pairs and singles in
+// wave slots of their own, which the waves claim one at a time; the job
+// list is the only thing in the workgroup's global scratch.  Which
+// particles pair follows the order of the counters' LDS atomics, so the
+// FP32 roundings (not the accuracy) of a grid vary from run to run.
 template <int TS, int NT, int NTAP, int DEG, bool kW, bool kMulti, bool kHalo = false>
 __global__ __launch_bounds__(NT) void scatter_fixed_kernel(
     ScatterCat one, const ScatterCat* __restrict__ cats, const int64_t* __restrict__ starts, int n_cats,

@@ -106,3 +106,49 @@ def test_crowded_cells(mps, prec):
     err = _err(g, want, scale)
     print(f"  max grid error / max |q| grid: {err:.2e}", flush=True)
     assert err < GRID_TOL[prec], err
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_single_tile_grid(mps, prec):
+    """A 16^3 grid is one tile whose halo wraps onto itself: 9000 particles
+    (paired) deposit into a block that the flush folds back periodically."""
+    n = 16
+    pos, vel, w = catalogs.uniform_gaussian(9_000, BOX, 300.0, seed=catalogs.seed_for(5, 904), with_weights=True)
+    print(f"paired scatter: N={n} {prec}, one tile of 9000 particles", flush=True)
+    g = mps.Plan(n, prec).assign(*_dev(pos, vel, w), box=BOX).cpu().numpy().astype(np.float64)
+    err = _err(g, _want(pos, vel, w, n))
+    print(f"  max grid error / max |grid|: {err:.2e}", flush=True)
+    assert err < GRID_TOL[prec], err
+
+
+# One cell of 16,000 particles: the tile's 32-bit fixed-point unit follows
+# that cell's bound and every cell within its reach sums 16,000 deposits
+# rounded to it, so the FP32 grid is coarser there than for any catalog of
+# the other tests: a copy of the library with the paired deposits compiled
+# out measured 1.06e-5 of the |q| grid maximum on this catalog, the paired
+# deposits 5.9e-6 (one rounding per pair instead of two).
+CROWD_TOL = {"f32": 1.5e-5, "f64": 1e-12}
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_one_crowded_cell(mps, prec):
+    """16,000 particles within one cell (one tile just under the paired
+    path's 16,384 particles, all same-cell pairs, ranks up to 16,000) and a
+    thin uniform background; the bound is CROWD_TOL's."""
+    n = 64
+    rng = np.random.default_rng(catalogs.seed_for(5, 905))
+    h = BOX / n
+    cell = np.array([37.0, 5.0, 60.0]) * h
+    clump = cell + rng.uniform(0.05 * h, 0.95 * h, size=(16_000, 3))
+    bg = rng.uniform(0.0, BOX, size=(10_000, 3))
+    pos = np.concatenate([clump, bg]).astype(np.float32)
+    vel = rng.normal(0.0, 300.0, size=pos.shape).astype(np.float32)
+    print(f"paired scatter: N={n} {prec}, 16000 particles in one cell + 10000 uniform", flush=True)
+    g = mps.Plan(n, prec).assign(*_dev(pos, vel, None), box=BOX).cpu().numpy().astype(np.float64)
+    want = _want(pos, vel, None, n)
+    v64 = vel.astype(np.float64)
+    q_abs = np.stack([np.ones(len(pos)), np.abs(v64[:, 0]), np.abs(v64[:, 1]), np.abs(v64[:, 2])])
+    scale = np.abs(oracle.assign(pos, q_abs, BOX, n)).max(axis=(1, 2, 3), keepdims=True)
+    err = _err(g, want, scale)
+    print(f"  max grid error / max |q| grid: {err:.2e}", flush=True)
+    assert err < CROWD_TOL[prec], err
