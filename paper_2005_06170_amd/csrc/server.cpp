@@ -48,13 +48,17 @@ struct Request {
   int status = MPS_OK;
 };
 
+// Scatter buffers a plan holds beyond its grids, tables and records: the
+// halo form's halo buffer, the paired deposits' job scratch.
+constexpr unsigned kExtraHalo = 1, kExtraPairs = 2;
+
 struct PooledPlan {
   mps_plan* plan = nullptr;   // nullptr while a worker creates it
   int n_grid = 0;
   mps_precision prec = MPS_F32;
   int64_t cap = 0;            // particles reserved
   int64_t host_cap = 0;       // particles of host-catalog staging reserved
-  bool halo = false;          // holds the halo scatter's buffer
+  unsigned extras = 0;        // kExtra* buffers it holds
   size_t bytes = 0;
   bool busy = false;
   uint64_t last_use = 0;
@@ -67,7 +71,7 @@ struct Admission {
   PooledPlan* pp = nullptr;
   enum { kReady, kGrow, kCreate } action = kReady;
   int64_t cap = 0, host_cap = 0;          // reservation to make (grow, create)
-  bool halo = false;                      // the plan must hold the halo buffer
+  unsigned extras = 0;                    // kExtra* buffers the plan must hold
   std::vector<std::pair<mps_plan*, size_t>> victims;
 };
 
@@ -121,29 +125,39 @@ bool make_room(Server* s, size_t need, const PooledPlan* keep, Admission* adm) {
 }
 
 // Device bytes of a pooled plan: grids and tables, cap particles' records,
-// host_cap particles' staging, and the halo buffer if it holds one.
-size_t plan_bytes(int n_grid, mps_precision prec, int64_t cap, int64_t host_cap, bool halo) {
+// host_cap particles' staging, and the `extras` buffers it holds (the
+// footprint counts those a catalog of cap particles would take instead).
+size_t plan_bytes(int n_grid, mps_precision prec, int64_t cap, int64_t host_cap, unsigned extras) {
+  const int64_t nt = n_grid / tile_for(n_grid, prec);
+  const size_t pairs = pair_scratch_bytes(nt * nt * nt, kPairBlocks);
   size_t b = mps_footprint(n_grid, prec, cap);
-  if (scatter_form_for(n_grid, prec, cap) == kFormHalo) b -= halo_bytes(n_grid, prec);  // counted by the footprint
-  if (halo) b += halo_bytes(n_grid, prec);
+  if (scatter_form_for(n_grid, prec, cap) == kFormHalo) b -= halo_bytes(n_grid, prec);
+  if (pairs_reachable(n_grid, prec, cap)) b -= pairs;
+  if (extras & kExtraHalo) b += halo_bytes(n_grid, prec);
+  if (extras & kExtraPairs) b += pairs;
   return b + kHostStageBytes * static_cast<size_t>(host_cap);
 }
 
-// The request's scatter takes the halo form (its plan needs the buffer).
-bool needs_halo(const mps_catalog& c, int n_grid, mps_precision prec) {
-  return kernel_id(c.flags) == 0 && scatter_form_for(n_grid, prec, c.n_particles) == kFormHalo;
+// The scatter buffers the request's plan needs: the halo form's, or the
+// paired deposits' (truncated BL3 kernel).
+unsigned needs_extras(const mps_catalog& c, int n_grid, mps_precision prec) {
+  if (kernel_id(c.flags) != 0) return 0u;
+  unsigned e = 0u;
+  if (scatter_form_for(n_grid, prec, c.n_particles) == kFormHalo) e |= kExtraHalo;
+  if (pairs_reachable(n_grid, prec, c.n_particles)) e |= kExtraPairs;
+  return e;
 }
 
 // Under the lock: choose an idle pooled plan of this shape with room for np
 // particles (and, for a host-resident catalog, np particles of staging; and
-// the halo buffer if `halo`), else one to grow, else a new one, and reserve
+// the `extras` buffers), else one to grow, else a new one, and reserve
 // its bytes.  Returns false if the budget cannot host it right now (*status
 // stays MPS_OK) or never can (*status = MPS_E_TOOBIG).
-bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host, bool halo, Admission* adm,
-                int* status) {
+bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host, unsigned extras,
+                Admission* adm, int* status) {
   *status = MPS_OK;
   const int64_t hp = host ? np : 0;
-  if (plan_bytes(n_grid, prec, np, hp, halo) > s->budget) {
+  if (plan_bytes(n_grid, prec, np, hp, extras) > s->budget) {
     *status = MPS_E_TOOBIG;
     return false;
   }
@@ -151,7 +165,7 @@ bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host
   PooledPlan* grow = nullptr;
   for (auto& pp : s->pool) {
     if (pp.busy || pp.n_grid != n_grid || pp.prec != prec) continue;
-    if (pp.cap >= np && pp.host_cap >= hp && (pp.halo || !halo)) {
+    if (pp.cap >= np && pp.host_cap >= hp && (pp.extras & extras) == extras) {
       if (!fit || pp.cap < fit->cap) fit = &pp;
     } else if (!grow || pp.cap > grow->cap) {
       grow = &pp;
@@ -166,21 +180,21 @@ bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host
   }
   if (grow) {
     const int64_t cap = std::max(grow->cap, np), hcap = std::max(grow->host_cap, hp);
-    const bool h = grow->halo || halo;
+    const unsigned h = grow->extras | extras;
     const size_t need = plan_bytes(n_grid, prec, cap, hcap, h);
     if (!make_room(s, need - grow->bytes, grow, adm)) return false;
     adm->pp = grow;
     adm->action = Admission::kGrow;
     adm->cap = cap;
     adm->host_cap = hcap;
-    adm->halo = h;
+    adm->extras = h;
     s->used += need - grow->bytes;
     grow->bytes = need;
     grow->busy = true;
     grow->last_use = ++s->clock;
     return true;
   }
-  const size_t need = plan_bytes(n_grid, prec, np, hp, halo);
+  const size_t need = plan_bytes(n_grid, prec, np, hp, extras);
   if (!make_room(s, need, nullptr, adm)) return false;
   PooledPlan pp;
   pp.n_grid = n_grid;
@@ -194,7 +208,7 @@ bool admit_plan(Server* s, int n_grid, mps_precision prec, int64_t np, bool host
   adm->action = Admission::kCreate;
   adm->cap = np;
   adm->host_cap = hp;
-  adm->halo = halo;
+  adm->extras = extras;
   return true;
 }
 
@@ -212,15 +226,13 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
   mps_plan* created = nullptr;
   if (adm->action == Admission::kCreate) {
     st = mps_plan_create(&created, pp->n_grid, pp->prec);
-    // the records only: the halo buffer is reserved when a request needs it
-    // (mps_plan_reserve would also allocate it for any plan that could)
+    // the records, and the scatter buffers the admitted request needs
+    // (mps_plan_reserve would allocate them for any plan that could use
+    // them), here rather than in the worker's first estimate
     if (st == MPS_OK && adm->cap > 0) st = ensure_particles(reinterpret_cast<Plan*>(created), adm->cap);
     if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(created), adm->host_cap);
-    if (st == MPS_OK && adm->halo) st = ensure_halo(reinterpret_cast<Plan*>(created));
-    // the paired deposits' job scratch (counted by the footprint), here
-    // rather than in the worker's first estimate
-    if (st == MPS_OK && pairs_reachable(pp->n_grid, pp->prec, adm->cap))
-      st = ensure_pair_scratch(reinterpret_cast<Plan*>(created));
+    if (st == MPS_OK && (adm->extras & kExtraHalo)) st = ensure_halo(reinterpret_cast<Plan*>(created));
+    if (st == MPS_OK && (adm->extras & kExtraPairs)) st = ensure_pair_scratch(reinterpret_cast<Plan*>(created));
     if (st != MPS_OK && created) {
       mps_plan_destroy(created);
       created = nullptr;
@@ -228,9 +240,8 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
   } else if (adm->action == Admission::kGrow) {
     if (adm->cap > 0) st = ensure_particles(reinterpret_cast<Plan*>(pp->plan), adm->cap);
     if (st == MPS_OK && adm->host_cap > 0) st = ensure_host_stage(reinterpret_cast<Plan*>(pp->plan), adm->host_cap);
-    if (st == MPS_OK && adm->halo) st = ensure_halo(reinterpret_cast<Plan*>(pp->plan));
-    if (st == MPS_OK && pairs_reachable(pp->n_grid, pp->prec, adm->cap))
-      st = ensure_pair_scratch(reinterpret_cast<Plan*>(pp->plan));
+    if (st == MPS_OK && (adm->extras & kExtraHalo)) st = ensure_halo(reinterpret_cast<Plan*>(pp->plan));
+    if (st == MPS_OK && (adm->extras & kExtraPairs)) st = ensure_pair_scratch(reinterpret_cast<Plan*>(pp->plan));
   }
   lk.lock();
   s->used -= freed;
@@ -239,7 +250,7 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
       pp->plan = created;
       pp->cap = adm->cap;
       pp->host_cap = adm->host_cap;
-      pp->halo = adm->halo;
+      pp->extras = adm->extras;
     } else {
       s->used -= pp->bytes;
       for (auto it = s->pool.begin(); it != s->pool.end(); ++it)
@@ -253,7 +264,7 @@ int carry_out(Server* s, Admission* adm, std::unique_lock<std::mutex>& lk) {
     if (st == MPS_OK) {
       pp->cap = adm->cap;
       pp->host_cap = adm->host_cap;
-      pp->halo = adm->halo;
+      pp->extras = adm->extras;
     } else {  // a failed reservation may have dropped part of the old one
       mps_plan* dead = pp->plan;
       s->used -= pp->bytes;
@@ -342,19 +353,18 @@ void worker_main(Server* s) {
         s->used -= wp.reserved;
         return;
       }
-      size_t pos = 0;
-      for (auto it = s->queue.begin(); it != s->queue.end(); ++pos) {
+      for (auto it = s->queue.begin(); it != s->queue.end();) {
         const auto r = *it;
         int st = MPS_OK;
         Admission adm;
         const bool large = r->cat.n_particles > s->small;
         const bool host = (r->cat.flags & MPS_CATALOG_HOST) != 0;
-        const bool halo = needs_halo(r->cat, r->n_grid, r->prec);
+        const unsigned extras = needs_extras(r->cat, r->n_grid, r->prec);
         if (large) {
           // the plan holds its grids only; the records live in this worker's
           // workspace, reserved (and grown if needed) first
           const int64_t np = r->cat.n_particles;
-          if (plan_bytes(r->n_grid, r->prec, 0, 0, halo) + ParticleSpace::size_of(np, host ? np : 0) > s->budget) {
+          if (plan_bytes(r->n_grid, r->prec, 0, 0, extras) + ParticleSpace::size_of(np, host ? np : 0) > s->budget) {
             it = s->queue.erase(it);
             finish(s, r, MPS_E_TOOBIG);
             s->cv_done.notify_all();
@@ -364,7 +374,7 @@ void worker_main(Server* s) {
           const int64_t hcap = host ? grown(np, wp.want_host > wp.host_cap ? wp.want_host : wp.host_cap)
                                     : (wp.want_host > wp.host_cap ? wp.want_host : wp.host_cap);
           size_t need = ParticleSpace::size_of(cap, hcap);
-          if (need + plan_bytes(r->n_grid, r->prec, 0, 0, halo) > s->budget)
+          if (need + plan_bytes(r->n_grid, r->prec, 0, 0, extras) > s->budget)
             need = ParticleSpace::size_of(np, host ? np : 0);  // no headroom: exactly what it needs
           if (need > wp.reserved) {
             Admission wadm;
@@ -381,7 +391,7 @@ void worker_main(Server* s) {
           }
         }
         Admission padm;
-        if (!admit_plan(s, r->n_grid, r->prec, large ? 0 : r->cat.n_particles, !large && host, halo, &padm, &st)) {
+        if (!admit_plan(s, r->n_grid, r->prec, large ? 0 : r->cat.n_particles, !large && host, extras, &padm, &st)) {
           // plans a workspace reservation evicted are freed before this
           // worker waits (their bytes stay counted until then)
           for (auto& v : adm.victims) dead.push_back(v);
@@ -413,7 +423,7 @@ void worker_main(Server* s) {
             int st2 = MPS_OK;
             Admission a2;
             if (!admit_plan(s, q->n_grid, q->prec, q->cat.n_particles, (q->cat.flags & MPS_CATALOG_HOST) != 0,
-                            needs_halo(q->cat, q->n_grid, q->prec), &a2, &st2))
+                            needs_extras(q->cat, q->n_grid, q->prec), &a2, &st2))
               break;
             batch.push_back(q);
             adms.push_back(std::move(a2));
