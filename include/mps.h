@@ -197,7 +197,8 @@ typedef struct {
 #define MPS_SCATTER_HALO_MAX_MEAN 2048
 /* MPS_F64 with the truncated BL3 kernel on grids of N >= MPS_SCATTER_MIN_GRID:
  * m <= MPS_SCATTER_GATHER64_MAX_MEAN, the owner-computes scatter (64-bit
- * fixed point, as the atomic FP64 scatter); else the atomic scatter. */
+ * fixed point, as the atomic FP64 scatter); else the atomic scatter, with
+ * the paired deposits and job scratch of the FP32 atomic scatter. */
 #define MPS_SCATTER_GATHER64_MAX_MEAN 384
 
 typedef struct mps_plan mps_plan;
