@@ -355,7 +355,9 @@ int mps_fft(mps_plan* plan, void* grids, hipStream_t stream);
 /* Per-stage device time of the last mps_estimate on this plan when stage
  * timing is on (mps_plan_set_timing).  ms[0..n) receives, in order:
  * moments+count, scan, permute, clear, scatter, fft_z, fft_y, fft_x+bin,
- * finalize. */
+ * finalize.  With timing off the first stages run as fewer launches (the
+ * clears together before the count, the moments' derivation and the scan
+ * in one), which only their boundaries tell apart; results are the same. */
 int mps_plan_set_timing(mps_plan* plan, int enable);
 int mps_plan_stage_times(const mps_plan* plan, double* ms, int n);
 

@@ -192,6 +192,14 @@ int enqueue_prescatter(Plan* p, const mps_catalog* c0, hipStream_t s, mps_catalo
     if (c0->weight)
       MPS_TRY(hipMemcpyAsync(p->host_stage + 6 * n, c0->weight, sizeof(float) * n, hipMemcpyHostToDevice, s));
   }
+  // only the atomic scatter adds into the grid; the other forms store every cell
+  const bool clear_grid = scatter_form(p, used) == kFormAtomic;
+  if (!p->timing) {  // a short chain of dependent launches: what small catalogs wait on
+    bool cleared = false;
+    MPS_TRY(launch_sort_fused(p, used, s, clear_grid, &cleared));
+    if (clear_grid && !cleared) MPS_TRY(launch_clear_grid(p, s));
+    return MPS_OK;
+  }
   mark(p, 0, s);
   MPS_TRY(launch_count(p, used, s));
   MPS_TRY(launch_derive(p, used, s));
@@ -200,8 +208,7 @@ int enqueue_prescatter(Plan* p, const mps_catalog* c0, hipStream_t s, mps_catalo
   mark(p, 2, s);
   MPS_TRY(launch_permute(p, used, s));
   mark(p, 3, s);
-  // only the atomic scatter adds into the grid; the other forms store every cell
-  if (scatter_form(p, used) == kFormAtomic) MPS_TRY(launch_clear_grid(p, s));
+  if (clear_grid) MPS_TRY(launch_clear_grid(p, s));
   mark(p, 4, s);
   return MPS_OK;
 }

@@ -304,6 +304,12 @@ hipError_t launch_derive(Plan* p, const mps_catalog* c, hipStream_t s);
 hipError_t launch_scan(Plan* p, const mps_catalog* c, hipStream_t s);
 hipError_t launch_permute(Plan* p, const mps_catalog* c, hipStream_t s);
 hipError_t launch_clear_grid(Plan* p, hipStream_t s);
+// The count, derive, scan and permute with fewer dependent launches (no
+// stage marks between them): one clear of the tile counters, the header and,
+// when clear_grid and the sort keeps no records in the grid, the grid
+// (*grid_cleared then true); the count; the derivation and the scan in one
+// launch for the one-level sort; the permute.
+hipError_t launch_sort_fused(Plan* p, const mps_catalog* c, hipStream_t s, bool clear_grid, bool* grid_cleared);
 hipError_t launch_scatter(Plan* p, const mps_catalog* c, hipStream_t s);
 // The catalog's scatter form (ScatterForm; FP64 grids take kFormGather or
 // kFormAtomic, the kernels other than the truncated BL3 kFormAtomic).

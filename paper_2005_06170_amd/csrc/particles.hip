@@ -294,8 +294,8 @@ __global__ __launch_bounds__(kCountThreads) void count_kernel(
 // and bulk-flow scalars.  One workgroup of kMomentBlocks threads: thread b
 // holds block b's partials (zero beyond the nb blocks the count ran) and a
 // fixed reduction tree combines them.
-__global__ __launch_bounds__(kMomentBlocks) void derive_kernel(const double* __restrict__ partials, int nb,
-                                                               ResultHeader* hdr, int bulk) {
+__device__ __forceinline__ void derive_block(const double* __restrict__ partials, int nb, ResultHeader* hdr,
+                                             int bulk) {
   constexpr int kW = kMomentBlocks / 64;
   __shared__ double red[kW][kMomentSums + kMomentMax];
   __shared__ double sums[kMomentSums];
@@ -357,12 +357,15 @@ __global__ __launch_bounds__(kMomentBlocks) void derive_kernel(const double* __r
   hdr->d = d;
 }
 
+__global__ __launch_bounds__(kMomentBlocks) void derive_kernel(const double* __restrict__ partials, int nb,
+                                                               ResultHeader* hdr, int bulk) {
+  derive_block(partials, nb, hdr, bulk);
+}
+
 // Exclusive scan of the tile counts (one workgroup); also resets the cursor.
-__global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__ count, int64_t n_tiles,
-                                                    uint32_t* __restrict__ offset, uint32_t* __restrict__ cursor,
-                                                    const ResultHeader* __restrict__ hdr, int order_mode) {
+__device__ __forceinline__ void scan_block(const uint32_t* __restrict__ count, int64_t n_tiles,
+                                           uint32_t* __restrict__ offset, uint32_t* __restrict__ cursor) {
   __shared__ uint32_t part[1024];
-  if (order_mode >= 0 && random_order(hdr) != (order_mode == 1)) return;  // uniform
   const int64_t per = (n_tiles + 1023) / 1024;
   const int64_t lo = threadIdx.x * per;
   const int64_t hi = lo + per < n_tiles ? lo + per : n_tiles;
@@ -383,6 +386,38 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__
     run += count[i];
   }
   if (threadIdx.x == 1023) offset[n_tiles] = part[1023];
+}
+
+__global__ __launch_bounds__(1024) void scan_kernel(const uint32_t* __restrict__ count, int64_t n_tiles,
+                                                    uint32_t* __restrict__ offset, uint32_t* __restrict__ cursor,
+                                                    const ResultHeader* __restrict__ hdr, int order_mode) {
+  if (order_mode >= 0 && random_order(hdr) != (order_mode == 1)) return;  // uniform
+  scan_block(count, n_tiles, offset, cursor);
+}
+
+// The two one-workgroup stages after the count in one launch (the one-level
+// sort): the moments' derivation, then the scan of the tile counts.  They
+// read and write disjoint data.
+static_assert(kMomentBlocks == 1024, "derive and scan share the workgroup");
+__global__ __launch_bounds__(1024) void derive_scan_kernel(const double* __restrict__ partials, int nb,
+                                                           ResultHeader* hdr, int bulk,
+                                                           const uint32_t* __restrict__ count, int64_t n_tiles,
+                                                           uint32_t* __restrict__ offset,
+                                                           uint32_t* __restrict__ cursor) {
+  derive_block(partials, nb, hdr, bulk);
+  scan_block(count, n_tiles, offset, cursor);
+}
+
+// Zeroes three word ranges in one launch (the tile counters, the result
+// header and, where the sort leaves it alone, the grid).
+__global__ __launch_bounds__(256) void clear3_kernel(uint32_t* __restrict__ a, int64_t na, uint32_t* __restrict__ b,
+                                                     int64_t nb, uint32_t* __restrict__ c, int64_t nc) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < na + nb + nc; i += stride) {
+    if (i < na) a[i] = 0u;
+    else if (i < na + nb) b[i - na] = 0u;
+    else c[i - na - nb] = 0u;
+  }
 }
 
 // Sorted particle records.  A catalog with weights stores (x, y, z, w) and
@@ -2170,14 +2205,11 @@ bool sort_two_level(const Plan* p, const mps_catalog* c, int* shift) {
 
 }  // namespace
 
-hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
+namespace {
+
+// The count's kernels, the tile counters and the header already zero.
+hipError_t launch_count_kernels(Plan* p, const mps_catalog* c, hipStream_t s) {
   const KeyParams kp = key_params(p, c);
-  // zero-fill kernels rather than memset nodes, so that the sequence can be
-  // captured in a HIP graph
-  clear_kernel<uint32_t><<<static_cast<unsigned>((p->n_tiles + 255) / 256 < 4096 ? (p->n_tiles + 255) / 256 : 4096),
-                           256, 0, s>>>(p->tile_count, p->n_tiles);
-  clear_kernel<uint32_t><<<1, 256, 0, s>>>(reinterpret_cast<uint32_t*>(p->d_header),
-                                           static_cast<int64_t>(sizeof(ResultHeader) / sizeof(uint32_t)));
   // the grid depends only on the particle count, so the moment sums of a
   // catalog are added in one order whatever else runs
   const int nb = count_blocks(c->n_particles);
@@ -2217,6 +2249,46 @@ hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
   if (c->weight) both(std::true_type{});
   else both(std::false_type{});
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_count(Plan* p, const mps_catalog* c, hipStream_t s) {
+  // zero-fill kernels rather than memset nodes, so that the sequence can be
+  // captured in a HIP graph
+  clear_kernel<uint32_t><<<static_cast<unsigned>((p->n_tiles + 255) / 256 < 4096 ? (p->n_tiles + 255) / 256 : 4096),
+                           256, 0, s>>>(p->tile_count, p->n_tiles);
+  clear_kernel<uint32_t><<<1, 256, 0, s>>>(reinterpret_cast<uint32_t*>(p->d_header),
+                                           static_cast<int64_t>(sizeof(ResultHeader) / sizeof(uint32_t)));
+  return launch_count_kernels(p, c, s);
+}
+
+hipError_t launch_sort_fused(Plan* p, const mps_catalog* c, hipStream_t s, bool clear_grid, bool* grid_cleared) {
+  int shift = 0;
+  const bool two = sort_two_level(p, c, &shift);
+  // the two-level sort keeps temporary records in the grid
+  *grid_cleared = clear_grid && !two;
+  const int64_t hdr_words = static_cast<int64_t>(sizeof(ResultHeader) / sizeof(uint32_t));
+  const int64_t grid_words =
+      *grid_cleared ? static_cast<int64_t>(kNumFields) * p->n * p->n * p->n * static_cast<int64_t>(p->real_size) / 4
+                    : 0;
+  int64_t blocks = (p->n_tiles + hdr_words + grid_words + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  clear3_kernel<<<static_cast<unsigned>(blocks), 256, 0, s>>>(
+      p->tile_count, p->n_tiles, reinterpret_cast<uint32_t*>(p->d_header), hdr_words,
+      static_cast<uint32_t*>(p->grid), grid_words);
+  hipError_t e = launch_count_kernels(p, c, s);
+  if (e != hipSuccess) return e;
+  if (two) {
+    if ((e = launch_derive(p, c, s)) != hipSuccess) return e;
+    if ((e = launch_scan(p, c, s)) != hipSuccess) return e;
+  } else {
+    derive_scan_kernel<<<1, 1024, 0, s>>>(p->moment_partials, count_blocks(c->n_particles), p->d_header,
+                                          (c->flags & MPS_BULKFLOW_SUBTRACT) ? 1 : 0, p->tile_count, p->n_tiles,
+                                          p->tile_offset, p->tile_cursor);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return launch_permute(p, c, s);
 }
 
 hipError_t launch_derive(Plan* p, const mps_catalog* c, hipStream_t s) {
