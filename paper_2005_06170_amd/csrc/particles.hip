@@ -408,16 +408,16 @@ __global__ __launch_bounds__(1024) void derive_scan_kernel(const double* __restr
   scan_block(count, n_tiles, offset, cursor);
 }
 
-// Zeroes three word ranges in one launch (the tile counters, the result
-// header and, where the sort leaves it alone, the grid).
+// Zeroes, in one launch, the grid (nc reals, stored as clear_kernel does)
+// and two word ranges (the tile counters and the result header).
+template <typename T>
 __global__ __launch_bounds__(256) void clear3_kernel(uint32_t* __restrict__ a, int64_t na, uint32_t* __restrict__ b,
-                                                     int64_t nb, uint32_t* __restrict__ c, int64_t nc) {
+                                                     int64_t nb, T* __restrict__ c, int64_t nc) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < na + nb + nc; i += stride) {
-    if (i < na) a[i] = 0u;
-    else if (i < na + nb) b[i - na] = 0u;
-    else c[i - na - nb] = 0u;
-  }
+  const int64_t t0 = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  for (int64_t i = t0; i < nc; i += stride) c[i] = T(0);
+  for (int64_t i = t0; i < na; i += stride) a[i] = 0u;
+  for (int64_t i = t0; i < nb; i += stride) b[i] = 0u;
 }
 
 // Sorted particle records.  A catalog with weights stores (x, y, z, w) and
@@ -2269,14 +2269,16 @@ hipError_t launch_sort_fused(Plan* p, const mps_catalog* c, hipStream_t s, bool 
   // the two-level sort keeps temporary records in the grid
   *grid_cleared = clear_grid && !two;
   const int64_t hdr_words = static_cast<int64_t>(sizeof(ResultHeader) / sizeof(uint32_t));
-  const int64_t grid_words =
-      *grid_cleared ? static_cast<int64_t>(kNumFields) * p->n * p->n * p->n * static_cast<int64_t>(p->real_size) / 4
-                    : 0;
-  int64_t blocks = (p->n_tiles + hdr_words + grid_words + 255) / 256;
+  const int64_t grid_n = *grid_cleared ? static_cast<int64_t>(kNumFields) * p->n * p->n * p->n : 0;
+  int64_t blocks = ((grid_n > p->n_tiles ? grid_n : p->n_tiles) + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  clear3_kernel<<<static_cast<unsigned>(blocks), 256, 0, s>>>(
-      p->tile_count, p->n_tiles, reinterpret_cast<uint32_t*>(p->d_header), hdr_words,
-      static_cast<uint32_t*>(p->grid), grid_words);
+  uint32_t* hdr = reinterpret_cast<uint32_t*>(p->d_header);
+  if (p->prec == MPS_F32)
+    clear3_kernel<float><<<static_cast<unsigned>(blocks), 256, 0, s>>>(p->tile_count, p->n_tiles, hdr, hdr_words,
+                                                                       static_cast<float*>(p->grid), grid_n);
+  else
+    clear3_kernel<double><<<static_cast<unsigned>(blocks), 256, 0, s>>>(p->tile_count, p->n_tiles, hdr, hdr_words,
+                                                                        static_cast<double*>(p->grid), grid_n);
   hipError_t e = launch_count_kernels(p, c, s);
   if (e != hipSuccess) return e;
   if (two) {
