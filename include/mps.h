@@ -357,7 +357,8 @@ int mps_fft(mps_plan* plan, void* grids, hipStream_t stream);
  * moments+count, scan, permute, clear, scatter, fft_z, fft_y, fft_x+bin,
  * finalize.  With timing off the first stages run as fewer launches (the
  * clears together before the count, the moments' derivation and the scan
- * in one), which only their boundaries tell apart; results are the same. */
+ * in one), which only their boundaries tell apart; results agree as those
+ * of two untimed runs do. */
 int mps_plan_set_timing(mps_plan* plan, int enable);
 int mps_plan_stage_times(const mps_plan* plan, double* ms, int n);
 
